@@ -1,0 +1,159 @@
+/*
+ * curveball.h - C ABI of the MI355X (gfx950) global Curveball super-step.
+ *
+ * One call of global_trade() applies one undirected global trade (Def.
+ * "Undirected Global Trade", Sec. 3.3 of Carstens et al., "Parallel and
+ * I/O-efficient Randomisation of Massive Networks using Global Curveball
+ * Trades") to a device-resident simple graph: floor(n/2) Curveball trades
+ * (Def. "Simple Undirected Trade", Sec. 3.2), paired and ordered by a
+ * hash-keyed sort of the node ids (Def. "Relaxed global trade", appendix on
+ * EM-GCB), each trade keeping the shared neighbours and the u-v edge of its
+ * pair and re-splitting the disjoint neighbours uniformly (Sec. 4, trade
+ * procedure). The result is the sequential definition's, byte for byte.
+ *
+ * Random-number convention (the paper leaves the generator open):
+ *   philox64(seed; c0..c3) = (w1 << 32) | w0 of Philox4x32-10 (Salmon et al.,
+ *     SC'11) keyed by (seed_lo32, seed_hi32), counter (c0, c1, c2, c3);
+ *   node v's sort key in round r:  philox64(seed; v, r, 0, 0x4D415443);
+ *     trade i pairs the nodes at sorted positions 2i (u) and 2i+1 (v),
+ *     ties broken by ascending id; with odd n the last node sits out;
+ *   draw j of trade i in round r:   philox64(seed; i, r, j, 0x46595348);
+ *   bounded(x, k) = floor(x * k / 2^64);
+ *   split of the ascending disjoint set D (|D| = N, a = |A_u \ (A_v u {v})|):
+ *     if a <= N - a: for j = 0..a-1:   swap D[j], D[j + bounded(draw j, N - j)]
+ *     else:          for j = N-1..a:   swap D[j], D[bounded(draw j, j + 1)]
+ *     u receives D[0..a), v receives D[a..N).
+ *
+ * Graph form: simple undirected graph as symmetric CSR; row_ptr int64[n+1]
+ * with row_ptr[0] = 0, col int32[row_ptr[n]] (= 2m), each row strictly
+ * ascending, no self id, 0 <= n <= 2^31 - 1, 2m < 2^31. Degrees never change,
+ * so row_ptr is the same after every round; rows stay ascending.
+ *
+ * Errors: every call returns cb_status; no exception crosses the ABI.
+ * cb_last_error() gives a thread-local message for the last failure.
+ * Argument and validation errors return at once and change nothing. A fault
+ * found on the device (a watchdog time-out of the trade kernel, an
+ * impossible counter) is reported by the next synchronising call
+ * (graph_sync, graph_download, graph_stats); the handle is then poisoned and
+ * only graph_free is valid.
+ */
+#ifndef CURVEBALL_H
+#define CURVEBALL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cb_graph cb_graph;
+
+typedef enum {
+    CB_OK = 0,
+    CB_EINVAL = 1,      /* bad argument */
+    CB_ENOTSIMPLE = 2,  /* upload validation: not a simple symmetric sorted CSR */
+    CB_ENOMEM = 3,      /* device allocation failed; nothing was kept */
+    CB_EDEVICE = 4,     /* HIP error or device-side invariant violation */
+    CB_EWATCHDOG = 5,   /* trade kernel made no progress within the limit */
+    CB_EPOISONED = 6    /* handle unusable after an earlier device error */
+} cb_status;
+
+/* Device memory provider. alloc returns device memory of `bytes` (or NULL);
+ * free releases it. Both run on the host, never inside a kernel. */
+typedef struct {
+    void* (*alloc)(size_t bytes, void* user);
+    void (*free)(void* ptr, void* user);
+    void* user;
+} cb_allocator;
+
+/* Set the provider used by later graph_upload calls (NULL: hipMalloc). */
+cb_status cb_set_allocator(const cb_allocator* allocator);
+
+/* Upload flags. */
+#define CB_VALIDATE 1u  /* check simple / sorted / symmetric on the device */
+
+/* Copy a host CSR (row_ptr: n+1 int64, col: row_ptr[n] int32; the caller
+ * keeps ownership) to the current HIP device and create a handle that owns
+ * all device state of one chain. stream: a hipStream_t on which every later
+ * call of this handle is ordered (NULL: the handle creates its own).
+ * Synchronises the stream before returning. */
+cb_status graph_upload(int64_t n, const int64_t* row_ptr, const int32_t* col,
+                       void* stream, uint32_t flags, cb_graph** out);
+
+/* Sizes for download buffers: n and nnz = 2m. */
+cb_status graph_info(const cb_graph* g, int64_t* n, int64_t* nnz);
+
+/* Apply one global trade with the given chain seed and round number.
+ * Asynchronous: enqueued on the handle's stream, returns before it runs. */
+cb_status global_trade(cb_graph* g, uint64_t seed, uint32_t round);
+
+/* Wait for all enqueued work; report device-side faults. */
+cb_status graph_sync(cb_graph* g);
+
+/* Synchronise and copy the current graph into caller buffers of n+1 and
+ * nnz entries (row_ptr may be NULL: it equals the uploaded one). */
+cb_status graph_download(cb_graph* g, int64_t* row_ptr, int32_t* col);
+
+/* Release all device memory of the handle (NULL is a no-op). */
+void graph_free(cb_graph* g);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* cb_last_error(void);
+
+/* ---- step-wise execution and state readout (parity tests) ------------- */
+
+/* Steps of one global trade, in order. */
+#define CB_STEP_MATCHING 1  /* keys, bucket sort, perm, trade_of */
+#define CB_STEP_DEPSCAN  2  /* per-trade count of edges to earlier trades */
+#define CB_STEP_TRADE    3  /* persistent trade kernel (col_out filled) */
+#define CB_STEP_REBUILD  4  /* per-row sort of col_out into col */
+
+/* Run the steps 1..last_step of global_trade(seed, round). A call with
+ * last_step < CB_STEP_REBUILD leaves the graph state unusable for further
+ * trades until graph_upload; it exists to read intermediate state. */
+cb_status global_trade_steps(cb_graph* g, uint64_t seed, uint32_t round, int32_t last_step);
+
+/* Device state readable after a (partial) round. */
+#define CB_STATE_PERM     1  /* int32[n]: nodes in sorted key order */
+#define CB_STATE_TRADE_OF 2  /* int32[n]: trade of each node, INT32_MAX if none */
+#define CB_STATE_DEP      3  /* int32[n/2]: dependency counts after DEPSCAN */
+#define CB_STATE_COL      4  /* int32[nnz]: current adjacency (rows ascending) */
+
+/* Synchronise and copy `count` elements of state `which` to host memory. */
+cb_status graph_download_state(cb_graph* g, int32_t which, void* host, int64_t count);
+
+/* ---- options ------------------------------------------------------------ */
+#define CB_OPT_SMALL_MAX     1  /* trades with deg u + deg v <= this run on one
+                                   wavefront (0..256); larger ones on a whole
+                                   workgroup. Default 256. */
+#define CB_OPT_BIG_WORKERS   2  /* workgroups reserved for large trades (>= 1) */
+#define CB_OPT_GRID_BLOCKS   3  /* workgroups of the trade kernel (0 = auto) */
+#define CB_OPT_WATCHDOG_MS   4  /* idle time after which the trade kernel gives up */
+#define CB_OPT_TIMING        5  /* 1: time every kernel with HIP events */
+#define CB_OPT_LOCAL_STACK   6  /* ready trades a wavefront keeps for itself (0..16) */
+
+cb_status graph_set_option(cb_graph* g, int32_t option, int64_t value);
+
+/* Counters of the last completed round (synchronises). */
+typedef struct {
+    int64_t trades;          /* floor(n/2) */
+    int64_t small_trades;    /* run by one wavefront */
+    int64_t big_trades;      /* run by a workgroup */
+    int64_t sources;         /* trades with no earlier neighbour */
+    int64_t queue_pushes;    /* ready trades handed over through global queues */
+    int64_t work;            /* sum of deg u + deg v over trades */
+    int64_t forwarded;       /* edges handed to a later trade */
+    int64_t emitted;         /* final edges written (both directions counted once) */
+} cb_round_stats;
+
+cb_status graph_stats(cb_graph* g, cb_round_stats* out);
+
+/* Kernel timing (CB_OPT_TIMING): mean milliseconds per round of each step,
+ * ms[0..4) = matching, depscan, trade, rebuild; rounds timed in *rounds. */
+cb_status graph_kernel_times(cb_graph* g, double* ms, int32_t count, int64_t* rounds);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,199 @@
+"""Global Curveball super-step on MI355X (gfx950): Python binding.
+
+Argument marshalling only: every step of a global trade runs in the HIP
+kernels of ``libcurveball.so`` behind the C ABI declared in
+``include/curveball.h``.  PyTorch supplies the stream (and, optionally, the
+device memory through its caching allocator); it does no computation here.
+If the shared library is missing the import of :func:`lib` fails loudly -
+there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcurveball.so")
+
+CB_OK, CB_EINVAL, CB_ENOTSIMPLE, CB_ENOMEM, CB_EDEVICE, CB_EWATCHDOG, CB_EPOISONED = range(7)
+STATUS_NAMES = {0: "CB_OK", 1: "CB_EINVAL", 2: "CB_ENOTSIMPLE", 3: "CB_ENOMEM",
+                4: "CB_EDEVICE", 5: "CB_EWATCHDOG", 6: "CB_EPOISONED"}
+CB_VALIDATE = 1
+STEP_MATCHING, STEP_DEPSCAN, STEP_TRADE, STEP_REBUILD = 1, 2, 3, 4
+STATE_PERM, STATE_TRADE_OF, STATE_DEP, STATE_COL = 1, 2, 3, 4
+OPT_SMALL_MAX, OPT_BIG_WORKERS, OPT_GRID_BLOCKS, OPT_WATCHDOG_MS, OPT_TIMING, OPT_LOCAL_STACK = range(1, 7)
+UNMATCHED = 2**31 - 1
+
+# Every symbol declared in include/curveball.h.
+EXPORTS = ("cb_set_allocator", "graph_upload", "graph_info", "global_trade", "graph_sync",
+           "graph_download", "graph_free", "cb_last_error", "global_trade_steps",
+           "graph_download_state", "graph_set_option", "graph_stats", "graph_kernel_times")
+
+
+class CurveballError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class _Allocator(ctypes.Structure):
+    _fields_ = [("alloc", ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)),
+                ("free", ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)),
+                ("user", ctypes.c_void_p)]
+
+
+class RoundStats(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in (
+        "trades", "small_trades", "big_trades", "sources", "queue_pushes", "work",
+        "forwarded", "emitted")]
+
+    def as_dict(self):
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """The loaded HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1804_08487_amd.build` (or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32, u32, u64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64
+        L.cb_set_allocator.argtypes = [ctypes.POINTER(_Allocator)]
+        L.graph_upload.argtypes = [i64, vp, vp, vp, u32, ctypes.POINTER(vp)]
+        L.graph_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        L.global_trade.argtypes = [vp, u64, u32]
+        L.graph_sync.argtypes = [vp]
+        L.graph_download.argtypes = [vp, vp, vp]
+        L.graph_free.argtypes = [vp]
+        L.graph_free.restype = None
+        L.cb_last_error.argtypes = []
+        L.cb_last_error.restype = ctypes.c_char_p
+        L.global_trade_steps.argtypes = [vp, u64, u32, i32]
+        L.graph_download_state.argtypes = [vp, i32, vp, i64]
+        L.graph_set_option.argtypes = [vp, i32, i64]
+        L.graph_stats.argtypes = [vp, ctypes.POINTER(RoundStats)]
+        L.graph_kernel_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(i64)]
+        for name in EXPORTS:
+            if name not in ("graph_free", "cb_last_error"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != CB_OK:
+        raise CurveballError(status, lib().cb_last_error().decode(errors="replace"))
+
+
+_torch_alloc_refs = None
+
+
+def use_torch_allocator(enable: bool = True):
+    """Route the library's device allocations through PyTorch's caching
+    allocator (current device, current stream)."""
+    global _torch_alloc_refs
+    if not enable:
+        _check(lib().cb_set_allocator(None))
+        _torch_alloc_refs = None
+        return
+    import torch
+
+    @ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+    def _alloc(nbytes, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes))
+        except Exception:
+            return None
+
+    @ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+    def _free(ptr, user):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    a = _Allocator(_alloc, _free, None)
+    _torch_alloc_refs = (a, _alloc, _free)
+    _check(lib().cb_set_allocator(ctypes.byref(a)))
+
+
+def current_stream_handle():
+    """hipStream_t of PyTorch's current stream on the current device."""
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Graph:
+    """One device-resident chain: a simple undirected graph in CSR form."""
+
+    def __init__(self, row_ptr, col, stream=None, validate: bool = True):
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        cl = np.ascontiguousarray(col, dtype=np.int32)
+        self.row_ptr = rp.copy()
+        n = len(rp) - 1
+        h = ctypes.c_void_p()
+        if stream is None:
+            stream = current_stream_handle()
+        self._stream = stream
+        _check(lib().graph_upload(n, rp.ctypes.data, cl.ctypes.data if len(cl) else None, stream,
+                                  CB_VALIDATE if validate else 0, ctypes.byref(h)))
+        self._h = h
+        self.n = n
+        self.nnz = int(rp[-1])
+
+    # ---- the super-step -------------------------------------------------
+    def global_trade(self, seed: int, rnd: int):
+        _check(lib().global_trade(self._h, seed, rnd))
+
+    def run_steps(self, seed: int, rnd: int, last_step: int):
+        _check(lib().global_trade_steps(self._h, seed, rnd, last_step))
+
+    def sync(self):
+        _check(lib().graph_sync(self._h))
+
+    def download(self):
+        col = np.empty(max(self.nnz, 1), np.int32)
+        _check(lib().graph_download(self._h, None, col.ctypes.data))
+        return col[:self.nnz]
+
+    def state(self, which: int):
+        count = {STATE_PERM: self.n, STATE_TRADE_OF: self.n, STATE_DEP: self.n // 2,
+                 STATE_COL: self.nnz}[which]
+        out = np.empty(max(count, 1), np.int32)
+        _check(lib().graph_download_state(self._h, which, out.ctypes.data, count))
+        return out[:count]
+
+    def set_option(self, option: int, value: int):
+        _check(lib().graph_set_option(self._h, option, value))
+
+    def stats(self):
+        st = RoundStats()
+        _check(lib().graph_stats(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def kernel_times(self):
+        ms = (ctypes.c_double * 4)()
+        rounds = ctypes.c_int64()
+        _check(lib().graph_kernel_times(self._h, ms, 4, ctypes.byref(rounds)))
+        return [float(x) for x in ms], int(rounds.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().graph_free(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,118 @@
+// Device-side helpers for the gfx950 global Curveball library: the counter
+// random numbers, agent-scope atomics and fences, and wavefront primitives.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cbx {
+
+constexpr uint32_t kTagMatch = 0x4D415443u;   // node sort keys
+constexpr uint32_t kTagSplit = 0x46595348u;   // split draws
+constexpr int32_t kUnmatched = 0x7fffffff;    // trade of the node left out
+constexpr int kWave = 64;
+
+// Error bits of the device error word.
+constexpr int32_t kErrWatchdog = 1;
+constexpr int32_t kErrInbox = 2;       // more arrivals than the row has slots
+constexpr int32_t kErrOut = 4;         // more final edges than the row has slots
+constexpr int32_t kErrDep = 8;         // dependency counter went below zero
+constexpr int32_t kErrGather = 16;     // trade saw a row of the wrong size
+constexpr int32_t kErrCapacity = 32;   // size outside what a tier can hold
+constexpr int32_t kErrRows = 64;       // rebuilt row count differs from degree
+constexpr int32_t kErrInvalid = 128;   // upload validation failed
+constexpr int32_t kErrMatch = 256;     // matching bucket beyond capacity
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11); returns (w1 << 32) | w0.
+__device__ __forceinline__ uint64_t philox64(uint64_t seed, uint32_t c0, uint32_t c1,
+                                             uint32_t c2, uint32_t c3) {
+  uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    const uint32_t n0 = hi1 ^ c1 ^ k0;
+    const uint32_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return ((uint64_t)c1 << 32) | c0;
+}
+
+// floor(x * k / 2^64)
+__device__ __forceinline__ uint64_t bounded(uint64_t x, uint64_t k) { return __umul64hi(x, k); }
+
+// ---- agent-scope memory operations ---------------------------------------
+__device__ __forceinline__ int32_t atomic_add(int32_t* p, int32_t v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t atomic_or(int32_t* p, int32_t v) {
+  return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ bool atomic_cas(int32_t* p, int32_t expected, int32_t desired) {
+  return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED,
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t load_agent(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_agent(int32_t* p, int32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+__device__ __forceinline__ void fence_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+__device__ __forceinline__ void fence_acq_rel() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent"); }
+
+// ---- wavefront primitives -------------------------------------------------
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
+
+// Number of set bits of `mask` below this lane.
+__device__ __forceinline__ int rank_below(uint64_t mask) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+__device__ __forceinline__ int popc64(uint64_t m) { return __popcll(m); }
+
+// Orders this wavefront's LDS accesses across lanes (no cross-wave effect).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_bcast(T v, int src_lane) {
+  return __shfl(v, src_lane, kWave);
+}
+
+// Inclusive prefix sum across the wavefront.
+__device__ __forceinline__ int32_t wave_incl_scan(int32_t v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int32_t t = __shfl_up(v, d, kWave);
+    if (l >= d) v += t;
+  }
+  return v;
+}
+
+__device__ __forceinline__ int32_t wave_sum(int32_t v) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+  return v;
+}
+
+__device__ __forceinline__ uint32_t next_pow2(uint32_t x) {
+  if (x <= 1) return 1;
+  return 1u << (32 - __clz(x - 1));
+}
+
+// Constant-rate clock (used only by the watchdog).
+__device__ __forceinline__ uint64_t now_ticks() { return wall_clock64(); }
+
+}  // namespace cbx

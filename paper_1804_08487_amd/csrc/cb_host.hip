@@ -1,0 +1,565 @@
+// Host side of the C ABI declared in include/curveball.h: device buffers of
+// one chain, the launch sequence of a global trade, error reporting.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "curveball.h"
+#include "cb_kernels.hpp"
+
+using namespace cbx;
+
+namespace {
+
+thread_local std::string g_last_error;
+cb_allocator g_allocator = {nullptr, nullptr, nullptr};
+
+cb_status fail(cb_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+bool hip_ok(hipError_t e, std::string* msg, const char* what) {
+  if (e == hipSuccess) return true;
+  *msg = std::string(what) + ": " + hipGetErrorString(e);
+  return false;
+}
+
+int bitlen(uint64_t x) { return x ? 64 - __builtin_clzll(x) : 0; }
+
+constexpr int kTimedSteps = 4;
+
+struct EventSet {
+  hipEvent_t ev[kTimedSteps + 1];
+};
+
+}  // namespace
+
+struct cb_graph {
+  int64_t n = 0, nnz = 0;
+  int32_t L = 0;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  cb_allocator alloc{};
+  std::vector<void*> owned;
+
+  int64_t* rp = nullptr;
+  int32_t* col = nullptr;
+  int32_t* col_t = nullptr;
+  int32_t* col_out = nullptr;
+  int32_t* inbox = nullptr;
+  int32_t* inbox_cur = nullptr;
+  int32_t* out_cur = nullptr;
+  int32_t* perm = nullptr;
+  int32_t* trade_of = nullptr;
+  int32_t* mtmp = nullptr;
+  uint64_t* mkey = nullptr;
+  int32_t* dep = nullptr;
+  int32_t* src_list = nullptr;
+  int32_t* qs = nullptr;
+  int32_t* qb = nullptr;
+  int32_t* bcount = nullptr;
+  int32_t* bstart = nullptr;
+  int32_t* bcur = nullptr;
+  int32_t* ctrl = nullptr;
+  unsigned long long* stats = nullptr;
+  uint64_t* slots = nullptr;
+  int32_t* rows_small = nullptr;
+  int32_t* rows_mid = nullptr;
+  int32_t* rows_big = nullptr;
+  int64_t n_small = 0, n_mid = 0, n_big = 0;
+
+  int nb_log2 = 0;
+  int32_t nb = 1;
+  int keybits_node = 1, keybits_entry = 1;
+  int64_t smax = 1;
+  int64_t slot_elems = 0;
+  int cu_count = 1;
+  int occupancy_blocks = 1;
+  uint64_t ticks_per_ms = 100000;
+
+  // options
+  int32_t small_max = kSmallCap;
+  int32_t nbig = 0;          // 0: automatic
+  int32_t nbig_alloc = 0;    // slots allocated
+  int32_t grid_blocks = 0;   // 0: automatic
+  int32_t stack_cap = 8;
+  int64_t watchdog_ms = 20000;
+  bool timing = false;
+
+  bool poisoned = false;
+  std::string poison_msg;
+
+  std::vector<EventSet> pending, spare;
+  double ms_acc[kTimedSteps] = {0, 0, 0, 0};
+  int64_t rounds_timed = 0;
+};
+
+namespace {
+
+void* dev_alloc(cb_graph* g, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  void* p = nullptr;
+  if (g->alloc.alloc) {
+    p = g->alloc.alloc(bytes, g->alloc.user);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    p = nullptr;
+  }
+  if (p) g->owned.push_back(p);
+  return p;
+}
+
+void release_all(cb_graph* g) {
+  for (void* p : g->owned) {
+    if (g->alloc.free) g->alloc.free(p, g->alloc.user);
+    else (void)hipFree(p);
+  }
+  g->owned.clear();
+  for (auto& s : g->pending)
+    for (auto& e : s.ev) (void)hipEventDestroy(e);
+  for (auto& s : g->spare)
+    for (auto& e : s.ev) (void)hipEventDestroy(e);
+  g->pending.clear();
+  g->spare.clear();
+  if (g->own_stream && g->stream) (void)hipStreamDestroy(g->stream);
+  g->stream = nullptr;
+}
+
+template <typename T>
+bool alloc_into(cb_graph* g, T** out, int64_t count) {
+  *out = static_cast<T*>(dev_alloc(g, (size_t)std::max<int64_t>(count, 1) * sizeof(T)));
+  return *out != nullptr;
+}
+
+int grid_for(int64_t items, int per_block, int cap) {
+  int64_t b = (items + per_block - 1) / per_block;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (int)b;
+}
+
+std::string error_bits_text(int32_t bits) {
+  std::string s;
+  const struct { int32_t bit; const char* name; } names[] = {
+      {kErrWatchdog, "watchdog: trade kernel made no progress"},
+      {kErrInbox, "inbox overflow"},
+      {kErrOut, "output row overflow"},
+      {kErrDep, "dependency counter underflow"},
+      {kErrGather, "trade input size mismatch"},
+      {kErrCapacity, "tier capacity exceeded"},
+      {kErrRows, "rebuilt row size differs from degree"},
+      {kErrInvalid, "graph is not a simple symmetric sorted CSR"},
+      {kErrMatch, "matching bucket overflow"}};
+  for (auto& nm : names)
+    if (bits & nm.bit) { if (!s.empty()) s += "; "; s += nm.name; }
+  return s;
+}
+
+// Drain finished timing event sets into the per-step sums.
+void collect_timing(cb_graph* g) {
+  for (auto& s : g->pending) {
+    for (int i = 0; i < kTimedSteps; ++i) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, s.ev[i], s.ev[i + 1]) == hipSuccess) g->ms_acc[i] += ms;
+    }
+    g->rounds_timed += 1;
+    g->spare.push_back(s);
+  }
+  g->pending.clear();
+}
+
+cb_status sync_and_check(cb_graph* g) {
+  if (g->poisoned) return fail(CB_EPOISONED, "graph handle poisoned: " + g->poison_msg);
+  std::string msg;
+  if (!hip_ok(hipStreamSynchronize(g->stream), &msg, "hipStreamSynchronize")) {
+    g->poisoned = true;
+    g->poison_msg = msg;
+    return fail(CB_EDEVICE, msg);
+  }
+  int32_t err = 0;
+  if (!hip_ok(hipMemcpy(&err, g->ctrl + kCtrlErr, sizeof(int32_t), hipMemcpyDeviceToHost), &msg,
+              "hipMemcpy(error word)")) {
+    g->poisoned = true;
+    g->poison_msg = msg;
+    return fail(CB_EDEVICE, msg);
+  }
+  if (g->timing) collect_timing(g);
+  if (err) {
+    g->poisoned = true;
+    g->poison_msg = error_bits_text(err);
+    return fail((err & kErrWatchdog) ? CB_EWATCHDOG : CB_EDEVICE,
+                "device reported: " + g->poison_msg);
+  }
+  return CB_OK;
+}
+
+int32_t effective_nbig(const cb_graph* g) {
+  int32_t v = g->nbig > 0 ? g->nbig : std::max(1, g->cu_count / 2);
+  return std::min(v, g->nbig_alloc);
+}
+
+int32_t trade_grid(const cb_graph* g) {
+  int32_t blocks = g->grid_blocks > 0 ? g->grid_blocks : g->cu_count * g->occupancy_blocks;
+  return std::max(blocks, effective_nbig(g) + 1);
+}
+
+cb_status enqueue_round(cb_graph* g, uint64_t seed, uint32_t round, int last_step) {
+  if (!g) return fail(CB_EINVAL, "null graph");
+  if (g->poisoned) return fail(CB_EPOISONED, "graph handle poisoned: " + g->poison_msg);
+  if (last_step < CB_STEP_MATCHING || last_step > CB_STEP_REBUILD)
+    return fail(CB_EINVAL, "last_step out of range");
+  if (g->n == 0) return CB_OK;
+  hipStream_t st = g->stream;
+  EventSet evs{};
+  const bool timed = g->timing && last_step == CB_STEP_REBUILD;
+  if (timed) {
+    if (!g->spare.empty()) {
+      evs = g->spare.back();
+      g->spare.pop_back();
+    } else {
+      for (auto& e : evs.ev)
+        if (hipEventCreate(&e) != hipSuccess) return fail(CB_EDEVICE, "hipEventCreate failed");
+    }
+    (void)hipEventRecord(evs.ev[0], st);
+  }
+  const int64_t n = g->n;
+  const int32_t L = g->L;
+
+  hipLaunchKernelGGL(k_round_reset, dim3(grid_for(std::max<int64_t>({n, (int64_t)L, (int64_t)g->nb}), 256, 8192)),
+                     dim3(256), 0, st, n, L, g->nb, g->inbox_cur, g->out_cur, g->bcount, g->bcur,
+                     g->qs, g->qb, g->ctrl, g->stats);
+  // 1. matching
+  hipLaunchKernelGGL(k_match_count, dim3(grid_for(n, 256, 16384)), dim3(256), 0, st, n, seed, round,
+                     g->nb_log2, g->bcount, g->ctrl);
+  hipLaunchKernelGGL(k_match_scan, dim3(1), dim3(1024), 0, st, g->nb, g->bcount, g->bstart, g->ctrl);
+  hipLaunchKernelGGL(k_match_scatter, dim3(grid_for(n, 256, 16384)), dim3(256), 0, st, n, seed,
+                     round, g->nb_log2, g->bstart, g->bcur, g->mtmp, g->ctrl);
+  hipLaunchKernelGGL(k_match_sort, dim3(std::min<int32_t>(g->nb, 1 << 20)), dim3(kMatchBlock), 0, st,
+                     n, seed, round, g->nb, g->bstart, g->mtmp, g->mkey, g->perm, g->trade_of,
+                     g->dep, g->ctrl);
+  if (timed) (void)hipEventRecord(evs.ev[1], st);
+  if (last_step >= CB_STEP_DEPSCAN) {
+    // 2. dependency scan + sources
+    if (g->nnz > 0)
+      hipLaunchKernelGGL(k_depscan, dim3((unsigned)((g->nnz + kScanChunk - 1) / kScanChunk)), dim3(256),
+                         0, st, n, g->nnz, g->rp, g->col, g->trade_of, g->col_t, g->dep, g->ctrl);
+    if (L > 0)
+      hipLaunchKernelGGL(k_sources, dim3(grid_for(L, 256, 8192)), dim3(256), 0, st, L, g->dep,
+                         g->src_list, g->ctrl, g->stats);
+  }
+  if (timed) (void)hipEventRecord(evs.ev[2], st);
+  if (last_step >= CB_STEP_TRADE && L > 0) {
+    // 3. trades
+    TradeArgs A{};
+    A.rp = g->rp;
+    A.col = g->col;
+    A.col_t = g->col_t;
+    A.perm = g->perm;
+    A.inbox = g->inbox;
+    A.inbox_cur = g->inbox_cur;
+    A.col_out = g->col_out;
+    A.out_cur = g->out_cur;
+    A.dep = g->dep;
+    A.src_list = g->src_list;
+    A.qs = g->qs;
+    A.qb = g->qb;
+    A.ctrl = g->ctrl;
+    A.stats = g->stats;
+    A.slots = g->slots;
+    A.slot_elems = g->slot_elems;
+    A.smax = g->smax;
+    A.n = n;
+    A.L = L;
+    A.small_max = g->small_max;
+    A.nbig = effective_nbig(g);
+    A.stack_cap = g->stack_cap;
+    A.keybits = g->keybits_entry;
+    A.round = round;
+    A.seed = seed;
+    A.watchdog_ticks = (uint64_t)g->watchdog_ms * g->ticks_per_ms;
+    hipLaunchKernelGGL(k_trade, dim3(trade_grid(g)), dim3(kTradeBlock), 0, st, A);
+    hipLaunchKernelGGL(k_check_rows, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, n, g->rp,
+                       g->out_cur, g->ctrl);
+  }
+  if (timed) (void)hipEventRecord(evs.ev[3], st);
+  if (last_step >= CB_STEP_REBUILD && g->nnz > 0) {
+    // 4. rebuild: per-row ascending sort of col_out into col
+    if (g->n_small)
+      hipLaunchKernelGGL(k_segsort_small, dim3(grid_for(g->n_small, 4, 65536)), dim3(256), 0, st,
+                         g->rows_small, g->n_small, g->rp, g->col_out, g->col, g->ctrl);
+    if (g->n_mid)
+      hipLaunchKernelGGL(k_segsort_mid, dim3(grid_for(g->n_mid, 1, 65536)), dim3(256), 0, st,
+                         g->rows_mid, g->n_mid, g->rp, g->col_out, g->col, g->ctrl);
+    if (g->n_big)
+      hipLaunchKernelGGL(k_segsort_big, dim3(grid_for(g->n_big, 1, 8192)), dim3(256), 0, st,
+                         g->rows_big, g->n_big, g->rp, g->col_out, g->col, g->keybits_node, g->ctrl);
+  }
+  if (timed) {
+    (void)hipEventRecord(evs.ev[4], st);
+    g->pending.push_back(evs);
+  }
+  std::string msg;
+  if (!hip_ok(hipGetLastError(), &msg, "kernel launch")) {
+    g->poisoned = true;
+    g->poison_msg = msg;
+    return fail(CB_EDEVICE, msg);
+  }
+  return CB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cb_status cb_set_allocator(const cb_allocator* a) {
+  if (a && (!a->alloc || !a->free)) return fail(CB_EINVAL, "allocator needs alloc and free");
+  g_allocator = a ? *a : cb_allocator{nullptr, nullptr, nullptr};
+  return CB_OK;
+}
+
+const char* cb_last_error(void) { return g_last_error.c_str(); }
+
+cb_status graph_upload(int64_t n, const int64_t* row_ptr, const int32_t* col, void* stream,
+                       uint32_t flags, cb_graph** out) {
+  if (!out) return fail(CB_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n < 0 || n > INT32_MAX) return fail(CB_EINVAL, "n must be in [0, 2^31 - 1]");
+  if (!row_ptr) return fail(CB_EINVAL, "row_ptr is NULL");
+  if (row_ptr[0] != 0) return fail(CB_EINVAL, "row_ptr[0] must be 0");
+  int64_t d1 = 0, d2 = 0;
+  for (int64_t x = 0; x < n; ++x) {
+    const int64_t d = row_ptr[x + 1] - row_ptr[x];
+    if (d < 0) return fail(CB_EINVAL, "row_ptr is not monotone");
+    if (d >= n && d > 0) return fail(CB_ENOTSIMPLE, "a row has more entries than other nodes");
+    if (d > d1) { d2 = d1; d1 = d; } else if (d > d2) { d2 = d; }
+  }
+  const int64_t nnz = row_ptr[n];
+  if (nnz % 2) return fail(CB_ENOTSIMPLE, "odd number of entries cannot be symmetric");
+  if (nnz >= INT32_MAX) return fail(CB_EINVAL, "2m must be below 2^31");
+  if (nnz > 0 && !col) return fail(CB_EINVAL, "col is NULL");
+
+  cb_graph* g = new cb_graph();
+  g->alloc = g_allocator;
+  g->n = n;
+  g->nnz = nnz;
+  g->L = (int32_t)(n / 2);
+  std::string msg;
+  if (!hip_ok(hipGetDevice(&g->device), &msg, "hipGetDevice")) { delete g; return fail(CB_EDEVICE, msg); }
+  if (stream) {
+    g->stream = (hipStream_t)stream;
+  } else {
+    if (!hip_ok(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking), &msg, "hipStreamCreate")) {
+      delete g;
+      return fail(CB_EDEVICE, msg);
+    }
+    g->own_stream = true;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, g->device) == hipSuccess) g->cu_count = prop.multiProcessorCount;
+  int rate_khz = 0;
+  if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, g->device) == hipSuccess &&
+      rate_khz > 0)
+    g->ticks_per_ms = (uint64_t)rate_khz;
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(k_trade),
+                                                   kTradeBlock, 0) == hipSuccess && occ > 0)
+    g->occupancy_blocks = occ;
+
+  g->nb_log2 = std::max(0, bitlen((uint64_t)std::max<int64_t>(n, 1)) - 1 - 8);
+  g->nb = 1 << g->nb_log2;
+  g->keybits_node = std::max(1, bitlen((uint64_t)std::max<int64_t>(n - 1, 1)));
+  g->keybits_entry = std::max(1, bitlen((uint64_t)std::max<int64_t>(2 * n - 1, 1)));
+  g->smax = std::max<int64_t>(d1 + d2, 1);
+  g->slot_elems = 2 * g->smax + g->smax / 2 + 1;
+  g->nbig_alloc = std::max(1, g->cu_count / 2);
+
+  // size classes of the per-row rebuild (degrees never change)
+  std::vector<int32_t> rs, rm, rb;
+  for (int64_t x = 0; x < n; ++x) {
+    const int64_t d = row_ptr[x + 1] - row_ptr[x];
+    if (d == 0) continue;
+    if (d <= kSegSmallMax) rs.push_back((int32_t)x);
+    else if (d <= kSegMidMax) rm.push_back((int32_t)x);
+    else rb.push_back((int32_t)x);
+  }
+  g->n_small = (int64_t)rs.size();
+  g->n_mid = (int64_t)rm.size();
+  g->n_big = (int64_t)rb.size();
+
+  bool ok = alloc_into(g, &g->rp, n + 1) && alloc_into(g, &g->col, nnz) &&
+            alloc_into(g, &g->col_t, nnz) && alloc_into(g, &g->col_out, nnz) &&
+            alloc_into(g, &g->inbox, nnz) && alloc_into(g, &g->inbox_cur, n) &&
+            alloc_into(g, &g->out_cur, n) && alloc_into(g, &g->perm, n) &&
+            alloc_into(g, &g->trade_of, n) && alloc_into(g, &g->mtmp, n) &&
+            alloc_into(g, &g->mkey, n) && alloc_into(g, &g->dep, g->L) &&
+            alloc_into(g, &g->src_list, g->L) && alloc_into(g, &g->qs, g->L) &&
+            alloc_into(g, &g->qb, g->L) && alloc_into(g, &g->bcount, g->nb) &&
+            alloc_into(g, &g->bstart, g->nb + 1) && alloc_into(g, &g->bcur, g->nb) &&
+            alloc_into(g, &g->ctrl, kCtrlCount) && alloc_into(g, &g->stats, kStatCount) &&
+            alloc_into(g, &g->slots, (int64_t)g->nbig_alloc * g->slot_elems) &&
+            alloc_into(g, &g->rows_small, g->n_small) && alloc_into(g, &g->rows_mid, g->n_mid) &&
+            alloc_into(g, &g->rows_big, g->n_big);
+  if (!ok) {
+    release_all(g);
+    delete g;
+    return fail(CB_ENOMEM, "device allocation failed");
+  }
+  hipStream_t st = g->stream;
+  ok = hip_ok(hipMemcpyAsync(g->rp, row_ptr, (size_t)(n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st), &msg, "copy row_ptr") &&
+       (nnz == 0 || hip_ok(hipMemcpyAsync(g->col, col, (size_t)nnz * sizeof(int32_t), hipMemcpyHostToDevice, st), &msg, "copy col")) &&
+       (rs.empty() || hip_ok(hipMemcpyAsync(g->rows_small, rs.data(), rs.size() * sizeof(int32_t), hipMemcpyHostToDevice, st), &msg, "copy rows")) &&
+       (rm.empty() || hip_ok(hipMemcpyAsync(g->rows_mid, rm.data(), rm.size() * sizeof(int32_t), hipMemcpyHostToDevice, st), &msg, "copy rows")) &&
+       (rb.empty() || hip_ok(hipMemcpyAsync(g->rows_big, rb.data(), rb.size() * sizeof(int32_t), hipMemcpyHostToDevice, st), &msg, "copy rows")) &&
+       hip_ok(hipMemsetAsync(g->ctrl, 0, kCtrlCount * sizeof(int32_t), st), &msg, "clear ctrl");
+  if (ok && (flags & CB_VALIDATE) && nnz > 0) {
+    hipLaunchKernelGGL(k_validate, dim3((unsigned)((nnz + kScanChunk - 1) / kScanChunk)), dim3(256), 0, st,
+                       n, nnz, g->rp, g->col, g->ctrl);
+    ok = hip_ok(hipGetLastError(), &msg, "k_validate launch");
+  }
+  if (ok) ok = hip_ok(hipStreamSynchronize(st), &msg, "upload sync");
+  int32_t err = 0;
+  if (ok) ok = hip_ok(hipMemcpy(&err, g->ctrl + kCtrlErr, sizeof(int32_t), hipMemcpyDeviceToHost), &msg, "read error word");
+  if (!ok) {
+    release_all(g);
+    delete g;
+    return fail(CB_EDEVICE, msg);
+  }
+  if (err) {
+    release_all(g);
+    delete g;
+    return fail(CB_ENOTSIMPLE, "upload validation: " + error_bits_text(err));
+  }
+  *out = g;
+  return CB_OK;
+}
+
+cb_status graph_info(const cb_graph* g, int64_t* n, int64_t* nnz) {
+  if (!g) return fail(CB_EINVAL, "null graph");
+  if (n) *n = g->n;
+  if (nnz) *nnz = g->nnz;
+  return CB_OK;
+}
+
+cb_status global_trade(cb_graph* g, uint64_t seed, uint32_t round) {
+  return enqueue_round(g, seed, round, CB_STEP_REBUILD);
+}
+
+cb_status global_trade_steps(cb_graph* g, uint64_t seed, uint32_t round, int32_t last_step) {
+  return enqueue_round(g, seed, round, last_step);
+}
+
+cb_status graph_sync(cb_graph* g) {
+  if (!g) return fail(CB_EINVAL, "null graph");
+  return sync_and_check(g);
+}
+
+cb_status graph_download(cb_graph* g, int64_t* row_ptr, int32_t* col) {
+  if (!g) return fail(CB_EINVAL, "null graph");
+  if (g->nnz > 0 && !col) return fail(CB_EINVAL, "col is NULL");
+  cb_status s = sync_and_check(g);
+  if (s != CB_OK) return s;
+  std::string msg;
+  if (row_ptr && !hip_ok(hipMemcpy(row_ptr, g->rp, (size_t)(g->n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost), &msg, "download row_ptr"))
+    return fail(CB_EDEVICE, msg);
+  if (g->nnz > 0 && !hip_ok(hipMemcpy(col, g->col, (size_t)g->nnz * sizeof(int32_t), hipMemcpyDeviceToHost), &msg, "download col"))
+    return fail(CB_EDEVICE, msg);
+  return CB_OK;
+}
+
+cb_status graph_download_state(cb_graph* g, int32_t which, void* host, int64_t count) {
+  if (!g) return fail(CB_EINVAL, "null graph");
+  if (count < 0 || (count > 0 && !host)) return fail(CB_EINVAL, "bad buffer");
+  const void* src = nullptr;
+  int64_t avail = 0;
+  switch (which) {
+    case CB_STATE_PERM: src = g->perm; avail = g->n; break;
+    case CB_STATE_TRADE_OF: src = g->trade_of; avail = g->n; break;
+    case CB_STATE_DEP: src = g->dep; avail = g->L; break;
+    case CB_STATE_COL: src = g->col; avail = g->nnz; break;
+    default: return fail(CB_EINVAL, "unknown state id");
+  }
+  if (count > avail) return fail(CB_EINVAL, "count exceeds the state size");
+  cb_status s = sync_and_check(g);
+  if (s != CB_OK) return s;
+  std::string msg;
+  if (count > 0 && !hip_ok(hipMemcpy(host, src, (size_t)count * sizeof(int32_t), hipMemcpyDeviceToHost), &msg, "download state"))
+    return fail(CB_EDEVICE, msg);
+  return CB_OK;
+}
+
+cb_status graph_set_option(cb_graph* g, int32_t option, int64_t value) {
+  if (!g) return fail(CB_EINVAL, "null graph");
+  switch (option) {
+    case CB_OPT_SMALL_MAX:
+      if (value < 0 || value > kSmallCap) return fail(CB_EINVAL, "small_max must be in [0, 256]");
+      g->small_max = (int32_t)value;
+      return CB_OK;
+    case CB_OPT_BIG_WORKERS:
+      if (value < 1 || value > g->nbig_alloc) return fail(CB_EINVAL, "big workers out of range");
+      g->nbig = (int32_t)value;
+      return CB_OK;
+    case CB_OPT_GRID_BLOCKS:
+      if (value < 0 || value > (1 << 20)) return fail(CB_EINVAL, "grid blocks out of range");
+      g->grid_blocks = (int32_t)value;
+      return CB_OK;
+    case CB_OPT_WATCHDOG_MS:
+      if (value < 1 || value > 3600 * 1000) return fail(CB_EINVAL, "watchdog out of range");
+      g->watchdog_ms = value;
+      return CB_OK;
+    case CB_OPT_TIMING:
+      g->timing = value != 0;
+      return CB_OK;
+    case CB_OPT_LOCAL_STACK:
+      if (value < 0 || value > kStackCap) return fail(CB_EINVAL, "local stack must be in [0, 16]");
+      g->stack_cap = (int32_t)value;
+      return CB_OK;
+    default:
+      return fail(CB_EINVAL, "unknown option");
+  }
+}
+
+cb_status graph_stats(cb_graph* g, cb_round_stats* out) {
+  if (!g || !out) return fail(CB_EINVAL, "null argument");
+  cb_status s = sync_and_check(g);
+  if (s != CB_OK) return s;
+  unsigned long long st[kStatCount] = {0};
+  std::string msg;
+  if (!hip_ok(hipMemcpy(st, g->stats, sizeof(st), hipMemcpyDeviceToHost), &msg, "read stats"))
+    return fail(CB_EDEVICE, msg);
+  out->trades = g->L;
+  out->small_trades = (int64_t)st[kStatSmall];
+  out->big_trades = (int64_t)st[kStatBig];
+  out->sources = (int64_t)st[kStatSources];
+  out->queue_pushes = (int64_t)st[kStatPush];
+  out->work = (int64_t)st[kStatWork];
+  out->forwarded = (int64_t)st[kStatForward];
+  out->emitted = (int64_t)st[kStatEmit];
+  return CB_OK;
+}
+
+cb_status graph_kernel_times(cb_graph* g, double* ms, int32_t count, int64_t* rounds) {
+  if (!g) return fail(CB_EINVAL, "null graph");
+  cb_status s = sync_and_check(g);
+  if (s != CB_OK) return s;
+  const int64_t r = g->rounds_timed;
+  for (int i = 0; i < count && i < kTimedSteps; ++i) ms[i] = r ? g->ms_acc[i] / (double)r : 0.0;
+  if (rounds) *rounds = r;
+  for (double& a : g->ms_acc) a = 0.0;
+  g->rounds_timed = 0;
+  return CB_OK;
+}
+
+void graph_free(cb_graph* g) {
+  if (!g) return;
+  if (g->stream) (void)hipStreamSynchronize(g->stream);
+  release_all(g);
+  delete g;
+}
+
+}  // extern "C"

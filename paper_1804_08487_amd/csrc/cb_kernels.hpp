@@ -1,0 +1,102 @@
+// Kernel entry points and argument blocks shared by the host orchestration
+// (cb_host.hip) and the kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cb_device.hpp"
+
+namespace cbx {
+
+// Slots of the per-graph control word array (int32, device memory).
+enum Ctrl : int {
+  kCtrlSrcCount = 0,   // trades with no dependency (written by k_sources)
+  kCtrlSrcHead,        // next source to hand out
+  kCtrlQsHead,         // small-trade ready queue
+  kCtrlQsTail,
+  kCtrlQbHead,         // large-trade ready queue
+  kCtrlQbTail,
+  kCtrlDone,           // completed trades (flushed by idle workers)
+  kCtrlErr,            // error bits (sticky across rounds)
+  kCtrlAbort,          // set with an error: every worker leaves
+  kCtrlCount = 16
+};
+
+// 64-bit round counters (device memory).
+enum Stat : int {
+  kStatSmall = 0, kStatBig, kStatPush, kStatWork, kStatForward, kStatEmit, kStatSources,
+  kStatCount = 8
+};
+
+constexpr int kSmallCap = 256;        // largest deg u + deg v on one wavefront
+constexpr int kTradeBlock = 256;      // threads per trade-kernel workgroup
+constexpr int kWavesPerBlock = kTradeBlock / 64;
+constexpr int kStackCap = 16;         // ready trades a wavefront may keep
+constexpr int kMatchCap = 2048;       // bucket size sorted in LDS by k_match_sort
+constexpr int kMatchBlock = 256;
+constexpr int kScanChunk = 2048;      // CSR entries per workgroup in k_depscan/k_validate
+constexpr int kSegMidMax = 4096;      // rows sorted in LDS by one workgroup
+constexpr int kSegSmallMax = 64;      // rows sorted in registers by one wavefront
+
+struct TradeArgs {
+  const int64_t* rp;
+  const int32_t* col;
+  const int32_t* col_t;     // trade index of every neighbour, from k_depscan
+  const int32_t* perm;
+  int32_t* inbox;           // CSR-shaped: arrivals for each node's row
+  int32_t* inbox_cur;
+  int32_t* col_out;         // CSR-shaped: final edges of the round
+  int32_t* out_cur;
+  int32_t* dep;
+  const int32_t* src_list;
+  int32_t* qs;              // ready queue, small trades (L slots, -1 = empty)
+  int32_t* qb;              // ready queue, large trades
+  int32_t* ctrl;
+  unsigned long long* stats;
+  uint64_t* slots;          // large-trade scratch, slot_elems u64 per workgroup
+  int64_t slot_elems;       // = 2 * smax + smax / 2 + 1
+  int64_t smax;             // largest possible deg u + deg v
+  int64_t n;
+  int32_t L;
+  int32_t small_max;
+  int32_t nbig;
+  int32_t stack_cap;
+  int32_t keybits;          // bits of (node << 1 | side)
+  uint32_t round;
+  uint64_t seed;
+  uint64_t watchdog_ticks;
+};
+
+// ---- kernels ---------------------------------------------------------------
+__global__ void k_round_reset(int64_t n, int32_t L, int32_t nb, int32_t* inbox_cur,
+                              int32_t* out_cur, int32_t* bcount, int32_t* bcur, int32_t* qs,
+                              int32_t* qb, int32_t* ctrl, unsigned long long* stats);
+__global__ void k_match_count(int64_t n, uint64_t seed, uint32_t round, int nb_log2,
+                              int32_t* bcount, const int32_t* ctrl);
+__global__ void k_match_scan(int32_t nb, const int32_t* bcount, int32_t* bstart,
+                             const int32_t* ctrl);
+__global__ void k_match_scatter(int64_t n, uint64_t seed, uint32_t round, int nb_log2,
+                                const int32_t* bstart, int32_t* bcur, int32_t* mtmp,
+                                const int32_t* ctrl);
+__global__ void k_match_sort(int64_t n, uint64_t seed, uint32_t round, int32_t nb,
+                             const int32_t* bstart, int32_t* mtmp, uint64_t* mkey,
+                             int32_t* perm, int32_t* trade_of, int32_t* dep, int32_t* ctrl);
+__global__ void k_depscan(int64_t n, int64_t nnz, const int64_t* rp, const int32_t* col,
+                          const int32_t* trade_of, int32_t* col_t, int32_t* dep,
+                          const int32_t* ctrl);
+__global__ void k_sources(int32_t L, const int32_t* dep, int32_t* src_list, int32_t* ctrl,
+                          unsigned long long* stats);
+__global__ void k_trade(TradeArgs A);
+__global__ void k_check_rows(int64_t n, const int64_t* rp, const int32_t* out_cur,
+                             int32_t* ctrl);
+__global__ void k_segsort_small(const int32_t* rows, int64_t nrows, const int64_t* rp,
+                                const int32_t* src, int32_t* dst, const int32_t* ctrl);
+__global__ void k_segsort_mid(const int32_t* rows, int64_t nrows, const int64_t* rp,
+                              const int32_t* src, int32_t* dst, const int32_t* ctrl);
+__global__ void k_segsort_big(const int32_t* rows, int64_t nrows, const int64_t* rp,
+                              int32_t* src, int32_t* dst, int keybits, const int32_t* ctrl);
+__global__ void k_validate(int64_t n, int64_t nnz, const int64_t* rp, const int32_t* col,
+                           int32_t* ctrl);
+
+}  // namespace cbx

@@ -1,0 +1,337 @@
+// Kernels around the trade kernel: per-round reset, the matching (hash keys,
+// bucket sort, pairing), the dependency scan, the source list, the row-count
+// check, the per-row sort that rebuilds the CSR, and upload validation.
+#include "cb_block.hpp"
+#include "cb_kernels.hpp"
+
+namespace cbx {
+
+__global__ void k_round_reset(int64_t n, int32_t L, int32_t nb, int32_t* inbox_cur,
+                              int32_t* out_cur, int32_t* bcount, int32_t* bcur, int32_t* qs,
+                              int32_t* qb, int32_t* ctrl, unsigned long long* stats) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t i = t0; i < n; i += stride) {
+    inbox_cur[i] = 0;
+    out_cur[i] = 0;
+  }
+  for (int64_t i = t0; i < nb; i += stride) {
+    bcount[i] = 0;
+    bcur[i] = 0;
+  }
+  for (int64_t i = t0; i < L; i += stride) {
+    qs[i] = -1;
+    qb[i] = -1;
+  }
+  if (t0 < kCtrlCount && t0 != kCtrlErr && t0 != kCtrlAbort) ctrl[t0] = 0;
+  if (t0 < kStatCount) stats[t0] = 0;
+}
+
+// ---------------------------------------------------------------- matching
+// Node v's key is philox64(seed; v, round, 0, TAG_M). Nodes are bucketed by
+// the top nb_log2 key bits (buckets are in key order), each bucket is sorted
+// by (key, id) in LDS, and the concatenation is the pairing order.
+
+__device__ __forceinline__ uint64_t node_key(uint64_t seed, uint32_t round, int64_t v) {
+  return philox64(seed, (uint32_t)v, round, 0u, kTagMatch);
+}
+__device__ __forceinline__ uint32_t key_bucket(uint64_t key, int nb_log2) {
+  return nb_log2 ? (uint32_t)(key >> (64 - nb_log2)) : 0u;
+}
+
+__global__ void k_match_count(int64_t n, uint64_t seed, uint32_t round, int nb_log2,
+                              int32_t* bcount, const int32_t* ctrl) {
+  if (ctrl[kCtrlErr]) return;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
+    atomicAdd(&bcount[key_bucket(node_key(seed, round, v), nb_log2)], 1);
+}
+
+__global__ void k_match_scan(int32_t nb, const int32_t* bcount, int32_t* bstart,
+                             const int32_t* ctrl) {
+  __shared__ int32_t scratch[17];
+  __shared__ int32_t carry;
+  if (ctrl[kCtrlErr]) return;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int32_t base = 0; base < nb; base += blockDim.x) {
+    const int32_t i = base + threadIdx.x;
+    const int32_t v = i < nb ? bcount[i] : 0;
+    int32_t total;
+    const int32_t ex = block_excl_scan(v, scratch, &total);
+    if (i < nb) bstart[i] = carry + ex;
+    __syncthreads();
+    if (threadIdx.x == 0) carry += total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bstart[nb] = carry;
+}
+
+__global__ void k_match_scatter(int64_t n, uint64_t seed, uint32_t round, int nb_log2,
+                                const int32_t* bstart, int32_t* bcur, int32_t* mtmp,
+                                const int32_t* ctrl) {
+  if (ctrl[kCtrlErr]) return;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+    const uint32_t b = key_bucket(node_key(seed, round, v), nb_log2);
+    mtmp[bstart[b] + atomicAdd(&bcur[b], 1)] = (int32_t)v;
+  }
+}
+
+struct KeyedNode {
+  uint64_t key;
+  uint32_t id;
+  __device__ bool operator<(const KeyedNode& o) const {
+    return key < o.key || (key == o.key && id < o.id);
+  }
+};
+
+__device__ __forceinline__ void write_pair_slot(int64_t n, int64_t p, int32_t id, int32_t* perm,
+                                                int32_t* trade_of, int32_t* dep) {
+  perm[p] = id;
+  const bool left_out = (n & 1) && p == n - 1;
+  trade_of[id] = left_out ? kUnmatched : (int32_t)(p >> 1);
+  if (!(p & 1) && p + 1 < n) dep[p >> 1] = 0;
+}
+
+__global__ void __launch_bounds__(kMatchBlock)
+k_match_sort(int64_t n, uint64_t seed, uint32_t round, int32_t nb, const int32_t* bstart,
+             int32_t* mtmp, uint64_t* mkey, int32_t* perm, int32_t* trade_of, int32_t* dep,
+             int32_t* ctrl) {
+  __shared__ KeyedNode buf[kMatchCap];
+  if (ctrl[kCtrlErr]) return;
+  for (int32_t b = blockIdx.x; b < nb; b += gridDim.x) {
+    const int64_t s0 = bstart[b];
+    const int64_t cnt = bstart[b + 1] - s0;
+    if (cnt <= kMatchCap) {
+      for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+        const int32_t id = mtmp[s0 + i];
+        buf[i].key = node_key(seed, round, id);
+        buf[i].id = (uint32_t)id;
+      }
+      __syncthreads();
+      block_bitonic_sort(buf, (uint32_t)cnt);
+      for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x)
+        write_pair_slot(n, s0 + i, (int32_t)buf[i].id, perm, trade_of, dep);
+      __syncthreads();
+    } else {
+      // A bucket this large has probability far below 2^-500 for hashed
+      // keys; it is still sorted exactly, in global memory.
+      uint64_t* k = mkey + s0;
+      int32_t* ids = mtmp + s0;
+      for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) k[i] = node_key(seed, round, ids[i]);
+      __syncthreads();
+      const uint64_t P = (uint64_t)next_pow2((uint32_t)cnt);
+      for (uint64_t k2 = 2; k2 <= P; k2 <<= 1) {
+        for (uint64_t d = k2 >> 1; d > 0; d >>= 1) {
+          for (uint64_t p = threadIdx.x; p < P / 2; p += blockDim.x) {
+            uint64_t i, j;
+            if (d == (k2 >> 1)) {
+              i = (p / d) * k2 + (p % d);
+              j = i ^ (k2 - 1);
+            } else {
+              i = (p / d) * 2 * d + (p % d);
+              j = i + d;
+            }
+            if (j < (uint64_t)cnt) {
+              const bool swap = k[j] < k[i] || (k[j] == k[i] && ids[j] < ids[i]);
+              if (swap) {
+                const uint64_t tk = k[i]; k[i] = k[j]; k[j] = tk;
+                const int32_t ti = ids[i]; ids[i] = ids[j]; ids[j] = ti;
+              }
+            }
+          }
+          __syncthreads();
+        }
+      }
+      for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x)
+        write_pair_slot(n, s0 + i, ids[i], perm, trade_of, dep);
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------- dep scan
+// dep[k] += number of neighbours y of the nodes of trade k with
+// trade_of[y] < k; col_t[e] = trade_of[col[e]] for every entry. Work is
+// split into equal chunks of CSR entries so hub rows do not serialise.
+
+__device__ __forceinline__ int64_t row_of_entry(const int64_t* rp, int64_t lo, int64_t hi, int64_t e) {
+  // largest r in [lo, hi] with rp[r] <= e
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (rp[mid] <= e) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void __launch_bounds__(256)
+k_depscan(int64_t n, int64_t nnz, const int64_t* rp, const int32_t* col,
+          const int32_t* trade_of, int32_t* col_t, int32_t* dep, const int32_t* ctrl) {
+  __shared__ int64_t lrp[kScanChunk + 1];
+  __shared__ int32_t cnt[kScanChunk];
+  __shared__ int64_t bounds[2];
+  if (ctrl[kCtrlErr]) return;
+  const int64_t e0 = (int64_t)blockIdx.x * kScanChunk;
+  if (e0 >= nnz) return;
+  const int64_t e1 = e0 + kScanChunk < nnz ? e0 + kScanChunk : nnz;
+  if (threadIdx.x == 0) bounds[0] = row_of_entry(rp, 0, n - 1, e0);
+  if (threadIdx.x == 1) bounds[1] = row_of_entry(rp, 0, n - 1, e1 - 1);
+  __syncthreads();
+  const int64_t r0 = bounds[0], r1 = bounds[1];
+  const int64_t nrows = r1 - r0 + 1;
+  const bool local = nrows <= kScanChunk;
+  if (local) {
+    for (int64_t i = threadIdx.x; i <= nrows; i += blockDim.x) lrp[i] = rp[r0 + i];
+    for (int64_t i = threadIdx.x; i < nrows; i += blockDim.x) cnt[i] = 0;
+  }
+  __syncthreads();
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    int64_t x;
+    if (local) {
+      int64_t lo = 0, hi = nrows - 1;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (lrp[mid] <= e) lo = mid; else hi = mid - 1;
+      }
+      x = r0 + lo;
+    } else {
+      x = row_of_entry(rp, r0, r1, e);
+    }
+    const int32_t t = trade_of[col[e]];
+    col_t[e] = t;
+    const int32_t k = trade_of[x];
+    if (k != kUnmatched && t < k) {
+      if (local) atomicAdd(&cnt[x - r0], 1);
+      else atomicAdd(&dep[k], 1);
+    }
+  }
+  __syncthreads();
+  if (local) {
+    for (int64_t i = threadIdx.x; i < nrows; i += blockDim.x)
+      if (cnt[i]) atomicAdd(&dep[trade_of[r0 + i]], cnt[i]);
+  }
+}
+
+__global__ void k_sources(int32_t L, const int32_t* dep, int32_t* src_list, int32_t* ctrl,
+                          unsigned long long* stats) {
+  if (ctrl[kCtrlErr]) return;
+  const int32_t stride = gridDim.x * blockDim.x;
+  // trip count is uniform across a wavefront (ballot below)
+  for (int32_t base = blockIdx.x * blockDim.x; base < L; base += stride) {
+    const int32_t k = base + threadIdx.x;
+    const bool src = k < L && dep[k] == 0;
+    const uint64_t m = ballot(src);
+    if (m == 0) continue;
+    int32_t pos = 0;
+    if (lane_id() == 0) {
+      pos = atomic_add(&ctrl[kCtrlSrcCount], popc64(m));
+      atomicAdd(&stats[kStatSources], (unsigned long long)popc64(m));
+    }
+    pos = wave_bcast(pos, 0);
+    if (src) src_list[pos + rank_below(m)] = k;
+  }
+}
+
+__global__ void k_check_rows(int64_t n, const int64_t* rp, const int32_t* out_cur, int32_t* ctrl) {
+  if (ctrl[kCtrlErr]) return;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += stride)
+    if ((int64_t)out_cur[x] != rp[x + 1] - rp[x]) atomic_or(&ctrl[kCtrlErr], kErrRows);
+}
+
+// ---------------------------------------------------------------- rebuild
+// Row x of src (its entries in any order) is written ascending to row x of
+// dst. Size classes are fixed at upload because degrees never change.
+
+__global__ void __launch_bounds__(256)
+k_segsort_small(const int32_t* rows, int64_t nrows, const int64_t* rp, const int32_t* src,
+                int32_t* dst, const int32_t* ctrl) {
+  if (ctrl[kCtrlErr]) return;
+  const int l = lane_id();
+  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t r = wid; r < nrows; r += nwaves) {
+    const int32_t x = rows[r];
+    const int64_t b = rp[x];
+    const int32_t d = (int32_t)(rp[x + 1] - b);
+    int32_t v = l < d ? src[b + l] : 0x7fffffff;
+    // bitonic network over the 64 lanes (padding sorts to the end)
+#pragma unroll
+    for (int k2 = 2; k2 <= kWave; k2 <<= 1) {
+#pragma unroll
+      for (int j = k2 >> 1; j > 0; j >>= 1) {
+        const int32_t o = __shfl_xor(v, j, kWave);
+        const bool up = (l & k2) == 0;
+        const bool lower = (l & j) == 0;
+        v = (lower == up) ? min(v, o) : max(v, o);
+      }
+    }
+    if (l < d) dst[b + l] = v;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_segsort_mid(const int32_t* rows, int64_t nrows, const int64_t* rp, const int32_t* src,
+              int32_t* dst, const int32_t* ctrl) {
+  __shared__ int32_t buf[kSegMidMax];
+  if (ctrl[kCtrlErr]) return;
+  for (int64_t r = blockIdx.x; r < nrows; r += gridDim.x) {
+    const int32_t x = rows[r];
+    const int64_t b = rp[x];
+    const int32_t d = (int32_t)(rp[x + 1] - b);
+    for (int32_t i = threadIdx.x; i < d; i += blockDim.x) buf[i] = src[b + i];
+    __syncthreads();
+    block_bitonic_sort(buf, (uint32_t)d);
+    for (int32_t i = threadIdx.x; i < d; i += blockDim.x) dst[b + i] = buf[i];
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_segsort_big(const int32_t* rows, int64_t nrows, const int64_t* rp, int32_t* src,
+              int32_t* dst, int keybits, const int32_t* ctrl) {
+  __shared__ RadixLds R;
+  if (ctrl[kCtrlErr]) return;
+  for (int64_t r = blockIdx.x; r < nrows; r += gridDim.x) {
+    const int32_t x = rows[r];
+    const int64_t b = rp[x];
+    const int64_t d = rp[x + 1] - b;
+    int32_t* out = block_radix_sort<int32_t>(src + b, dst + b, d, keybits, R);
+    if (out != dst + b) {
+      for (int64_t i = threadIdx.x; i < d; i += blockDim.x) dst[b + i] = out[i];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- validate
+// Every entry: id in range, not the row's own id, strictly above its left
+// neighbour in the row, and present in the neighbour's row (symmetry).
+
+__global__ void __launch_bounds__(256)
+k_validate(int64_t n, int64_t nnz, const int64_t* rp, const int32_t* col, int32_t* ctrl) {
+  __shared__ int64_t bounds[2];
+  const int64_t e0 = (int64_t)blockIdx.x * kScanChunk;
+  if (e0 >= nnz) return;
+  const int64_t e1 = e0 + kScanChunk < nnz ? e0 + kScanChunk : nnz;
+  if (threadIdx.x == 0) bounds[0] = row_of_entry(rp, 0, n - 1, e0);
+  if (threadIdx.x == 1) bounds[1] = row_of_entry(rp, 0, n - 1, e1 - 1);
+  __syncthreads();
+  bool bad = false;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    const int64_t x = row_of_entry(rp, bounds[0], bounds[1], e);
+    const int32_t y = col[e];
+    if (y < 0 || (int64_t)y >= n || (int64_t)y == x) { bad = true; continue; }
+    if (e > rp[x] && col[e - 1] >= y) bad = true;
+    int64_t lo = rp[y], hi = rp[y + 1];
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if ((int64_t)col[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    if (lo >= rp[y + 1] || (int64_t)col[lo] != x) bad = true;
+  }
+  if (bad) atomic_or(&ctrl[kCtrlErr], kErrInvalid);
+}
+
+}  // namespace cbx

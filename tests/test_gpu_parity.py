@@ -1,0 +1,155 @@
+"""Parity of the HIP path with the oracle, through the C ABI, on the GPU.
+
+Bit-exact integer results are the bar: every downloaded adjacency must equal
+the oracle's bytes; the matching and the dependency counts are compared
+element by element; at the full large size the matching and dependency
+counts are compared in full and the trade result by its invariants."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen
+import paper_1804_08487_amd as cb
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-parity] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.init()
+    yield
+
+
+def _small_graphs():
+    yield "pair", graphgen.edge_list_to_csr(2, [(0, 1)])
+    yield "three", graphgen.edge_list_to_csr(3, [(0, 1), (1, 2)])
+    yield "isolated", graphgen.edge_list_to_csr(7, [(0, 1), (2, 3)])
+    yield "empty", (np.zeros(6, np.int64), np.zeros(0, np.int32))
+    yield "star", graphgen.edge_list_to_csr(41, [(0, i) for i in range(1, 41)])
+    yield "clique", graphgen.edge_list_to_csr(24, [(i, j) for i in range(24) for j in range(i + 1, 24)])
+    yield "bipartite", graphgen.edge_list_to_csr(30, [(i, j) for i in range(10) for j in range(10, 30)])
+    for s in range(6):
+        yield f"er{s}", graphgen.random_simple_graph(40 + 7 * s, 0.08 + 0.05 * s, 100 + s)
+    yield "pld", graphgen.pld_graph(3000, 2, 300, 2.0, 11)
+    yield "pld_odd", graphgen.pld_graph(3001, 3, 400, 1.9, 12)
+
+
+SMALL = list(_small_graphs())
+TIERS = {"default": {}, "all_workgroup": {cb.OPT_SMALL_MAX: 0},
+         "tiny_wave": {cb.OPT_SMALL_MAX: 8, cb.OPT_BIG_WORKERS: 1},
+         "no_stack": {cb.OPT_LOCAL_STACK: 0}}
+
+
+def _run_and_compare(orc, rp, col, seed, rounds, options=None, form="o1"):
+    g = cb.Graph(rp, col)
+    for opt, val in (options or {}).items():
+        g.set_option(opt, val)
+    ref = col
+    for r in range(rounds):
+        ref, st = orc.global_trade(rp, ref, seed, r, form)
+        g.global_trade(seed, r)
+        got = g.download()
+        assert np.array_equal(got, ref), f"round {r}: {int((got != ref).sum())} entries differ"
+        gs = g.stats()
+        assert gs["trades"] == st["trades"]
+        assert gs["small_trades"] + gs["big_trades"] == st["trades"]
+        assert gs["work"] == st["work"]
+    g.close()
+    return ref
+
+
+@pytest.mark.parametrize("tier", list(TIERS))
+@pytest.mark.parametrize("name,g", SMALL, ids=[n for n, _ in SMALL])
+def test_small_graphs_bit_exact(orc, name, g, tier):
+    _say(f"small graph {name} tier {tier}")
+    rp, col = g
+    _run_and_compare(orc, rp, col, seed=7, rounds=3, options=TIERS[tier])
+
+
+def test_matching_and_depscan_match_oracle(orc):
+    for n_, seed, rnd in ((1, 3, 0), (2, 3, 1), (5, 4, 2), (8192, 1, 0), (8193, 2, 5), (100000, 9, 3)):
+        _say(f"matching n={n_}")
+        rp, col = graphgen.pld_graph(n_, 1, max(2, min(n_, 60)), 2.0, 5) if n_ > 2 else \
+            graphgen.edge_list_to_csr(n_, [(0, 1)] if n_ == 2 else [])
+        g = cb.Graph(rp, col)
+        g.run_steps(seed, rnd, cb.STEP_DEPSCAN)
+        perm = g.state(cb.STATE_PERM)
+        tof = g.state(cb.STATE_TRADE_OF)
+        dep = g.state(cb.STATE_DEP)
+        o_perm, o_tof = orc.matching(n_, seed, rnd)
+        assert np.array_equal(perm, o_perm)
+        assert np.array_equal(tof, o_tof)
+        assert np.array_equal(dep, orc.depcount(rp, col, o_tof, o_perm))
+        g.close()
+
+
+def test_small_workload_ten_rounds_every_round(orc):
+    rp, col = graphgen.workload("small")
+    _say(f"small workload n={len(rp)-1} m={len(col)//2}")
+    for tier in ("default", "all_workgroup"):
+        _run_and_compare(orc, rp, col, seed=1, rounds=10, options=TIERS[tier])
+
+
+def test_mid_workload_rounds_match_o2(orc):
+    rp, col = graphgen.workload("mid")
+    _say(f"mid workload n={len(rp)-1} m={len(col)//2}")
+    _run_and_compare(orc, rp, col, seed=1, rounds=2, form="o2")
+
+
+def test_determinism_and_resume(orc):
+    rp, col = graphgen.pld_graph(5000, 3, 500, 2.0, 21)
+    a = cb.Graph(rp, col)
+    for r in range(4):
+        a.global_trade(3, r)
+    x = a.download()
+    b = cb.Graph(rp, col)
+    for r in range(2):
+        b.global_trade(3, r)
+    mid = b.download()
+    b.close()
+    c = cb.Graph(rp, mid)
+    for r in range(2, 4):
+        c.global_trade(3, r)
+    assert np.array_equal(x, c.download())
+    a.close()
+    c.close()
+
+
+def test_torch_allocator_path(orc):
+    import torch
+    rp, col = graphgen.pld_graph(2000, 2, 200, 2.0, 31)
+    cb.use_torch_allocator(True)
+    try:
+        before = torch.cuda.memory_allocated()
+        g = cb.Graph(rp, col)
+        assert torch.cuda.memory_allocated() > before
+        g.global_trade(5, 0)
+        ref, _ = orc.global_trade(rp, col, 5, 0)
+        assert np.array_equal(g.download(), ref)
+        g.close()
+    finally:
+        cb.use_torch_allocator(False)
+
+
+@pytest.mark.parametrize("name", ["self_loop", "asymmetric", "unsorted", "out_of_range"])
+def test_upload_validation_rejects(name):
+    if name == "self_loop":
+        rp, col = np.array([0, 2, 3, 4]), np.array([0, 1, 0, 0])
+    elif name == "asymmetric":
+        rp, col = np.array([0, 1, 2, 2]), np.array([1, 2])
+    elif name == "unsorted":
+        rp, col = np.array([0, 2, 3, 4]), np.array([2, 1, 0, 0])
+    else:
+        rp, col = np.array([0, 1, 2, 2]), np.array([5, 0])
+    with pytest.raises(cb.CurveballError) as e:
+        cb.Graph(rp, col)
+    assert e.value.status == cb.CB_ENOTSIMPLE
