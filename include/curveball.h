@@ -119,19 +119,25 @@ cb_status global_trade_steps(cb_graph* g, uint64_t seed, uint32_t round, int32_t
 #define CB_STATE_TRADE_OF 2  /* int32[n]: trade of each node, INT32_MAX if none */
 #define CB_STATE_DEP      3  /* int32[n/2]: dependency counts after DEPSCAN */
 #define CB_STATE_COL      4  /* int32[nnz]: current adjacency (rows ascending) */
+#define CB_STATE_OUT_CUR  5  /* int32[n]: final edges written per row this round */
+#define CB_STATE_INBOX_CUR 6 /* int32[n]: edges handed to each row this round */
 
-/* Synchronise and copy `count` elements of state `which` to host memory. */
+/* Synchronise and copy `count` elements of state `which` to host memory.
+ * Also valid on a poisoned handle (diagnosis after a device error). */
 cb_status graph_download_state(cb_graph* g, int32_t which, void* host, int64_t count);
 
 /* ---- options ------------------------------------------------------------ */
 #define CB_OPT_SMALL_MAX     1  /* trades with deg u + deg v <= this run on one
-                                   wavefront (0..256); larger ones on a whole
-                                   workgroup. Default 256. */
+                                   wavefront (0..512); larger ones on a whole
+                                   workgroup. Default 512. */
 #define CB_OPT_BIG_WORKERS   2  /* workgroups reserved for large trades (>= 1) */
 #define CB_OPT_GRID_BLOCKS   3  /* workgroups of the trade kernel (0 = auto) */
 #define CB_OPT_WATCHDOG_MS   4  /* idle time after which the trade kernel gives up */
 #define CB_OPT_TIMING        5  /* 1: time every kernel with HIP events */
 #define CB_OPT_LOCAL_STACK   6  /* ready trades a wavefront keeps for itself (0..16) */
+#define CB_OPT_BIG_LDS_MAX   7  /* workgroup trades with deg u + deg v <= this
+                                   stay in LDS (0..12288); larger ones use a
+                                   global scratch slot. Default 12288. */
 
 cb_status graph_set_option(cb_graph* g, int32_t option, int64_t value);
 

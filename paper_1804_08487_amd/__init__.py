@@ -22,8 +22,8 @@ STATUS_NAMES = {0: "CB_OK", 1: "CB_EINVAL", 2: "CB_ENOTSIMPLE", 3: "CB_ENOMEM",
                 4: "CB_EDEVICE", 5: "CB_EWATCHDOG", 6: "CB_EPOISONED"}
 CB_VALIDATE = 1
 STEP_MATCHING, STEP_DEPSCAN, STEP_TRADE, STEP_REBUILD = 1, 2, 3, 4
-STATE_PERM, STATE_TRADE_OF, STATE_DEP, STATE_COL = 1, 2, 3, 4
-OPT_SMALL_MAX, OPT_BIG_WORKERS, OPT_GRID_BLOCKS, OPT_WATCHDOG_MS, OPT_TIMING, OPT_LOCAL_STACK = range(1, 7)
+STATE_PERM, STATE_TRADE_OF, STATE_DEP, STATE_COL, STATE_OUT_CUR, STATE_INBOX_CUR = 1, 2, 3, 4, 5, 6
+OPT_SMALL_MAX, OPT_BIG_WORKERS, OPT_GRID_BLOCKS, OPT_WATCHDOG_MS, OPT_TIMING, OPT_LOCAL_STACK, OPT_BIG_LDS_MAX = range(1, 8)
 UNMATCHED = 2**31 - 1
 
 # Every symbol declared in include/curveball.h.
@@ -162,7 +162,7 @@ class Graph:
 
     def state(self, which: int):
         count = {STATE_PERM: self.n, STATE_TRADE_OF: self.n, STATE_DEP: self.n // 2,
-                 STATE_COL: self.nnz}[which]
+                 STATE_COL: self.nnz, STATE_OUT_CUR: self.n, STATE_INBOX_CUR: self.n}[which]
         out = np.empty(max(count, 1), np.int32)
         _check(lib().graph_download_state(self._h, which, out.ctypes.data, count))
         return out[:count]

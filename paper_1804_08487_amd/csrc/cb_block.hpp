@@ -101,7 +101,7 @@ __device__ void wave_bitonic_sort(T* a, uint32_t s) {
 struct RadixLds {
   int32_t hist[256];
   int32_t offs[256];
-  int32_t wcnt[4][257];    // per-wave digit counts of one tile (at most 4 waves)
+  int32_t wcnt[16][257];   // per-wave digit counts of one tile (at most 16 waves)
   int32_t scan[17];
 };
 
@@ -112,7 +112,7 @@ template <> __device__ __forceinline__ uint32_t radix_key<int32_t>(int32_t e) { 
 // Stable LSD radix sort (8-bit digits) of s elements by the low `keybits`
 // bits of radix_key(), ping-ponging between a and b (both global memory,
 // s elements each). Returns the buffer that holds the sorted sequence.
-// Workgroup-wide (blockDim a multiple of 64, at most 256); barriers inside.
+// Workgroup-wide (blockDim a multiple of 64, at most 1024); barriers inside.
 template <typename T>
 __device__ T* block_radix_sort(T* a, T* b, int64_t s, int keybits, RadixLds& R) {
   const int tid = threadIdx.x;

@@ -85,6 +85,7 @@ struct cb_graph {
 
   // options
   int32_t small_max = kSmallCap;
+  int32_t big_lds_max = kBigCap;
   int32_t nbig = 0;          // 0: automatic
   int32_t nbig_alloc = 0;    // slots allocated
   int32_t grid_blocks = 0;   // 0: automatic
@@ -183,7 +184,7 @@ cb_status sync_and_check(cb_graph* g) {
     return fail(CB_EDEVICE, msg);
   }
   int32_t err = 0;
-  if (!hip_ok(hipMemcpy(&err, g->ctrl + kCtrlErr, sizeof(int32_t), hipMemcpyDeviceToHost), &msg,
+  if (!hip_ok(hipMemcpy(&err, g->ctrl + cw(kCwErr), sizeof(int32_t), hipMemcpyDeviceToHost), &msg,
               "hipMemcpy(error word)")) {
     g->poisoned = true;
     g->poison_msg = msg;
@@ -200,7 +201,7 @@ cb_status sync_and_check(cb_graph* g) {
 }
 
 int32_t effective_nbig(const cb_graph* g) {
-  int32_t v = g->nbig > 0 ? g->nbig : std::max(1, g->cu_count / 2);
+  int32_t v = g->nbig > 0 ? g->nbig : std::max(1, g->cu_count / 4);
   return std::min(v, g->nbig_alloc);
 }
 
@@ -231,9 +232,9 @@ cb_status enqueue_round(cb_graph* g, uint64_t seed, uint32_t round, int last_ste
   const int64_t n = g->n;
   const int32_t L = g->L;
 
-  hipLaunchKernelGGL(k_round_reset, dim3(grid_for(std::max<int64_t>({n, (int64_t)L, (int64_t)g->nb}), 256, 8192)),
-                     dim3(256), 0, st, n, L, g->nb, g->inbox_cur, g->out_cur, g->bcount, g->bcur,
-                     g->qs, g->qb, g->ctrl, g->stats);
+  hipLaunchKernelGGL(k_round_reset, dim3(grid_for(std::max<int64_t>({n, (int64_t)g->nb, (int64_t)kCwCount}), 256, 8192)),
+                     dim3(256), 0, st, n, g->nb, g->inbox_cur, g->out_cur, g->bcount, g->bcur,
+                     g->ctrl, g->stats);
   // 1. matching
   hipLaunchKernelGGL(k_match_count, dim3(grid_for(n, 256, 16384)), dim3(256), 0, st, n, seed, round,
                      g->nb_log2, g->bcount, g->ctrl);
@@ -277,6 +278,7 @@ cb_status enqueue_round(cb_graph* g, uint64_t seed, uint32_t round, int last_ste
     A.n = n;
     A.L = L;
     A.small_max = g->small_max;
+    A.big_lds_max = g->big_lds_max;
     A.nbig = effective_nbig(g);
     A.stack_cap = g->stack_cap;
     A.keybits = g->keybits_entry;
@@ -284,10 +286,11 @@ cb_status enqueue_round(cb_graph* g, uint64_t seed, uint32_t round, int last_ste
     A.seed = seed;
     A.watchdog_ticks = (uint64_t)g->watchdog_ms * g->ticks_per_ms;
     hipLaunchKernelGGL(k_trade, dim3(trade_grid(g)), dim3(kTradeBlock), 0, st, A);
-    hipLaunchKernelGGL(k_check_rows, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, n, g->rp,
-                       g->out_cur, g->ctrl);
   }
   if (timed) (void)hipEventRecord(evs.ev[3], st);
+  if (last_step >= CB_STEP_TRADE && L > 0)
+    hipLaunchKernelGGL(k_check_rows, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, n, g->rp,
+                       g->out_cur, g->ctrl);
   if (last_step >= CB_STEP_REBUILD && g->nnz > 0) {
     // 4. rebuild: per-row ascending sort of col_out into col
     if (g->n_small)
@@ -398,10 +401,10 @@ cb_status graph_upload(int64_t n, const int64_t* row_ptr, const int32_t* col, vo
             alloc_into(g, &g->out_cur, n) && alloc_into(g, &g->perm, n) &&
             alloc_into(g, &g->trade_of, n) && alloc_into(g, &g->mtmp, n) &&
             alloc_into(g, &g->mkey, n) && alloc_into(g, &g->dep, g->L) &&
-            alloc_into(g, &g->src_list, g->L) && alloc_into(g, &g->qs, g->L) &&
-            alloc_into(g, &g->qb, g->L) && alloc_into(g, &g->bcount, g->nb) &&
+            alloc_into(g, &g->src_list, g->L) && alloc_into(g, &g->qs, (int64_t)kQsShards * std::max<int64_t>(g->L, 1)) &&
+            alloc_into(g, &g->qb, (int64_t)kQbShards * std::max<int64_t>(g->L, 1)) && alloc_into(g, &g->bcount, g->nb) &&
             alloc_into(g, &g->bstart, g->nb + 1) && alloc_into(g, &g->bcur, g->nb) &&
-            alloc_into(g, &g->ctrl, kCtrlCount) && alloc_into(g, &g->stats, kStatCount) &&
+            alloc_into(g, &g->ctrl, kCtrlInts) && alloc_into(g, &g->stats, kStatCount) &&
             alloc_into(g, &g->slots, (int64_t)g->nbig_alloc * g->slot_elems) &&
             alloc_into(g, &g->rows_small, g->n_small) && alloc_into(g, &g->rows_mid, g->n_mid) &&
             alloc_into(g, &g->rows_big, g->n_big);
@@ -416,7 +419,9 @@ cb_status graph_upload(int64_t n, const int64_t* row_ptr, const int32_t* col, vo
        (rs.empty() || hip_ok(hipMemcpyAsync(g->rows_small, rs.data(), rs.size() * sizeof(int32_t), hipMemcpyHostToDevice, st), &msg, "copy rows")) &&
        (rm.empty() || hip_ok(hipMemcpyAsync(g->rows_mid, rm.data(), rm.size() * sizeof(int32_t), hipMemcpyHostToDevice, st), &msg, "copy rows")) &&
        (rb.empty() || hip_ok(hipMemcpyAsync(g->rows_big, rb.data(), rb.size() * sizeof(int32_t), hipMemcpyHostToDevice, st), &msg, "copy rows")) &&
-       hip_ok(hipMemsetAsync(g->ctrl, 0, kCtrlCount * sizeof(int32_t), st), &msg, "clear ctrl");
+       hip_ok(hipMemsetAsync(g->ctrl, 0, kCtrlInts * sizeof(int32_t), st), &msg, "clear ctrl") &&
+       hip_ok(hipMemsetAsync(g->qs, 0xFF, (size_t)kQsShards * std::max<int64_t>(g->L, 1) * sizeof(int32_t), st), &msg, "clear queues") &&
+       hip_ok(hipMemsetAsync(g->qb, 0xFF, (size_t)kQbShards * std::max<int64_t>(g->L, 1) * sizeof(int32_t), st), &msg, "clear queues");
   if (ok && (flags & CB_VALIDATE) && nnz > 0) {
     hipLaunchKernelGGL(k_validate, dim3((unsigned)((nnz + kScanChunk - 1) / kScanChunk)), dim3(256), 0, st,
                        n, nnz, g->rp, g->col, g->ctrl);
@@ -424,7 +429,7 @@ cb_status graph_upload(int64_t n, const int64_t* row_ptr, const int32_t* col, vo
   }
   if (ok) ok = hip_ok(hipStreamSynchronize(st), &msg, "upload sync");
   int32_t err = 0;
-  if (ok) ok = hip_ok(hipMemcpy(&err, g->ctrl + kCtrlErr, sizeof(int32_t), hipMemcpyDeviceToHost), &msg, "read error word");
+  if (ok) ok = hip_ok(hipMemcpy(&err, g->ctrl + cw(kCwErr), sizeof(int32_t), hipMemcpyDeviceToHost), &msg, "read error word");
   if (!ok) {
     release_all(g);
     delete g;
@@ -482,12 +487,13 @@ cb_status graph_download_state(cb_graph* g, int32_t which, void* host, int64_t c
     case CB_STATE_TRADE_OF: src = g->trade_of; avail = g->n; break;
     case CB_STATE_DEP: src = g->dep; avail = g->L; break;
     case CB_STATE_COL: src = g->col; avail = g->nnz; break;
+    case CB_STATE_OUT_CUR: src = g->out_cur; avail = g->n; break;
+    case CB_STATE_INBOX_CUR: src = g->inbox_cur; avail = g->n; break;
     default: return fail(CB_EINVAL, "unknown state id");
   }
   if (count > avail) return fail(CB_EINVAL, "count exceeds the state size");
-  cb_status s = sync_and_check(g);
-  if (s != CB_OK) return s;
   std::string msg;
+  if (!hip_ok(hipStreamSynchronize(g->stream), &msg, "hipStreamSynchronize")) return fail(CB_EDEVICE, msg);
   if (count > 0 && !hip_ok(hipMemcpy(host, src, (size_t)count * sizeof(int32_t), hipMemcpyDeviceToHost), &msg, "download state"))
     return fail(CB_EDEVICE, msg);
   return CB_OK;
@@ -497,7 +503,7 @@ cb_status graph_set_option(cb_graph* g, int32_t option, int64_t value) {
   if (!g) return fail(CB_EINVAL, "null graph");
   switch (option) {
     case CB_OPT_SMALL_MAX:
-      if (value < 0 || value > kSmallCap) return fail(CB_EINVAL, "small_max must be in [0, 256]");
+      if (value < 0 || value > kSmallCap) return fail(CB_EINVAL, "small_max must be in [0, 512]");
       g->small_max = (int32_t)value;
       return CB_OK;
     case CB_OPT_BIG_WORKERS:
@@ -514,6 +520,10 @@ cb_status graph_set_option(cb_graph* g, int32_t option, int64_t value) {
       return CB_OK;
     case CB_OPT_TIMING:
       g->timing = value != 0;
+      return CB_OK;
+    case CB_OPT_BIG_LDS_MAX:
+      if (value < 0 || value > kBigCap) return fail(CB_EINVAL, "big_lds_max must be in [0, 12288]");
+      g->big_lds_max = (int32_t)value;
       return CB_OK;
     case CB_OPT_LOCAL_STACK:
       if (value < 0 || value > kStackCap) return fail(CB_EINVAL, "local stack must be in [0, 16]");

@@ -9,19 +9,25 @@
 
 namespace cbx {
 
-// Slots of the per-graph control word array (int32, device memory).
-enum Ctrl : int {
-  kCtrlSrcCount = 0,   // trades with no dependency (written by k_sources)
-  kCtrlSrcHead,        // next source to hand out
-  kCtrlQsHead,         // small-trade ready queue
-  kCtrlQsTail,
-  kCtrlQbHead,         // large-trade ready queue
-  kCtrlQbTail,
-  kCtrlDone,           // completed trades (flushed by idle workers)
-  kCtrlErr,            // error bits (sticky across rounds)
-  kCtrlAbort,          // set with an error: every worker leaves
-  kCtrlCount = 16
+// Control words of one graph (int32, device memory), each on its own
+// 128-byte line so that polling and pushing do not share a cache line.
+constexpr int kCtrlStride = 32;
+constexpr int kQsShards = 16;   // ready queues of small trades
+constexpr int kQbShards = 4;    // ready queues of large trades
+enum CtrlWord : int {
+  kCwSrcCount = 0,   // trades with no dependency (written by k_sources)
+  kCwSrcHead,        // next source to hand out
+  kCwDone,           // completed trades (flushed by workers in batches)
+  kCwErr,            // error bits (sticky across rounds)
+  kCwAbort,          // set with an error: every worker leaves
+  kCwQsHead0,
+  kCwQsTail0 = kCwQsHead0 + kQsShards,
+  kCwQbHead0 = kCwQsTail0 + kQsShards,
+  kCwQbTail0 = kCwQbHead0 + kQbShards,
+  kCwCount = kCwQbTail0 + kQbShards
 };
+__host__ __device__ constexpr int cw(int word) { return word * kCtrlStride; }
+constexpr int kCtrlInts = kCwCount * kCtrlStride;
 
 // 64-bit round counters (device memory).
 enum Stat : int {
@@ -29,8 +35,9 @@ enum Stat : int {
   kStatCount = 8
 };
 
-constexpr int kSmallCap = 256;        // largest deg u + deg v on one wavefront
-constexpr int kTradeBlock = 256;      // threads per trade-kernel workgroup
+constexpr int kSmallCap = 512;        // largest deg u + deg v on one wavefront
+constexpr int kBigCap = 12288;        // largest deg u + deg v held in LDS by one workgroup
+constexpr int kTradeBlock = 1024;     // threads per trade-kernel workgroup
 constexpr int kWavesPerBlock = kTradeBlock / 64;
 constexpr int kStackCap = 16;         // ready trades a wavefront may keep
 constexpr int kMatchCap = 2048;       // bucket size sorted in LDS by k_match_sort
@@ -50,8 +57,8 @@ struct TradeArgs {
   int32_t* out_cur;
   int32_t* dep;
   const int32_t* src_list;
-  int32_t* qs;              // ready queue, small trades (L slots, -1 = empty)
-  int32_t* qb;              // ready queue, large trades
+  int32_t* qs;              // kQsShards ready queues of L slots (-1 = empty)
+  int32_t* qb;              // kQbShards ready queues of large trades
   int32_t* ctrl;
   unsigned long long* stats;
   uint64_t* slots;          // large-trade scratch, slot_elems u64 per workgroup
@@ -60,6 +67,7 @@ struct TradeArgs {
   int64_t n;
   int32_t L;
   int32_t small_max;
+  int32_t big_lds_max;
   int32_t nbig;
   int32_t stack_cap;
   int32_t keybits;          // bits of (node << 1 | side)
@@ -69,9 +77,9 @@ struct TradeArgs {
 };
 
 // ---- kernels ---------------------------------------------------------------
-__global__ void k_round_reset(int64_t n, int32_t L, int32_t nb, int32_t* inbox_cur,
-                              int32_t* out_cur, int32_t* bcount, int32_t* bcur, int32_t* qs,
-                              int32_t* qb, int32_t* ctrl, unsigned long long* stats);
+__global__ void k_round_reset(int64_t n, int32_t nb, int32_t* inbox_cur, int32_t* out_cur,
+                              int32_t* bcount, int32_t* bcur, int32_t* ctrl,
+                              unsigned long long* stats);
 __global__ void k_match_count(int64_t n, uint64_t seed, uint32_t round, int nb_log2,
                               int32_t* bcount, const int32_t* ctrl);
 __global__ void k_match_scan(int32_t nb, const int32_t* bcount, int32_t* bstart,

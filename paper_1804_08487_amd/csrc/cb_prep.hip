@@ -6,9 +6,9 @@
 
 namespace cbx {
 
-__global__ void k_round_reset(int64_t n, int32_t L, int32_t nb, int32_t* inbox_cur,
-                              int32_t* out_cur, int32_t* bcount, int32_t* bcur, int32_t* qs,
-                              int32_t* qb, int32_t* ctrl, unsigned long long* stats) {
+__global__ void k_round_reset(int64_t n, int32_t nb, int32_t* inbox_cur, int32_t* out_cur,
+                              int32_t* bcount, int32_t* bcur, int32_t* ctrl,
+                              unsigned long long* stats) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t i = t0; i < n; i += stride) {
@@ -19,11 +19,8 @@ __global__ void k_round_reset(int64_t n, int32_t L, int32_t nb, int32_t* inbox_c
     bcount[i] = 0;
     bcur[i] = 0;
   }
-  for (int64_t i = t0; i < L; i += stride) {
-    qs[i] = -1;
-    qb[i] = -1;
-  }
-  if (t0 < kCtrlCount && t0 != kCtrlErr && t0 != kCtrlAbort) ctrl[t0] = 0;
+  // Ready-queue slots need no reset: every pushed slot is cleared by its consumer.
+  if (t0 < kCwCount && t0 != kCwErr && t0 != kCwAbort) ctrl[cw((int)t0)] = 0;
   if (t0 < kStatCount) stats[t0] = 0;
 }
 
@@ -41,7 +38,7 @@ __device__ __forceinline__ uint32_t key_bucket(uint64_t key, int nb_log2) {
 
 __global__ void k_match_count(int64_t n, uint64_t seed, uint32_t round, int nb_log2,
                               int32_t* bcount, const int32_t* ctrl) {
-  if (ctrl[kCtrlErr]) return;
+  if (ctrl[cw(kCwErr)]) return;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
     atomicAdd(&bcount[key_bucket(node_key(seed, round, v), nb_log2)], 1);
@@ -51,7 +48,7 @@ __global__ void k_match_scan(int32_t nb, const int32_t* bcount, int32_t* bstart,
                              const int32_t* ctrl) {
   __shared__ int32_t scratch[17];
   __shared__ int32_t carry;
-  if (ctrl[kCtrlErr]) return;
+  if (ctrl[cw(kCwErr)]) return;
   if (threadIdx.x == 0) carry = 0;
   __syncthreads();
   for (int32_t base = 0; base < nb; base += blockDim.x) {
@@ -70,7 +67,7 @@ __global__ void k_match_scan(int32_t nb, const int32_t* bcount, int32_t* bstart,
 __global__ void k_match_scatter(int64_t n, uint64_t seed, uint32_t round, int nb_log2,
                                 const int32_t* bstart, int32_t* bcur, int32_t* mtmp,
                                 const int32_t* ctrl) {
-  if (ctrl[kCtrlErr]) return;
+  if (ctrl[cw(kCwErr)]) return;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
     const uint32_t b = key_bucket(node_key(seed, round, v), nb_log2);
@@ -99,7 +96,7 @@ k_match_sort(int64_t n, uint64_t seed, uint32_t round, int32_t nb, const int32_t
              int32_t* mtmp, uint64_t* mkey, int32_t* perm, int32_t* trade_of, int32_t* dep,
              int32_t* ctrl) {
   __shared__ KeyedNode buf[kMatchCap];
-  if (ctrl[kCtrlErr]) return;
+  if (ctrl[cw(kCwErr)]) return;
   for (int32_t b = blockIdx.x; b < nb; b += gridDim.x) {
     const int64_t s0 = bstart[b];
     const int64_t cnt = bstart[b + 1] - s0;
@@ -171,7 +168,7 @@ k_depscan(int64_t n, int64_t nnz, const int64_t* rp, const int32_t* col,
   __shared__ int64_t lrp[kScanChunk + 1];
   __shared__ int32_t cnt[kScanChunk];
   __shared__ int64_t bounds[2];
-  if (ctrl[kCtrlErr]) return;
+  if (ctrl[cw(kCwErr)]) return;
   const int64_t e0 = (int64_t)blockIdx.x * kScanChunk;
   if (e0 >= nnz) return;
   const int64_t e1 = e0 + kScanChunk < nnz ? e0 + kScanChunk : nnz;
@@ -215,7 +212,7 @@ k_depscan(int64_t n, int64_t nnz, const int64_t* rp, const int32_t* col,
 
 __global__ void k_sources(int32_t L, const int32_t* dep, int32_t* src_list, int32_t* ctrl,
                           unsigned long long* stats) {
-  if (ctrl[kCtrlErr]) return;
+  if (ctrl[cw(kCwErr)]) return;
   const int32_t stride = gridDim.x * blockDim.x;
   // trip count is uniform across a wavefront (ballot below)
   for (int32_t base = blockIdx.x * blockDim.x; base < L; base += stride) {
@@ -225,7 +222,7 @@ __global__ void k_sources(int32_t L, const int32_t* dep, int32_t* src_list, int3
     if (m == 0) continue;
     int32_t pos = 0;
     if (lane_id() == 0) {
-      pos = atomic_add(&ctrl[kCtrlSrcCount], popc64(m));
+      pos = atomic_add(&ctrl[cw(kCwSrcCount)], popc64(m));
       atomicAdd(&stats[kStatSources], (unsigned long long)popc64(m));
     }
     pos = wave_bcast(pos, 0);
@@ -234,10 +231,10 @@ __global__ void k_sources(int32_t L, const int32_t* dep, int32_t* src_list, int3
 }
 
 __global__ void k_check_rows(int64_t n, const int64_t* rp, const int32_t* out_cur, int32_t* ctrl) {
-  if (ctrl[kCtrlErr]) return;
+  if (ctrl[cw(kCwErr)]) return;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += stride)
-    if ((int64_t)out_cur[x] != rp[x + 1] - rp[x]) atomic_or(&ctrl[kCtrlErr], kErrRows);
+    if ((int64_t)out_cur[x] != rp[x + 1] - rp[x]) atomic_or(&ctrl[cw(kCwErr)], kErrRows);
 }
 
 // ---------------------------------------------------------------- rebuild
@@ -247,7 +244,7 @@ __global__ void k_check_rows(int64_t n, const int64_t* rp, const int32_t* out_cu
 __global__ void __launch_bounds__(256)
 k_segsort_small(const int32_t* rows, int64_t nrows, const int64_t* rp, const int32_t* src,
                 int32_t* dst, const int32_t* ctrl) {
-  if (ctrl[kCtrlErr]) return;
+  if (ctrl[cw(kCwErr)]) return;
   const int l = lane_id();
   const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -275,7 +272,7 @@ __global__ void __launch_bounds__(256)
 k_segsort_mid(const int32_t* rows, int64_t nrows, const int64_t* rp, const int32_t* src,
               int32_t* dst, const int32_t* ctrl) {
   __shared__ int32_t buf[kSegMidMax];
-  if (ctrl[kCtrlErr]) return;
+  if (ctrl[cw(kCwErr)]) return;
   for (int64_t r = blockIdx.x; r < nrows; r += gridDim.x) {
     const int32_t x = rows[r];
     const int64_t b = rp[x];
@@ -292,7 +289,7 @@ __global__ void __launch_bounds__(256)
 k_segsort_big(const int32_t* rows, int64_t nrows, const int64_t* rp, int32_t* src,
               int32_t* dst, int keybits, const int32_t* ctrl) {
   __shared__ RadixLds R;
-  if (ctrl[kCtrlErr]) return;
+  if (ctrl[cw(kCwErr)]) return;
   for (int64_t r = blockIdx.x; r < nrows; r += gridDim.x) {
     const int32_t x = rows[r];
     const int64_t b = rp[x];
@@ -331,7 +328,7 @@ k_validate(int64_t n, int64_t nnz, const int64_t* rp, const int32_t* col, int32_
     }
     if (lo >= rp[y + 1] || (int64_t)col[lo] != x) bad = true;
   }
-  if (bad) atomic_or(&ctrl[kCtrlErr], kErrInvalid);
+  if (bad) atomic_or(&ctrl[cw(kCwErr)], kErrInvalid);
 }
 
 }  // namespace cbx

@@ -23,8 +23,9 @@
 // trade").
 //
 // Workers: workgroups [0, nbig) run large trades with the whole workgroup
-// (global scratch, radix sort); every other workgroup holds four wavefronts
-// that each run small trades (deg u + deg v <= small_max) in LDS.
+// (in LDS up to kBigCap entries, else in a global scratch slot with a radix
+// sort); every other workgroup holds sixteen wavefronts that each run small
+// trades (deg u + deg v <= small_max) in LDS.
 #include "cb_block.hpp"
 #include "cb_kernels.hpp"
 
@@ -53,7 +54,13 @@ struct WaveLds {
 };
 
 struct BigLds {
-  RadixLds R;
+  union {
+    struct {
+      uint64_t E[kBigCap];
+      int32_t D[kBigCap];
+    } tile;          // trades that fit in LDS
+    RadixLds R;      // scratch of the global-memory sort for larger trades
+  } u;
   int32_t scan[kWavesPerBlock + 1];
   int32_t next;
   int32_t cnt[4];
@@ -67,8 +74,8 @@ union TradeLds {
 };
 
 __device__ __forceinline__ void raise_error(const TradeArgs& A, int32_t bits) {
-  atomic_or(&A.ctrl[kCtrlErr], bits);
-  store_agent(&A.ctrl[kCtrlAbort], 1);
+  atomic_or(&A.ctrl[cw(kCwErr)], bits);
+  store_agent(&A.ctrl[cw(kCwAbort)], 1);
 }
 
 // Split of the ascending disjoint set (indices into the entry array) in
@@ -91,35 +98,67 @@ __device__ __forceinline__ void split_serial(Idx* D, int64_t N, int64_t a, uint6
   }
 }
 
-// Pop one item of a ready queue (single thread). -1: empty or lost a race.
-__device__ int32_t queue_pop(const TradeArgs& A, int32_t* q, int head_slot, int tail_slot) {
-  int32_t* head = &A.ctrl[head_slot];
-  const int32_t h = load_agent(head);
-  const int32_t t = load_agent(&A.ctrl[tail_slot]);
-  if (h >= t) return -1;
-  if (!atomic_cas(head, h, h + 1)) return -1;
-  int32_t k;
-  // The pusher reserved slot h before filling it; the fill is imminent.
-  while ((k = load_agent(&q[h])) < 0) {
-    if (load_agent(&A.ctrl[kCtrlAbort])) return -1;
-    __builtin_amdgcn_s_sleep(1);
+// Ready queues: `shards` queues of L slots each; q[shard * L + pos]. A pusher
+// reserves a slot with its shard's tail counter and fills it; a popper takes
+// a slot with a compare-and-swap on the head, waits for the fill, and
+// resets the slot to -1 so the queues are clean for the next round.
+__device__ int32_t queue_pop(const TradeArgs& A, int32_t* q, int shards, int head0, int tail0,
+                             int start) {
+  for (int i = 0; i < shards; ++i) {
+    const int sh = (start + i) % shards;
+    int32_t* head = &A.ctrl[cw(head0 + sh)];
+    const int32_t h = load_agent(head);
+    if (h >= load_agent(&A.ctrl[cw(tail0 + sh)])) continue;
+    if (!atomic_cas(head, h, h + 1)) continue;
+    int32_t* slot = &q[(int64_t)sh * A.L + h];
+    int32_t k;
+    // The pusher reserved slot h before filling it; the fill is imminent.
+    while ((k = load_agent(slot)) < 0) {
+      if (load_agent(&A.ctrl[cw(kCwAbort)])) return -1;
+      __builtin_amdgcn_s_sleep(1);
+    }
+    store_agent(slot, -1);
+    return k;
   }
-  return k;
+  return -1;
 }
 
 // Hand a ready trade to other workers (single lane; caller fenced).
-__device__ __forceinline__ void queue_push(const TradeArgs& A, int32_t* q, int tail_slot, int32_t k) {
-  const int32_t pos = atomic_add(&A.ctrl[tail_slot], 1);
+__device__ __forceinline__ void queue_push(const TradeArgs& A, int32_t* q, int tail0, int shard,
+                                           int32_t k) {
+  const int32_t pos = atomic_add(&A.ctrl[cw(tail0 + shard)], 1);
   if (pos >= A.L) { raise_error(A, kErrCapacity); return; }
-  store_agent(&q[pos], k);
+  store_agent(&q[(int64_t)shard * A.L + pos], k);
 }
 
 __device__ __forceinline__ int32_t source_pop(const TradeArgs& A) {
-  if (load_agent(&A.ctrl[kCtrlSrcHead]) >= load_agent(&A.ctrl[kCtrlSrcCount])) return -1;
-  const int32_t h = atomic_add(&A.ctrl[kCtrlSrcHead], 1);
-  if (h < load_agent(&A.ctrl[kCtrlSrcCount])) return A.src_list[h];
-  return -1;
+  const int32_t count = load_agent(&A.ctrl[cw(kCwSrcCount)]);
+  if (load_agent(&A.ctrl[cw(kCwSrcHead)]) >= count) return -1;
+  const int32_t h = atomic_add(&A.ctrl[cw(kCwSrcHead)], 1);
+  return h < count ? A.src_list[h] : -1;
 }
+
+// Idle wait that grows with the time spent idle (fewer polls of the shared
+// control words while there is nothing to do).
+__device__ __forceinline__ void idle_backoff(int32_t level) {
+  for (int32_t i = 0; i < level; ++i) __builtin_amdgcn_s_sleep(32);
+}
+
+// Watchdog bookkeeping of an idle worker: true when no trade has completed
+// anywhere for longer than the limit.
+struct Watchdog {
+  int32_t last_done;
+  uint64_t since;
+  __device__ bool stalled(const TradeArgs& A, int32_t done) {
+    const uint64_t now = now_ticks();
+    if (since == 0 || done != last_done) {
+      last_done = done;
+      since = now;
+      return false;
+    }
+    return now - since > A.watchdog_ticks;
+  }
+};
 
 // Emit/forward one output edge {owner, x}. Returns true if it is forwarded.
 __device__ __forceinline__ void route_edge(const TradeArgs& A, int32_t owner, int32_t x,
@@ -141,6 +180,7 @@ __device__ __forceinline__ void route_edge(const TradeArgs& A, int32_t owner, in
 struct WaveState {
   int32_t top;        // local stack depth (uniform)
   int32_t ndone;
+  int32_t shard;      // home shard of the small-trade queues
   unsigned long long n_small, n_push, work, fwd, emit;
 };
 
@@ -165,7 +205,7 @@ __device__ __forceinline__ void wave_release_item(const TradeArgs& A, WaveLds& W
   if (spill) fence_acq_rel();
   if (ready) {
     if (r < room) W.stack[S.top + r] = t;
-    else queue_push(A, A.qs, kCtrlQsTail, t);
+    else queue_push(A, A.qs, kCwQsTail0, S.shard, t);
   }
   wave_sync();
   S.top += cnt < room ? cnt : (room > 0 ? room : 0);
@@ -310,7 +350,7 @@ __device__ void small_trade(const TradeArgs& A, int32_t k, int32_t u, int32_t v,
 
 __device__ void wave_flush(const TradeArgs& A, WaveState& S) {
   if (lane_id() == 0) {
-    if (S.ndone) atomic_add(&A.ctrl[kCtrlDone], S.ndone);
+    if (S.ndone) atomic_add(&A.ctrl[cw(kCwDone)], S.ndone);
     if (S.n_small) atomicAdd(&A.stats[kStatSmall], S.n_small);
     if (S.n_push) atomicAdd(&A.stats[kStatPush], S.n_push);
     if (S.work) atomicAdd(&A.stats[kStatWork], S.work);
@@ -321,10 +361,15 @@ __device__ void wave_flush(const TradeArgs& A, WaveState& S) {
   S.n_small = S.n_push = S.work = S.fwd = S.emit = 0;
 }
 
+constexpr int32_t kFlushEvery = 32;   // trades between progress flushes
+
 __device__ void small_worker(const TradeArgs& A, WaveLds& W) {
   const int l = lane_id();
+  const int32_t wid = (int32_t)(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6));
   WaveState S{};
-  uint64_t idle_since = 0;
+  S.shard = wid % kQsShards;
+  Watchdog wd{0, 0};
+  int32_t backoff = 1;
   for (;;) {
     int32_t k = -1;
     if (S.top > 0) {
@@ -333,7 +378,7 @@ __device__ void small_worker(const TradeArgs& A, WaveLds& W) {
     } else {
       if (l == 0) {
         k = source_pop(A);
-        if (k < 0) k = queue_pop(A, A.qs, kCtrlQsHead, kCtrlQsTail);
+        if (k < 0) k = queue_pop(A, A.qs, kQsShards, kCwQsHead0, kCwQsTail0, S.shard);
       }
       k = wave_bcast(k, 0);
     }
@@ -341,59 +386,87 @@ __device__ void small_worker(const TradeArgs& A, WaveLds& W) {
       wave_flush(A, S);
       int32_t stop = 0;
       if (l == 0) {
-        stop = load_agent(&A.ctrl[kCtrlAbort]) ||
-               load_agent(&A.ctrl[kCtrlDone]) >= A.L;
-        if (!stop) {
-          const uint64_t now = now_ticks();
-          if (idle_since == 0) idle_since = now;
-          else if (now - idle_since > A.watchdog_ticks) { raise_error(A, kErrWatchdog); stop = 1; }
-        }
+        const int32_t done = load_agent(&A.ctrl[cw(kCwDone)]);
+        stop = load_agent(&A.ctrl[cw(kCwAbort)]) || done >= A.L;
+        if (!stop && wd.stalled(A, done)) { raise_error(A, kErrWatchdog); stop = 1; }
       }
       if (wave_bcast(stop, 0)) break;
-      __builtin_amdgcn_s_sleep(2);
+      idle_backoff(backoff);
+      backoff = backoff < 16 ? backoff * 2 : 16;
       continue;
     }
-    idle_since = 0;
+    backoff = 1;
     const int32_t u = A.perm[2 * k], v = A.perm[2 * k + 1];
     const int64_t s = (A.rp[u + 1] - A.rp[u]) + (A.rp[v + 1] - A.rp[v]);
     if (s > A.small_max) {
       // large trade: hand it to a workgroup worker
       if (l == 0) {
         fence_acq_rel();
-        queue_push(A, A.qb, kCtrlQbTail, k);
+        queue_push(A, A.qb, kCwQbTail0, wid % kQbShards, k);
       }
       continue;
     }
     fence_acquire();
     small_trade(A, k, u, v, W, S);
     S.ndone += 1;
+    if (S.ndone >= kFlushEvery) wave_flush(A, S);
     int32_t ab = 0;
-    if (l == 0) ab = load_agent(&A.ctrl[kCtrlAbort]);
+    if (l == 0) ab = load_agent(&A.ctrl[cw(kCwAbort)]);
     if (wave_bcast(ab, 0)) break;
   }
   wave_flush(A, S);
 }
 
 // ============================================================ large trades
+// One workgroup per trade. Entries live in LDS when deg u + deg v <= kBigCap,
+// otherwise in this workgroup's global scratch slot (sorted by radix sort).
+
+// Output item o of a trade: o < s is entry o of the sorted list (used when it
+// is shared or the partner); o >= s is position o - s of the split disjoint
+// set. Returns false for entries that are not items.
+__device__ __forceinline__ bool trade_item(const uint64_t* E, const int32_t* D, int32_t s, int32_t a,
+                                           int32_t u, int32_t v, int32_t o, int32_t* owner,
+                                           int32_t* x, uint32_t* tag) {
+  uint64_t e;
+  if (o < s) {
+    e = E[o];
+    const int32_t nx = ent_node(e);
+    const bool isP = ent_tag(e) == kTagPartner;
+    const bool isC = !isP && ((o > 0 && ent_node(E[o - 1]) == nx) ||
+                              (o + 1 < s && ent_node(E[o + 1]) == nx));
+    if (!isP && !isC) return false;
+    *owner = ent_side(e) ? v : u;
+  } else {
+    const int32_t j = o - s;
+    e = E[D[j]];
+    *owner = j < a ? u : v;
+  }
+  *x = ent_node(e);
+  *tag = ent_tag(e);
+  return true;
+}
+
+constexpr int kBatch = 4;   // items per thread whose atomics are in flight together
 
 __device__ void big_trade(const TradeArgs& A, int32_t k, BigLds& B, uint64_t* slot,
                           unsigned long long* counters) {
   const int tid = threadIdx.x;
+  const int nt = blockDim.x;
   const int32_t u = A.perm[2 * k], v = A.perm[2 * k + 1];
   const int64_t bu = A.rp[u], bv = A.rp[v];
   const int32_t du = (int32_t)(A.rp[u + 1] - bu), dv = (int32_t)(A.rp[v + 1] - bv);
-  const int64_t s = (int64_t)du + dv;
-  if (s > A.smax) {
+  const int32_t s = du + dv;
+  if ((int64_t)s > A.smax) {
     if (tid == 0) raise_error(A, kErrCapacity);
     return;
   }
-  uint64_t* E0 = slot;
-  uint64_t* E1 = slot + A.smax;
-  int32_t* D = (int32_t*)(slot + 2 * A.smax);
+  const bool in_lds = s <= A.big_lds_max;
+  uint64_t* E = in_lds ? B.u.tile.E : slot;
+  int32_t* D = in_lds ? B.u.tile.D : (int32_t*)(slot + 2 * A.smax);
   const int32_t niu = load_agent(&A.inbox_cur[u]);
   const int32_t niv = load_agent(&A.inbox_cur[v]);
 
-  // ---- gather (order is irrelevant: the list is sorted next)
+  // ---- gather (any order: the list is sorted next)
   for (int side = 0; side < 2; ++side) {
     const int64_t b = side ? bv : bu;
     const int32_t d = side ? dv : du;
@@ -401,11 +474,11 @@ __device__ void big_trade(const TradeArgs& A, int32_t k, BigLds& B, uint64_t* sl
     const int32_t ni = side ? niv : niu;
     if (tid == 0) B.cnt[0] = 0;
     __syncthreads();
-    for (int32_t e = tid; e < d; e += blockDim.x) {
+    for (int32_t e = tid; e < d; e += nt) {
       const int32_t t = A.col_t[b + e];
       if (t >= k) {
         const int32_t p = atomicAdd(&B.cnt[0], 1);
-        E0[off + p] = make_entry(A.col[b + e], side, tag_of(t, k));
+        E[off + p] = make_entry(A.col[b + e], side, tag_of(t, k));
       }
     }
     __syncthreads();
@@ -415,120 +488,121 @@ __device__ void big_trade(const TradeArgs& A, int32_t k, BigLds& B, uint64_t* sl
       if (tid == 0) raise_error(A, kErrGather);
       return;
     }
-    for (int32_t j = tid; j < ni; j += blockDim.x)
-      E0[off + nf + j] = make_entry(A.inbox[b + j], side, kTagEmit);
+    for (int32_t j = tid; j < ni; j += nt) E[off + nf + j] = make_entry(A.inbox[b + j], side, kTagEmit);
   }
   __syncthreads();
-  uint64_t* E = block_radix_sort<uint64_t>(E0, E1, s, A.keybits, B.R);
+  if (in_lds) block_bitonic_sort(E, (uint32_t)s);
+  else E = block_radix_sort<uint64_t>(E, slot + A.smax, s, A.keybits, B.u.R);
+  __syncthreads();
 
-  // ---- classify and compact the disjoint set in ascending order
+  // ---- classify; compact the disjoint set (ascending); a = |A_u minus shared|
   int32_t nD = 0, a = 0;
-  for (int64_t c = 0; c < s; c += blockDim.x) {
-    const int64_t i = c + tid;
-    int32_t isD = 0, isU = 0;
+  for (int32_t c = 0; c < s; c += nt) {
+    const int32_t i = c + tid;
+    int32_t flags = 0;   // bit 0: disjoint, bit 16: disjoint and on u's side
     if (i < s) {
       const uint64_t e = E[i];
       const int32_t x = ent_node(e);
       const bool isP = ent_tag(e) == kTagPartner;
       const bool isC = !isP && ((i > 0 && ent_node(E[i - 1]) == x) ||
                                 (i + 1 < s && ent_node(E[i + 1]) == x));
-      isD = (!isP && !isC) ? 1 : 0;
-      isU = (isD && ent_side(e) == 0) ? 1 : 0;
+      if (!isP && !isC) flags = ent_side(e) == 0 ? 0x10001 : 1;
     }
     int32_t tot;
-    const int32_t pos = block_excl_scan(isD, B.scan, &tot);
-    if (isD) D[nD + pos] = (int32_t)i;
-    nD += tot;
-    int32_t totu;
-    (void)block_excl_scan(isU, B.scan, &totu);
-    a += totu;
+    const int32_t pre = block_excl_scan(flags, B.scan, &tot);
+    if (flags) D[nD + (pre & 0xFFFF)] = i;
+    nD += tot & 0xFFFF;
+    a += tot >> 16;
   }
   __syncthreads();
   if (tid == 0) split_serial<int32_t>(D, nD, a, A.seed, A.round, k);
   __syncthreads();
 
-  // ---- write
+  // ---- own-row slots: one reservation per owner for the whole trade
+  const int32_t items = s + nD;
+  int32_t own_u = 0, own_v = 0;   // own-row items of this thread
+  for (int32_t o = tid; o < items; o += nt) {
+    int32_t owner, x;
+    uint32_t tag;
+    if (trade_item(E, D, s, a, u, v, o, &owner, &x, &tag) && tag <= kTagPartner) {
+      if (owner == u) ++own_u; else ++own_v;
+    }
+  }
+  int32_t tot_u, tot_v;
+  const int32_t pre_u = block_excl_scan(own_u, B.scan, &tot_u);
+  const int32_t pre_v = block_excl_scan(own_v, B.scan, &tot_v);
+  if (tid == 0) {
+    B.base[0] = tot_u ? atomic_add(&A.out_cur[u], tot_u) : 0;
+    B.base[1] = tot_v ? atomic_add(&A.out_cur[v], tot_v) : 0;
+  }
+  __syncthreads();
+  int32_t pos_u = B.base[0] + pre_u;
+  int32_t pos_v = B.base[1] + pre_v;
+
+  // ---- write: own rows directly, other rows and inboxes by batched atomics
   int32_t nfwd = 0, nemit = 0;
-  for (int pass = 0; pass < 2; ++pass) {
-    const int64_t count = pass ? nD : s;
-    for (int64_t c = 0; c < count; c += blockDim.x) {
-      const int64_t o = c + tid;
-      bool valid = o < count;
-      int32_t owner = u, x = 0;
-      uint32_t tag = 0;
-      if (valid) {
-        if (pass == 0) {
-          const uint64_t e = E[o];
-          x = ent_node(e);
-          tag = ent_tag(e);
-          const bool isP = tag == kTagPartner;
-          const bool isC = !isP && ((o > 0 && ent_node(E[o - 1]) == x) ||
-                                    (o + 1 < s && ent_node(E[o + 1]) == x));
-          valid = isP || isC;
-          owner = ent_side(e) ? v : u;
-        } else {
-          const uint64_t e = E[D[o]];
-          x = ent_node(e);
-          tag = ent_tag(e);
-          owner = o < a ? u : v;
+  for (int32_t o0 = tid; o0 < items; o0 += nt * kBatch) {
+    int32_t tx[kBatch], towner[kBatch], tp[kBatch];
+    uint32_t ttag[kBatch];
+#pragma unroll
+    for (int r = 0; r < kBatch; ++r) {
+      const int32_t o = o0 + r * nt;
+      tx[r] = -1;
+      tp[r] = 0;
+      if (o < items && trade_item(E, D, s, a, u, v, o, &towner[r], &tx[r], &ttag[r])) {
+        if (ttag[r] <= kTagPartner) {
+          const bool ou = towner[r] == u;
+          const int32_t p = ou ? pos_u++ : pos_v++;
+          if (p < (ou ? du : dv)) A.col_out[(ou ? bu : bv) + p] = tx[r];
+          else raise_error(A, kErrOut);
         }
+        if (ttag[r] == kTagEmit) tp[r] = atomic_add(&A.out_cur[tx[r]], 1);
+        else if (ttag[r] >= 2u) tp[r] = atomic_add(&A.inbox_cur[tx[r]], 1);
+      } else {
+        tx[r] = -1;
       }
-      const bool own = valid && tag <= kTagPartner;
-      if (tid == 0) { B.cnt[1] = 0; B.cnt[2] = 0; }
-      __syncthreads();
-      int32_t slot_pos = -1;
-      if (own) slot_pos = atomicAdd(&B.cnt[owner == u ? 1 : 2], 1);
-      __syncthreads();
-      if (tid == 0) {
-        B.base[0] = B.cnt[1] ? atomic_add(&A.out_cur[u], B.cnt[1]) : 0;
-        B.base[1] = B.cnt[2] ? atomic_add(&A.out_cur[v], B.cnt[2]) : 0;
-      }
-      __syncthreads();
-      if (own) {
-        const int32_t p = B.base[owner == u ? 0 : 1] + slot_pos;
-        const int32_t dd = owner == u ? du : dv;
-        if (p < dd) A.col_out[(owner == u ? bu : bv) + p] = x; else raise_error(A, kErrOut);
-      }
-      if (valid) {
-        route_edge(A, owner, x, tag);
-        if (tag >= 2u) ++nfwd;
-        if (tag == kTagEmit) ++nemit;
-      }
+    }
+#pragma unroll
+    for (int r = 0; r < kBatch; ++r) {
+      if (tx[r] < 0 || ttag[r] == kTagPartner) continue;
+      const int64_t rx = A.rp[tx[r]];
+      const int32_t dx = (int32_t)(A.rp[tx[r] + 1] - rx);
+      if (tp[r] >= dx) { raise_error(A, ttag[r] == kTagEmit ? kErrOut : kErrInbox); continue; }
+      if (ttag[r] == kTagEmit) { A.col_out[rx + tp[r]] = towner[r]; ++nemit; }
+      else { A.inbox[rx + tp[r]] = towner[r]; ++nfwd; }
     }
   }
   __syncthreads();
   fence_release();
-  for (int pass = 0; pass < 2; ++pass) {
-    const int64_t count = pass ? nD : s;
-    for (int64_t o = tid; o < count; o += blockDim.x) {
+
+  // ---- unlock later trades
+  for (int32_t o0 = tid; o0 < items; o0 += nt * kBatch) {
+    int32_t tt[kBatch], old[kBatch];
+#pragma unroll
+    for (int r = 0; r < kBatch; ++r) {
+      const int32_t o = o0 + r * nt;
+      int32_t owner, x;
       uint32_t tag;
-      bool fwd;
-      if (pass == 0) {
-        const uint64_t e = E[o];
-        const int32_t x = ent_node(e);
-        tag = ent_tag(e);
-        const bool isC = tag != kTagPartner && ((o > 0 && ent_node(E[o - 1]) == x) ||
-                                                (o + 1 < s && ent_node(E[o + 1]) == x));
-        fwd = isC && tag >= 2u;
-      } else {
-        tag = ent_tag(E[D[o]]);
-        fwd = tag >= 2u;
+      tt[r] = -1;
+      if (o < items && trade_item(E, D, s, a, u, v, o, &owner, &x, &tag) && tag >= 2u) {
+        tt[r] = (int32_t)(tag - 2u);
+        old[r] = atomic_add(&A.dep[tt[r]], -1);
       }
-      if (fwd) {
-        const int32_t t = (int32_t)(tag - 2u);
-        const int32_t old = atomic_add(&A.dep[t], -1);
-        if (old <= 0) raise_error(A, kErrDep);
-        if (old == 1) {
-          fence_acq_rel();
-          queue_push(A, A.qs, kCtrlQsTail, t);
-          counters[2] += 1;
-        }
+    }
+#pragma unroll
+    for (int r = 0; r < kBatch; ++r) {
+      if (tt[r] < 0) continue;
+      if (old[r] <= 0) raise_error(A, kErrDep);
+      if (old[r] == 1) {
+        fence_acq_rel();
+        queue_push(A, A.qs, kCwQsTail0, (int)((blockIdx.x * 7 + tid) % kQsShards), tt[r]);
+        counters[2] += 1;
       }
     }
   }
   if (tid == 0) counters[0] += (unsigned long long)s;
-  counters[1] += (unsigned long long)(nfwd);
-  counters[3] += (unsigned long long)(nemit);
+  counters[1] += (unsigned long long)nfwd;
+  counters[3] += (unsigned long long)nemit;
   __syncthreads();
 }
 
@@ -538,29 +612,19 @@ __device__ void big_worker(const TradeArgs& A, BigLds& B) {
   // per-thread partial counters: work, forwarded, pushes, emitted
   unsigned long long counters[4] = {0, 0, 0, 0};
   unsigned long long n_big = 0;
-  uint64_t idle_since = 0;
-  if (tid == 0) B.ndone = 0;
-  __syncthreads();
+  Watchdog wd{0, 0};
+  int32_t backoff = 1;
   for (;;) {
     if (tid == 0) {
-      int32_t k = -1;
-      if (load_agent(&A.ctrl[kCtrlAbort])) {
+      int32_t k;
+      if (load_agent(&A.ctrl[cw(kCwAbort)])) {
         k = -2;
       } else {
-        k = queue_pop(A, A.qb, kCtrlQbHead, kCtrlQbTail);
-        if (k < 0) k = source_pop(A);
-        if (k < 0) k = queue_pop(A, A.qs, kCtrlQsHead, kCtrlQsTail);
+        k = queue_pop(A, A.qb, kQbShards, kCwQbHead0, kCwQbTail0, (int)(blockIdx.x % kQbShards));
         if (k < 0) {
-          if (B.ndone) { atomic_add(&A.ctrl[kCtrlDone], B.ndone); B.ndone = 0; }
-          if (load_agent(&A.ctrl[kCtrlDone]) >= A.L) {
-            k = -2;
-          } else {
-            const uint64_t now = now_ticks();
-            if (idle_since == 0) idle_since = now;
-            else if (now - idle_since > A.watchdog_ticks) { raise_error(A, kErrWatchdog); k = -2; }
-          }
-        } else {
-          idle_since = 0;
+          const int32_t done = load_agent(&A.ctrl[cw(kCwDone)]);
+          if (done >= A.L) k = -2;
+          else if (wd.stalled(A, done)) { raise_error(A, kErrWatchdog); k = -2; }
         }
       }
       B.next = k;
@@ -570,15 +634,19 @@ __device__ void big_worker(const TradeArgs& A, BigLds& B) {
     __syncthreads();
     if (k == -2) break;
     if (k < 0) {
-      __builtin_amdgcn_s_sleep(2);
+      idle_backoff(backoff);
+      backoff = backoff < 16 ? backoff * 2 : 16;
       continue;
     }
+    backoff = 1;
     fence_acquire();
     big_trade(A, k, B, slot, counters);
-    if (tid == 0) { B.ndone += 1; n_big += 1; }
+    if (tid == 0) {
+      atomic_add(&A.ctrl[cw(kCwDone)], 1);
+      n_big += 1;
+    }
   }
   __syncthreads();
-  if (tid == 0 && B.ndone) atomic_add(&A.ctrl[kCtrlDone], B.ndone);
   if (counters[0]) atomicAdd(&A.stats[kStatWork], counters[0]);
   if (counters[1]) atomicAdd(&A.stats[kStatForward], counters[1]);
   if (counters[2]) atomicAdd(&A.stats[kStatPush], counters[2]);
@@ -588,7 +656,7 @@ __device__ void big_worker(const TradeArgs& A, BigLds& B) {
 
 __global__ void __launch_bounds__(kTradeBlock) k_trade(TradeArgs A) {
   __shared__ TradeLds lds;
-  if (load_agent(&A.ctrl[kCtrlErr])) return;
+  if (load_agent(&A.ctrl[cw(kCwErr)])) return;
   if ((int32_t)blockIdx.x < A.nbig) {
     big_worker(A, lds.big);
   } else {

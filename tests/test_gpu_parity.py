@@ -45,6 +45,8 @@ def _small_graphs():
 
 SMALL = list(_small_graphs())
 TIERS = {"default": {}, "all_workgroup": {cb.OPT_SMALL_MAX: 0},
+         "all_global": {cb.OPT_SMALL_MAX: 0, cb.OPT_BIG_LDS_MAX: 0},
+         "mixed_global": {cb.OPT_SMALL_MAX: 64, cb.OPT_BIG_LDS_MAX: 200},
          "tiny_wave": {cb.OPT_SMALL_MAX: 8, cb.OPT_BIG_WORKERS: 1},
          "no_stack": {cb.OPT_LOCAL_STACK: 0}}
 
@@ -75,6 +77,28 @@ def test_small_graphs_bit_exact(orc, name, g, tier):
     _run_and_compare(orc, rp, col, seed=7, rounds=3, options=TIERS[tier])
 
 
+def _hub_graph():
+    """Node 0 adjacent to 35000 of 40000 nodes plus a sparse random graph, so
+    one trade per round has a side of more than 2^15 entries."""
+    rng = np.random.default_rng(77)
+    n = 40000
+    edges = {(0, int(i)) for i in rng.choice(np.arange(1, n), 35000, replace=False)}
+    for _ in range(60000):
+        x, y = sorted(int(t) for t in rng.integers(1, n, 2))
+        if x != y:
+            edges.add((x, y))
+    return graphgen.edge_list_to_csr(n, sorted(edges))
+
+
+@pytest.mark.parametrize("tier", ["default", "all_global", "all_workgroup"])
+def test_hub_above_2_15_entries(orc, tier):
+    """Regression: own-row counts of a side above 2^15 entries."""
+    _say(f"hub graph tier {tier}")
+    rp, col = _hub_graph()
+    assert np.diff(rp).max() >= 35000
+    _run_and_compare(orc, rp, col, seed=3, rounds=2, options=TIERS[tier])
+
+
 def test_matching_and_depscan_match_oracle(orc):
     for n_, seed, rnd in ((1, 3, 0), (2, 3, 1), (5, 4, 2), (8192, 1, 0), (8193, 2, 5), (100000, 9, 3)):
         _say(f"matching n={n_}")
@@ -95,7 +119,7 @@ def test_matching_and_depscan_match_oracle(orc):
 def test_small_workload_ten_rounds_every_round(orc):
     rp, col = graphgen.workload("small")
     _say(f"small workload n={len(rp)-1} m={len(col)//2}")
-    for tier in ("default", "all_workgroup"):
+    for tier in ("default", "all_workgroup", "mixed_global"):
         _run_and_compare(orc, rp, col, seed=1, rounds=10, options=TIERS[tier])
 
 
