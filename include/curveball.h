@@ -138,6 +138,12 @@ cb_status graph_download_state(cb_graph* g, int32_t which, void* host, int64_t c
 #define CB_OPT_BIG_LDS_MAX   7  /* workgroup trades with deg u + deg v <= this
                                    stay in LDS (0..12288); larger ones use a
                                    global scratch slot. Default 12288. */
+#define CB_OPT_DEBUG_CHECKS  9  /* 1: extra invariant checks between kernels */
+#define CB_OPT_GIANT_DEG     8  /* nodes of at least this degree keep the edges
+                                   handed to them in a bitmap over all node ids
+                                   (n/8 bytes each) instead of a list; 0 = none.
+                                   Default 6144, raised while the bitmaps would
+                                   exceed min(64 GiB, 40% of free memory). */
 
 cb_status graph_set_option(cb_graph* g, int32_t option, int64_t value);
 
@@ -151,6 +157,15 @@ typedef struct {
     int64_t work;            /* sum of deg u + deg v over trades */
     int64_t forwarded;       /* edges handed to a later trade */
     int64_t emitted;         /* final edges written (both directions counted once) */
+    int64_t small_workers;   /* wavefront workers of the trade kernel */
+    int64_t big_workers;     /* workgroup workers of the trade kernel */
+    double small_busy_us;    /* summed time wavefronts spent inside trades */
+    double big_busy_us;      /* summed time workgroups spent inside trades */
+    double big_gather_us;    /* ... collecting and sorting the two lists */
+    double big_split_us;     /* ... classifying and splitting */
+    double big_write_us;     /* ... writing final edges and forwarding */
+    double big_release_us;   /* ... unlocking later trades */
+    double big_max_us;       /* longest single workgroup trade */
 } cb_round_stats;
 
 cb_status graph_stats(cb_graph* g, cb_round_stats* out);

@@ -23,7 +23,7 @@ STATUS_NAMES = {0: "CB_OK", 1: "CB_EINVAL", 2: "CB_ENOTSIMPLE", 3: "CB_ENOMEM",
 CB_VALIDATE = 1
 STEP_MATCHING, STEP_DEPSCAN, STEP_TRADE, STEP_REBUILD = 1, 2, 3, 4
 STATE_PERM, STATE_TRADE_OF, STATE_DEP, STATE_COL, STATE_OUT_CUR, STATE_INBOX_CUR = 1, 2, 3, 4, 5, 6
-OPT_SMALL_MAX, OPT_BIG_WORKERS, OPT_GRID_BLOCKS, OPT_WATCHDOG_MS, OPT_TIMING, OPT_LOCAL_STACK, OPT_BIG_LDS_MAX = range(1, 8)
+OPT_SMALL_MAX, OPT_BIG_WORKERS, OPT_GRID_BLOCKS, OPT_WATCHDOG_MS, OPT_TIMING, OPT_LOCAL_STACK, OPT_BIG_LDS_MAX, OPT_GIANT_DEG, OPT_DEBUG_CHECKS = range(1, 10)
 UNMATCHED = 2**31 - 1
 
 # Every symbol declared in include/curveball.h.
@@ -47,10 +47,14 @@ class _Allocator(ctypes.Structure):
 class RoundStats(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in (
         "trades", "small_trades", "big_trades", "sources", "queue_pushes", "work",
-        "forwarded", "emitted")]
+        "forwarded", "emitted", "small_workers", "big_workers")] + [
+        (name, ctypes.c_double) for name in (
+            "small_busy_us", "big_busy_us", "big_gather_us", "big_split_us", "big_write_us",
+            "big_release_us", "big_max_us")]
 
     def as_dict(self):
-        return {name: int(getattr(self, name)) for name, _ in self._fields_}
+        return {name: (getattr(self, name) if isinstance(getattr(self, name), float)
+                       else int(getattr(self, name))) for name, _ in self._fields_}
 
 
 _lib = None

@@ -63,9 +63,30 @@ __device__ __forceinline__ int32_t load_agent(const int32_t* p) {
 __device__ __forceinline__ void store_agent(int32_t* p, int32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
-__device__ __forceinline__ void fence_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
-__device__ __forceinline__ void fence_acq_rel() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent"); }
+__device__ __forceinline__ int64_t load_agent64(const int64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long load_agent_u64(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Ordering between trades. Every datum one trade hands to another inside
+// the trade kernel (inbox entries, bitmap words, counters, queue slots) is
+// written and read with agent-scope atomic operations, which are coherent
+// across the XCDs' L2 caches (agent-scope stores and loads are issued with
+// sc1 and go to the coherence point; read-modify-write atomics are
+// performed there). So a producer only has to let its writes complete
+// before the counter update that publishes them, and a consumer's reads
+// depend on the value that handed it the work. Full agent-scope fences
+// (an L2 write-back plus an L2 invalidate around every trade) are not
+// needed for that data; data read by later kernels is ordered by the kernel
+// boundary.
+__device__ __forceinline__ void publish_wait() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+__device__ __forceinline__ void consume_order() { __atomic_signal_fence(__ATOMIC_SEQ_CST); }
 
 // ---- wavefront primitives -------------------------------------------------
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <functional>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -57,6 +58,14 @@ struct cb_graph {
   int32_t* out_cur = nullptr;
   int32_t* perm = nullptr;
   int32_t* trade_of = nullptr;
+  int32_t* tinfo = nullptr;
+  int32_t* giant_id = nullptr;
+  unsigned long long* gbm = nullptr;
+  int32_t* gsc = nullptr;
+  int32_t ngiant = 0;
+  int64_t giant_deg = 0;        // 0: no giant nodes
+  bool giant_dirty = false;     // a partial round left bitmap members behind
+  int64_t gwords = 0;
   int32_t* mtmp = nullptr;
   uint64_t* mkey = nullptr;
   int32_t* dep = nullptr;
@@ -92,6 +101,7 @@ struct cb_graph {
   int32_t stack_cap = 8;
   int64_t watchdog_ms = 20000;
   bool timing = false;
+  bool debug_checks = false;
 
   bool poisoned = false;
   std::string poison_msg;
@@ -192,11 +202,71 @@ cb_status sync_and_check(cb_graph* g) {
   }
   if (g->timing) collect_timing(g);
   if (err) {
+    int32_t dbg[3] = {0, 0, 0};
+    for (int i = 0; i < 3; ++i)
+      (void)hipMemcpy(&dbg[i], g->ctrl + cw(kCwDbgBits + i), sizeof(int32_t), hipMemcpyDeviceToHost);
     g->poisoned = true;
-    g->poison_msg = error_bits_text(err);
+    g->poison_msg = error_bits_text(err) + " (first: bits " + std::to_string(dbg[0]) + ", trade " +
+                    std::to_string(dbg[1] - 1) + ", detail " + std::to_string(dbg[2]) + ")";
     return fail((err & kErrWatchdog) ? CB_EWATCHDOG : CB_EDEVICE,
                 "device reported: " + g->poison_msg);
   }
+  return CB_OK;
+}
+
+GiantSets giant_sets(const cb_graph* g) {
+  GiantSets gs;
+  gs.giant_id = g->giant_id;
+  gs.bm = g->gbm;
+  gs.sc = g->gsc;
+  gs.gwords = g->gwords;
+  return gs;
+}
+
+// Give every node of degree >= deg (0: none) a bitmap neighbour set. Degrees
+// never change, so this is fixed until the next call. Bitmaps start empty
+// and are left empty by every completed round.
+cb_status setup_giants(cb_graph* g, int64_t deg, const int64_t* host_row_ptr) {
+  std::string msg;
+  if (!hip_ok(hipStreamSynchronize(g->stream), &msg, "sync")) return fail(CB_EDEVICE, msg);
+  auto drop = [&](void* p) {
+    if (!p) return;
+    for (auto it = g->owned.begin(); it != g->owned.end(); ++it)
+      if (*it == p) { g->owned.erase(it); break; }
+    if (g->alloc.free) g->alloc.free(p, g->alloc.user); else (void)hipFree(p);
+  };
+  drop(g->gbm);
+  drop(g->gsc);
+  g->gbm = nullptr;
+  g->gsc = nullptr;
+  std::vector<int32_t> gid((size_t)std::max<int64_t>(g->n, 1), -1);
+  int32_t ng = 0;
+  if (deg > 0 && host_row_ptr)
+    for (int64_t x = 0; x < g->n; ++x)
+      if (host_row_ptr[x + 1] - host_row_ptr[x] >= deg) gid[x] = ng++;
+  g->ngiant = ng;
+  g->giant_deg = ng ? deg : 0;
+  g->gwords = ((g->n + 4095) / 4096) * 64;
+  if (!hip_ok(hipMemcpyAsync(g->giant_id, gid.data(), gid.size() * sizeof(int32_t), hipMemcpyHostToDevice, g->stream), &msg, "copy giant ids") ||
+      !hip_ok(hipStreamSynchronize(g->stream), &msg, "sync"))
+    return fail(CB_EDEVICE, msg);
+  if (ng == 0) return CB_OK;
+  if (!alloc_into(g, &g->gbm, (int64_t)ng * g->gwords) || !alloc_into(g, &g->gsc, (int64_t)ng * (g->gwords >> 6))) {
+    drop(g->gbm);
+    g->gbm = nullptr;
+    g->ngiant = 0;
+    g->giant_deg = 0;
+    std::vector<int32_t> none(gid.size(), -1);
+    (void)hipMemcpyAsync(g->giant_id, none.data(), none.size() * sizeof(int32_t), hipMemcpyHostToDevice, g->stream);
+    (void)hipStreamSynchronize(g->stream);
+    return fail(CB_ENOMEM, "no device memory for giant bitmaps");
+  }
+  // cleared on the graph's own stream (a non-blocking stream is not ordered
+  // after work on the null stream)
+  if (!hip_ok(hipMemsetAsync(g->gbm, 0, (size_t)ng * g->gwords * 8, g->stream), &msg, "clear bitmaps") ||
+      !hip_ok(hipMemsetAsync(g->gsc, 0, (size_t)ng * (g->gwords >> 6) * 4, g->stream), &msg, "clear counts") ||
+      !hip_ok(hipStreamSynchronize(g->stream), &msg, "sync"))
+    return fail(CB_EDEVICE, msg);
   return CB_OK;
 }
 
@@ -231,6 +301,14 @@ cb_status enqueue_round(cb_graph* g, uint64_t seed, uint32_t round, int last_ste
   }
   const int64_t n = g->n;
   const int32_t L = g->L;
+  if (g->giant_dirty) {
+    std::string msg;
+    if (!hip_ok(hipMemsetAsync(g->gbm, 0, (size_t)g->ngiant * g->gwords * 8, st), &msg, "clear bitmaps") ||
+        !hip_ok(hipMemsetAsync(g->gsc, 0, (size_t)g->ngiant * (g->gwords >> 6) * 4, st), &msg, "clear counts"))
+      return fail(CB_EDEVICE, msg);
+    g->giant_dirty = false;
+  }
+  if (last_step < CB_STEP_TRADE && g->ngiant > 0) g->giant_dirty = true;
 
   hipLaunchKernelGGL(k_round_reset, dim3(grid_for(std::max<int64_t>({n, (int64_t)g->nb, (int64_t)kCwCount}), 256, 8192)),
                      dim3(256), 0, st, n, g->nb, g->inbox_cur, g->out_cur, g->bcount, g->bcur,
@@ -243,13 +321,17 @@ cb_status enqueue_round(cb_graph* g, uint64_t seed, uint32_t round, int last_ste
                      round, g->nb_log2, g->bstart, g->bcur, g->mtmp, g->ctrl);
   hipLaunchKernelGGL(k_match_sort, dim3(std::min<int32_t>(g->nb, 1 << 20)), dim3(kMatchBlock), 0, st,
                      n, seed, round, g->nb, g->bstart, g->mtmp, g->mkey, g->perm, g->trade_of,
-                     g->dep, g->ctrl);
+                     g->tinfo, g->giant_id, g->dep, g->ctrl);
   if (timed) (void)hipEventRecord(evs.ev[1], st);
+  if (g->debug_checks && g->ngiant > 0)
+    hipLaunchKernelGGL(k_check_giants_empty, dim3(1024), dim3(256), 0, st,
+                       (int64_t)g->ngiant * (g->gwords >> 6), g->gsc, g->ctrl);
   if (last_step >= CB_STEP_DEPSCAN) {
     // 2. dependency scan + sources
     if (g->nnz > 0)
       hipLaunchKernelGGL(k_depscan, dim3((unsigned)((g->nnz + kScanChunk - 1) / kScanChunk)), dim3(256),
-                         0, st, n, g->nnz, g->rp, g->col, g->trade_of, g->col_t, g->dep, g->ctrl);
+                         0, st, n, g->nnz, g->rp, g->col, g->trade_of, g->tinfo, g->col_t, g->dep,
+                         giant_sets(g), g->ctrl);
     if (L > 0)
       hipLaunchKernelGGL(k_sources, dim3(grid_for(L, 256, 8192)), dim3(256), 0, st, L, g->dep,
                          g->src_list, g->ctrl, g->stats);
@@ -261,6 +343,8 @@ cb_status enqueue_round(cb_graph* g, uint64_t seed, uint32_t round, int last_ste
     A.rp = g->rp;
     A.col = g->col;
     A.col_t = g->col_t;
+    A.tinfo = g->tinfo;
+    A.gs = giant_sets(g);
     A.perm = g->perm;
     A.inbox = g->inbox;
     A.inbox_cur = g->inbox_cur;
@@ -277,7 +361,7 @@ cb_status enqueue_round(cb_graph* g, uint64_t seed, uint32_t round, int last_ste
     A.smax = g->smax;
     A.n = n;
     A.L = L;
-    A.small_max = g->small_max;
+    A.small_max = g->giant_deg > 0 ? std::min<int64_t>(g->small_max, g->giant_deg - 1) : g->small_max;
     A.big_lds_max = g->big_lds_max;
     A.nbig = effective_nbig(g);
     A.stack_cap = g->stack_cap;
@@ -399,7 +483,8 @@ cb_status graph_upload(int64_t n, const int64_t* row_ptr, const int32_t* col, vo
             alloc_into(g, &g->col_t, nnz) && alloc_into(g, &g->col_out, nnz) &&
             alloc_into(g, &g->inbox, nnz) && alloc_into(g, &g->inbox_cur, n) &&
             alloc_into(g, &g->out_cur, n) && alloc_into(g, &g->perm, n) &&
-            alloc_into(g, &g->trade_of, n) && alloc_into(g, &g->mtmp, n) &&
+            alloc_into(g, &g->trade_of, n) && alloc_into(g, &g->tinfo, n) &&
+            alloc_into(g, &g->giant_id, n) && alloc_into(g, &g->mtmp, n) &&
             alloc_into(g, &g->mkey, n) && alloc_into(g, &g->dep, g->L) &&
             alloc_into(g, &g->src_list, g->L) && alloc_into(g, &g->qs, (int64_t)kQsShards * std::max<int64_t>(g->L, 1)) &&
             alloc_into(g, &g->qb, (int64_t)kQbShards * std::max<int64_t>(g->L, 1)) && alloc_into(g, &g->bcount, g->nb) &&
@@ -439,6 +524,31 @@ cb_status graph_upload(int64_t n, const int64_t* row_ptr, const int32_t* col, vo
     release_all(g);
     delete g;
     return fail(CB_ENOTSIMPLE, "upload validation: " + error_bits_text(err));
+  }
+  // giant nodes: the default threshold keeps every other pair within one
+  // workgroup's LDS; it rises if the bitmaps would take too much memory
+  {
+    size_t free_b = 0, total_b = 0;
+    (void)hipMemGetInfo(&free_b, &total_b);
+    const double budget = std::min(64.0 * (1ull << 30), 0.4 * (double)free_b);
+    const int64_t gwords = ((n + 4095) / 4096) * 64;
+    const double per_giant = (double)gwords * 8.0 + (double)(gwords >> 6) * 4.0;
+    std::vector<int64_t> degs;
+    for (int64_t x = 0; x < n; ++x) {
+      const int64_t d = row_ptr[x + 1] - row_ptr[x];
+      if (d >= kGiantMinDeg) degs.push_back(d);
+    }
+    std::sort(degs.begin(), degs.end(), std::greater<int64_t>());
+    const int64_t fit = (int64_t)(budget / per_giant);
+    int64_t thr = kGiantMinDeg;
+    if ((int64_t)degs.size() > fit) thr = fit > 0 ? degs[(size_t)fit - 1] + 1 : INT64_MAX;
+    if (thr == INT64_MAX || degs.empty()) thr = 0;
+    cb_status gs = setup_giants(g, thr, row_ptr);
+    if (gs != CB_OK) {
+      release_all(g);
+      delete g;
+      return gs;
+    }
   }
   *out = g;
   return CB_OK;
@@ -521,10 +631,22 @@ cb_status graph_set_option(cb_graph* g, int32_t option, int64_t value) {
     case CB_OPT_TIMING:
       g->timing = value != 0;
       return CB_OK;
+    case CB_OPT_DEBUG_CHECKS:
+      g->debug_checks = value != 0;
+      return CB_OK;
     case CB_OPT_BIG_LDS_MAX:
       if (value < 0 || value > kBigCap) return fail(CB_EINVAL, "big_lds_max must be in [0, 12288]");
       g->big_lds_max = (int32_t)value;
       return CB_OK;
+    case CB_OPT_GIANT_DEG: {
+      if (value < 0) return fail(CB_EINVAL, "giant degree must be >= 0");
+      std::vector<int64_t> rp((size_t)g->n + 1);
+      std::string msg;
+      if (!hip_ok(hipStreamSynchronize(g->stream), &msg, "sync") ||
+          !hip_ok(hipMemcpy(rp.data(), g->rp, rp.size() * sizeof(int64_t), hipMemcpyDeviceToHost), &msg, "read row_ptr"))
+        return fail(CB_EDEVICE, msg);
+      return setup_giants(g, value, rp.data());
+    }
     case CB_OPT_LOCAL_STACK:
       if (value < 0 || value > kStackCap) return fail(CB_EINVAL, "local stack must be in [0, 16]");
       g->stack_cap = (int32_t)value;
@@ -550,6 +672,16 @@ cb_status graph_stats(cb_graph* g, cb_round_stats* out) {
   out->work = (int64_t)st[kStatWork];
   out->forwarded = (int64_t)st[kStatForward];
   out->emitted = (int64_t)st[kStatEmit];
+  const double us = 1000.0 / (double)g->ticks_per_ms;
+  out->small_busy_us = (double)st[kStatSmallTicks] * us;
+  out->big_busy_us = (double)st[kStatBigTicks] * us;
+  out->big_gather_us = (double)st[kStatBigGather] * us;
+  out->big_split_us = (double)st[kStatBigSplit] * us;
+  out->big_write_us = (double)st[kStatBigWrite] * us;
+  out->big_release_us = (double)st[kStatBigRelease] * us;
+  out->big_max_us = (double)st[kStatBigMaxTicks] * us;
+  out->small_workers = (int64_t)(trade_grid(g) - effective_nbig(g)) * kWavesPerBlock;
+  out->big_workers = effective_nbig(g);
   return CB_OK;
 }
 

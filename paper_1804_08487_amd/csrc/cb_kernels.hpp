@@ -20,6 +20,9 @@ enum CtrlWord : int {
   kCwDone,           // completed trades (flushed by workers in batches)
   kCwErr,            // error bits (sticky across rounds)
   kCwAbort,          // set with an error: every worker leaves
+  kCwDbgBits,        // error bits of the first recorded error
+  kCwDbgA,           // first recorded error: trade (+1)
+  kCwDbgB,           // first recorded error: detail
   kCwQsHead0,
   kCwQsTail0 = kCwQsHead0 + kQsShards,
   kCwQbHead0 = kCwQsTail0 + kQsShards,
@@ -32,11 +35,19 @@ constexpr int kCtrlInts = kCwCount * kCtrlStride;
 // 64-bit round counters (device memory).
 enum Stat : int {
   kStatSmall = 0, kStatBig, kStatPush, kStatWork, kStatForward, kStatEmit, kStatSources,
-  kStatCount = 8
+  kStatSmallTicks,   // wall-clock ticks inside small trades (all wavefronts)
+  kStatBigTicks,     // wall-clock ticks inside large trades (all workgroups)
+  kStatBigGather,    // ... of which collecting and sorting the lists
+  kStatBigSplit,     // ... classification and split
+  kStatBigWrite,     // ... writing and forwarding
+  kStatBigRelease,   // ... unlocking later trades
+  kStatBigMaxTicks,  // longest single large trade
+  kStatCount = 16
 };
 
 constexpr int kSmallCap = 512;        // largest deg u + deg v on one wavefront
 constexpr int kBigCap = 12288;        // largest deg u + deg v held in LDS by one workgroup
+constexpr int kGiantMinDeg = kBigCap / 2;   // default giant degree: any other pair fits LDS
 constexpr int kTradeBlock = 1024;     // threads per trade-kernel workgroup
 constexpr int kWavesPerBlock = kTradeBlock / 64;
 constexpr int kStackCap = 16;         // ready trades a wavefront may keep
@@ -46,10 +57,34 @@ constexpr int kScanChunk = 2048;      // CSR entries per workgroup in k_depscan/
 constexpr int kSegMidMax = 4096;      // rows sorted in LDS by one workgroup
 constexpr int kSegSmallMax = 64;      // rows sorted in registers by one wavefront
 
+// Trade information of a node as stored per CSR entry (col_t) and per node
+// (tinfo): its trade index, with bit 30 set when the node keeps its arrivals
+// in a bitmap (a "giant" node); kUnmatched for the node left out.
+constexpr int32_t kGiantBit = 0x40000000;
+__host__ __device__ constexpr bool tinfo_giant(int32_t ti) { return ti != kUnmatched && (ti & kGiantBit); }
+__host__ __device__ constexpr int32_t tinfo_trade(int32_t ti) { return ti == kUnmatched ? ti : (ti & ~kGiantBit); }
+
+// Bitmap neighbour sets of giant nodes: per giant, words of 64 bits over all
+// node ids (gwords per giant, a multiple of 64) and one count per superblock
+// of 64 words (4096 ids).
+struct GiantSets {
+  const int32_t* giant_id;  // index among giant nodes, or -1
+  unsigned long long* bm;   // ngiant * gwords
+  int32_t* sc;              // ngiant * (gwords / 64)
+  int64_t gwords;
+};
+
+// Add node y to giant gi's bitmap set.
+__device__ __forceinline__ void giant_insert(const GiantSets& gs, int32_t gi, int32_t y) {
+  atomicOr(&gs.bm[(int64_t)gi * gs.gwords + (y >> 6)], 1ull << (y & 63));
+  atomicAdd(&gs.sc[(int64_t)gi * (gs.gwords >> 6) + (y >> 12)], 1);
+}
+
 struct TradeArgs {
   const int64_t* rp;
   const int32_t* col;
-  const int32_t* col_t;     // trade index of every neighbour, from k_depscan
+  const int32_t* col_t;     // trade information of every neighbour, from k_depscan
+  const int32_t* tinfo;     // trade information per node
   const int32_t* perm;
   int32_t* inbox;           // CSR-shaped: arrivals for each node's row
   int32_t* inbox_cur;
@@ -61,6 +96,7 @@ struct TradeArgs {
   int32_t* qb;              // kQbShards ready queues of large trades
   int32_t* ctrl;
   unsigned long long* stats;
+  GiantSets gs;
   uint64_t* slots;          // large-trade scratch, slot_elems u64 per workgroup
   int64_t slot_elems;       // = 2 * smax + smax / 2 + 1
   int64_t smax;             // largest possible deg u + deg v
@@ -89,13 +125,15 @@ __global__ void k_match_scatter(int64_t n, uint64_t seed, uint32_t round, int nb
                                 const int32_t* ctrl);
 __global__ void k_match_sort(int64_t n, uint64_t seed, uint32_t round, int32_t nb,
                              const int32_t* bstart, int32_t* mtmp, uint64_t* mkey,
-                             int32_t* perm, int32_t* trade_of, int32_t* dep, int32_t* ctrl);
+                             int32_t* perm, int32_t* trade_of, int32_t* tinfo,
+                             const int32_t* giant_id, int32_t* dep, int32_t* ctrl);
 __global__ void k_depscan(int64_t n, int64_t nnz, const int64_t* rp, const int32_t* col,
-                          const int32_t* trade_of, int32_t* col_t, int32_t* dep,
-                          const int32_t* ctrl);
+                          const int32_t* trade_of, const int32_t* tinfo, int32_t* col_t,
+                          int32_t* dep, GiantSets gs, const int32_t* ctrl);
 __global__ void k_sources(int32_t L, const int32_t* dep, int32_t* src_list, int32_t* ctrl,
                           unsigned long long* stats);
 __global__ void k_trade(TradeArgs A);
+__global__ void k_check_giants_empty(int64_t total_sb, const int32_t* sc, int32_t* ctrl);
 __global__ void k_check_rows(int64_t n, const int64_t* rp, const int32_t* out_cur,
                              int32_t* ctrl);
 __global__ void k_segsort_small(const int32_t* rows, int64_t nrows, const int64_t* rp,

@@ -20,7 +20,9 @@ __global__ void k_round_reset(int64_t n, int32_t nb, int32_t* inbox_cur, int32_t
     bcur[i] = 0;
   }
   // Ready-queue slots need no reset: every pushed slot is cleared by its consumer.
-  if (t0 < kCwCount && t0 != kCwErr && t0 != kCwAbort) ctrl[cw((int)t0)] = 0;
+  if (t0 < kCwCount && t0 != kCwErr && t0 != kCwAbort && t0 != kCwDbgBits && t0 != kCwDbgA &&
+      t0 != kCwDbgB)
+    ctrl[cw((int)t0)] = 0;
   if (t0 < kStatCount) stats[t0] = 0;
 }
 
@@ -84,17 +86,20 @@ struct KeyedNode {
 };
 
 __device__ __forceinline__ void write_pair_slot(int64_t n, int64_t p, int32_t id, int32_t* perm,
-                                                int32_t* trade_of, int32_t* dep) {
+                                                int32_t* trade_of, int32_t* tinfo,
+                                                const int32_t* giant_id, int32_t* dep) {
   perm[p] = id;
   const bool left_out = (n & 1) && p == n - 1;
-  trade_of[id] = left_out ? kUnmatched : (int32_t)(p >> 1);
+  const int32_t t = left_out ? kUnmatched : (int32_t)(p >> 1);
+  trade_of[id] = t;
+  tinfo[id] = (!left_out && giant_id[id] >= 0) ? (t | kGiantBit) : t;
   if (!(p & 1) && p + 1 < n) dep[p >> 1] = 0;
 }
 
 __global__ void __launch_bounds__(kMatchBlock)
 k_match_sort(int64_t n, uint64_t seed, uint32_t round, int32_t nb, const int32_t* bstart,
-             int32_t* mtmp, uint64_t* mkey, int32_t* perm, int32_t* trade_of, int32_t* dep,
-             int32_t* ctrl) {
+             int32_t* mtmp, uint64_t* mkey, int32_t* perm, int32_t* trade_of, int32_t* tinfo,
+             const int32_t* giant_id, int32_t* dep, int32_t* ctrl) {
   __shared__ KeyedNode buf[kMatchCap];
   if (ctrl[cw(kCwErr)]) return;
   for (int32_t b = blockIdx.x; b < nb; b += gridDim.x) {
@@ -109,7 +114,7 @@ k_match_sort(int64_t n, uint64_t seed, uint32_t round, int32_t nb, const int32_t
       __syncthreads();
       block_bitonic_sort(buf, (uint32_t)cnt);
       for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x)
-        write_pair_slot(n, s0 + i, (int32_t)buf[i].id, perm, trade_of, dep);
+        write_pair_slot(n, s0 + i, (int32_t)buf[i].id, perm, trade_of, tinfo, giant_id, dep);
       __syncthreads();
     } else {
       // A bucket this large has probability far below 2^-500 for hashed
@@ -142,7 +147,7 @@ k_match_sort(int64_t n, uint64_t seed, uint32_t round, int32_t nb, const int32_t
         }
       }
       for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x)
-        write_pair_slot(n, s0 + i, ids[i], perm, trade_of, dep);
+        write_pair_slot(n, s0 + i, ids[i], perm, trade_of, tinfo, giant_id, dep);
       __syncthreads();
     }
   }
@@ -150,8 +155,10 @@ k_match_sort(int64_t n, uint64_t seed, uint32_t round, int32_t nb, const int32_t
 
 // ---------------------------------------------------------------- dep scan
 // dep[k] += number of neighbours y of the nodes of trade k with
-// trade_of[y] < k; col_t[e] = trade_of[col[e]] for every entry. Work is
-// split into equal chunks of CSR entries so hub rows do not serialise.
+// trade_of[y] < k; col_t[e] = tinfo[col[e]] for every entry. Rows of giant
+// nodes also put their neighbours of later trades (and the partner, and the
+// node left out) into the node's bitmap. Work is split into equal chunks of
+// CSR entries so hub rows do not serialise.
 
 __device__ __forceinline__ int64_t row_of_entry(const int64_t* rp, int64_t lo, int64_t hi, int64_t e) {
   // largest r in [lo, hi] with rp[r] <= e
@@ -164,7 +171,8 @@ __device__ __forceinline__ int64_t row_of_entry(const int64_t* rp, int64_t lo, i
 
 __global__ void __launch_bounds__(256)
 k_depscan(int64_t n, int64_t nnz, const int64_t* rp, const int32_t* col,
-          const int32_t* trade_of, int32_t* col_t, int32_t* dep, const int32_t* ctrl) {
+          const int32_t* trade_of, const int32_t* tinfo, int32_t* col_t, int32_t* dep,
+          GiantSets gs, const int32_t* ctrl) {
   __shared__ int64_t lrp[kScanChunk + 1];
   __shared__ int32_t cnt[kScanChunk];
   __shared__ int64_t bounds[2];
@@ -195,12 +203,18 @@ k_depscan(int64_t n, int64_t nnz, const int64_t* rp, const int32_t* col,
     } else {
       x = row_of_entry(rp, r0, r1, e);
     }
-    const int32_t t = trade_of[col[e]];
-    col_t[e] = t;
+    const int32_t y = col[e];
+    const int32_t ti = tinfo[y];
+    col_t[e] = ti;
+    const int32_t t = tinfo_trade(ti);
     const int32_t k = trade_of[x];
-    if (k != kUnmatched && t < k) {
+    if (k == kUnmatched) continue;
+    if (t < k) {
       if (local) atomicAdd(&cnt[x - r0], 1);
       else atomicAdd(&dep[k], 1);
+    } else {
+      const int32_t gi = gs.giant_id[x];
+      if (gi >= 0) giant_insert(gs, gi, y);
     }
   }
   __syncthreads();
@@ -208,6 +222,19 @@ k_depscan(int64_t n, int64_t nnz, const int64_t* rp, const int32_t* col,
     for (int64_t i = threadIdx.x; i < nrows; i += blockDim.x)
       if (cnt[i]) atomicAdd(&dep[trade_of[r0 + i]], cnt[i]);
   }
+}
+
+// Debug check: every giant bitmap is empty before the dependency scan.
+__global__ void k_check_giants_empty(int64_t total_sb, const int32_t* sc, int32_t* ctrl) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total_sb; i += stride)
+    if (sc[i] != 0) {
+      if (atomic_cas(&ctrl[cw(kCwDbgBits)], 0, kErrMatch)) {
+        store_agent(&ctrl[cw(kCwDbgA)], (int32_t)i + 1);
+        store_agent(&ctrl[cw(kCwDbgB)], sc[i]);
+      }
+      atomic_or(&ctrl[cw(kCwErr)], kErrMatch);
+    }
 }
 
 __global__ void k_sources(int32_t L, const int32_t* dep, int32_t* src_list, int32_t* ctrl,

@@ -33,9 +33,11 @@ namespace cbx {
 
 // Entry = ((node << 1 | side) << 32) | tag; side 0 = u's list, 1 = v's.
 // tag 0: final when emitted (earlier node or the node left out),
-// tag 1: the partner, tag t + 2: node of the later trade t.
+// tag 1: the partner, tag t + 2: node of the later trade t, with bit 31 set
+// when that node keeps its arrivals in a bitmap.
 constexpr uint32_t kTagEmit = 0u;
 constexpr uint32_t kTagPartner = 1u;
+constexpr uint32_t kTagGiant = 0x80000000u;
 
 __device__ __forceinline__ uint64_t make_entry(int32_t x, int side, uint32_t tag) {
   return ((uint64_t)(((uint32_t)x << 1) | (uint32_t)side) << 32) | tag;
@@ -43,9 +45,14 @@ __device__ __forceinline__ uint64_t make_entry(int32_t x, int side, uint32_t tag
 __device__ __forceinline__ int32_t ent_node(uint64_t e) { return (int32_t)(e >> 33); }
 __device__ __forceinline__ int ent_side(uint64_t e) { return (int)((e >> 32) & 1u); }
 __device__ __forceinline__ uint32_t ent_tag(uint64_t e) { return (uint32_t)e; }
-__device__ __forceinline__ uint32_t tag_of(int32_t t, int32_t k) {
-  return t == k ? kTagPartner : (t == kUnmatched ? kTagEmit : (uint32_t)t + 2u);
+// Tag of neighbour information ti (a tinfo value) seen from trade k.
+__device__ __forceinline__ uint32_t tag_of(int32_t ti, int32_t k) {
+  const int32_t t = tinfo_trade(ti);
+  if (t == k) return kTagPartner;
+  if (t == kUnmatched || t < k) return kTagEmit;
+  return ((uint32_t)t + 2u) | (tinfo_giant(ti) ? kTagGiant : 0u);
 }
+__device__ __forceinline__ int32_t tag_trade(uint32_t tag) { return (int32_t)((tag & ~kTagGiant) - 2u); }
 
 struct WaveLds {
   uint64_t E[kSmallCap];
@@ -66,6 +73,8 @@ struct BigLds {
   int32_t cnt[4];
   int32_t base[2];
   int32_t ndone;
+  int32_t sboff[kTradeBlock];   // giant extraction: output offset per superblock
+  int32_t sbcnt[kTradeBlock];   // giant extraction: members per superblock
 };
 
 union TradeLds {
@@ -73,7 +82,12 @@ union TradeLds {
   BigLds big;
 };
 
-__device__ __forceinline__ void raise_error(const TradeArgs& A, int32_t bits) {
+__device__ __forceinline__ void raise_error(const TradeArgs& A, int32_t bits, int32_t trade = -1,
+                                            int32_t detail = 0) {
+  if (atomic_cas(&A.ctrl[cw(kCwDbgBits)], 0, bits)) {
+    store_agent(&A.ctrl[cw(kCwDbgA)], trade + 1);
+    store_agent(&A.ctrl[cw(kCwDbgB)], detail);
+  }
   atomic_or(&A.ctrl[cw(kCwErr)], bits);
   store_agent(&A.ctrl[cw(kCwAbort)], 1);
 }
@@ -162,16 +176,18 @@ struct Watchdog {
 
 // Emit/forward one output edge {owner, x}. Returns true if it is forwarded.
 __device__ __forceinline__ void route_edge(const TradeArgs& A, int32_t owner, int32_t x,
-                                           uint32_t tag) {
+                                           uint32_t tag, int32_t k) {
   if (tag == kTagPartner) return;  // own row only (handled by the caller)
   const int64_t rx = A.rp[x];
   const int32_t dx = (int32_t)(A.rp[x + 1] - rx);
   if (tag == kTagEmit) {
     const int32_t p = atomic_add(&A.out_cur[x], 1);
-    if (p < dx) A.col_out[rx + p] = owner; else raise_error(A, kErrOut);
+    if (p < dx) A.col_out[rx + p] = owner; else raise_error(A, kErrOut, k, x);
   } else {
     const int32_t p = atomic_add(&A.inbox_cur[x], 1);
-    if (p < dx) A.inbox[rx + p] = owner; else raise_error(A, kErrInbox);
+    if (p >= dx) raise_error(A, kErrInbox, k, x);
+    else if (tag & kTagGiant) giant_insert(A.gs, A.gs.giant_id[x], owner);
+    else store_agent(&A.inbox[rx + p], owner);
   }
 }
 
@@ -181,7 +197,7 @@ struct WaveState {
   int32_t top;        // local stack depth (uniform)
   int32_t ndone;
   int32_t shard;      // home shard of the small-trade queues
-  unsigned long long n_small, n_push, work, fwd, emit;
+  unsigned long long n_small, n_push, work, fwd, emit, ticks;
 };
 
 // Drops the dependency counters of later trades reached by this trade's
@@ -191,9 +207,9 @@ __device__ __forceinline__ void wave_release_item(const TradeArgs& A, WaveLds& W
   bool ready = false;
   int32_t t = -1;
   if (fwd) {
-    t = (int32_t)(tag - 2u);
+    t = tag_trade(tag);
     const int32_t old = atomic_add(&A.dep[t], -1);
-    if (old <= 0) raise_error(A, kErrDep);
+    if (old <= 0) raise_error(A, kErrDep, t, -1 - old);
     ready = old == 1;
   }
   const uint64_t m = ballot(ready);
@@ -202,7 +218,7 @@ __device__ __forceinline__ void wave_release_item(const TradeArgs& A, WaveLds& W
   const int room = A.stack_cap - S.top;
   const int r = rank_below(m);
   const uint64_t spill = ballot(ready && r >= room);
-  if (spill) fence_acq_rel();
+  if (spill) publish_wait();
   if (ready) {
     if (r < room) W.stack[S.top + r] = t;
     else queue_push(A, A.qs, kCwQsTail0, S.shard, t);
@@ -233,15 +249,16 @@ __device__ void small_trade(const TradeArgs& A, int32_t k, int32_t u, int32_t v,
       const int32_t e = c + l;
       int32_t x = 0, t = -1;
       if (e < d) { x = A.col[b + e]; t = A.col_t[b + e]; }
-      const bool fresh = e < d && t >= k;
+      const bool fresh = e < d && tinfo_trade(t) >= k;
       const uint64_t m = ballot(fresh);
       if (fresh) W.E[off + cnt + rank_below(m)] = make_entry(x, side, tag_of(t, k));
       cnt += popc64(m);
     }
     nf[side] = cnt;
     const int32_t ni = side ? niv : niu;
-    if (cnt + ni != d) { raise_error(A, kErrGather); return; }
-    for (int32_t j = l; j < ni; j += kWave) W.E[off + cnt + j] = make_entry(A.inbox[b + j], side, kTagEmit);
+    if (cnt + ni != d) { raise_error(A, kErrGather, k, (cnt + ni) - d); return; }
+    for (int32_t j = l; j < ni; j += kWave)
+      W.E[off + cnt + j] = make_entry(load_agent(&A.inbox[b + j]), side, kTagEmit);
   }
   wave_sync();
   wave_bitonic_sort(W.E, (uint32_t)s);
@@ -310,15 +327,15 @@ __device__ void small_trade(const TradeArgs& A, int32_t k, int32_t u, int32_t v,
       if (own) {
         const int32_t p = owner == u ? baseu + rank_below(mu) : basev + rank_below(mv);
         const int32_t dd = owner == u ? du : dv;
-        if (p < dd) A.col_out[(owner == u ? bu : bv) + p] = x; else raise_error(A, kErrOut);
+        if (p < dd) A.col_out[(owner == u ? bu : bv) + p] = x; else raise_error(A, kErrOut, k, -2 - owner);
       }
-      if (valid) route_edge(A, owner, x, tag);
+      if (valid) route_edge(A, owner, x, tag, k);
       nfwd += popc64(ballot(valid && tag >= 2u));
       nemit += popc64(ballot(valid && tag == kTagEmit));
     }
   }
   // every write above is visible before any counter it unlocks
-  fence_release();
+  publish_wait();
 #pragma unroll
   for (int pass = 0; pass < 2; ++pass) {
     const int32_t count = pass ? nD : s;
@@ -356,9 +373,10 @@ __device__ void wave_flush(const TradeArgs& A, WaveState& S) {
     if (S.work) atomicAdd(&A.stats[kStatWork], S.work);
     if (S.fwd) atomicAdd(&A.stats[kStatForward], S.fwd);
     if (S.emit) atomicAdd(&A.stats[kStatEmit], S.emit);
+    if (S.ticks) atomicAdd(&A.stats[kStatSmallTicks], S.ticks);
   }
   S.ndone = 0;
-  S.n_small = S.n_push = S.work = S.fwd = S.emit = 0;
+  S.n_small = S.n_push = S.work = S.fwd = S.emit = S.ticks = 0;
 }
 
 constexpr int32_t kFlushEvery = 32;   // trades between progress flushes
@@ -401,13 +419,15 @@ __device__ void small_worker(const TradeArgs& A, WaveLds& W) {
     if (s > A.small_max) {
       // large trade: hand it to a workgroup worker
       if (l == 0) {
-        fence_acq_rel();
+        publish_wait();
         queue_push(A, A.qb, kCwQbTail0, wid % kQbShards, k);
       }
       continue;
     }
-    fence_acquire();
+    consume_order();
+    const uint64_t t_start = now_ticks();
     small_trade(A, k, u, v, W, S);
+    S.ticks += now_ticks() - t_start;
     S.ndone += 1;
     if (S.ndone >= kFlushEvery) wave_flush(A, S);
     int32_t ab = 0;
@@ -446,10 +466,101 @@ __device__ __forceinline__ bool trade_item(const uint64_t* E, const int32_t* D, 
   return true;
 }
 
+// Collect one list of trade k (in any order): the round-start neighbours of
+// later trades (plus partner and left-out node) from the CSR row, then the
+// arrivals from the inbox. Workgroup-wide; false (error raised) on a size
+// mismatch.
+__device__ bool gather_list(const TradeArgs& A, int32_t k, int64_t b, int32_t d, int32_t ni,
+                            int side, uint64_t* out, BigLds& B) {
+  const int tid = threadIdx.x;
+  if (tid == 0) B.cnt[0] = 0;
+  __syncthreads();
+  for (int32_t e = tid; e < d; e += blockDim.x) {
+    const int32_t t = A.col_t[b + e];
+    if (tinfo_trade(t) >= k) {
+      const int32_t p = atomicAdd(&B.cnt[0], 1);
+      out[p] = make_entry(A.col[b + e], side, tag_of(t, k));
+    }
+  }
+  __syncthreads();
+  const int32_t nf = B.cnt[0];
+  __syncthreads();
+  if (nf + ni != d) {
+    if (tid == 0) raise_error(A, kErrGather, k, 1000000 + nf + ni - d);
+    return false;
+  }
+  for (int32_t j = tid; j < ni; j += blockDim.x)
+    out[nf + j] = make_entry(load_agent(&A.inbox[b + j]), side, kTagEmit);
+  __syncthreads();
+  return true;
+}
+
+// Write giant gi's neighbour set, ascending, as entries of `side` of trade k
+// into out[0..d), and clear the bitmap and its counts for the next round.
+// Workgroup-wide; false (error raised) if the set does not hold d members.
+__device__ bool extract_giant(const TradeArgs& A, int32_t k, int32_t gi, int side, int32_t d,
+                              uint64_t* out, BigLds& B) {
+  const int tid = threadIdx.x;
+  const int w = tid >> 6;
+  const int l = lane_id();
+  const int64_t nsb = A.gs.gwords >> 6;
+  unsigned long long* bm = A.gs.bm + (int64_t)gi * A.gs.gwords;
+  int32_t* sc = A.gs.sc + (int64_t)gi * nsb;
+  int32_t carry = 0;
+  bool bad = false;
+  for (int64_t j0 = 0; j0 < nsb; j0 += blockDim.x) {
+    const int64_t j = j0 + tid;
+    const int32_t c = j < nsb ? load_agent(&sc[j]) : 0;
+    int32_t tot;
+    const int32_t pre = block_excl_scan(c, B.scan, &tot);
+    B.sboff[tid] = carry + pre;
+    B.sbcnt[tid] = c;
+    __syncthreads();
+    // wave w handles superblocks j0 + 64w .. j0 + 64w + 63
+    for (int q = 0; q < kWave; ++q) {
+      const int slot_i = w * kWave + q;
+      const int64_t jj = j0 + slot_i;
+      if (jj >= nsb) break;
+      const int32_t cnt = B.sbcnt[slot_i];
+      if (cnt == 0) continue;
+      const int32_t base = B.sboff[slot_i];
+      const int64_t wi = jj * kWave + l;
+      unsigned long long word = load_agent_u64(&bm[wi]);
+      const int32_t pc = __popcll(word);
+      const int32_t at = base + wave_incl_scan(pc) - pc;
+      if (wave_sum(pc) != cnt) bad = true;
+      if (word) bm[wi] = 0ull;
+      int32_t idx = 0;
+      while (word) {
+        const int bit = __builtin_ctzll(word);
+        word &= word - 1;
+        const int32_t y = (int32_t)(wi * 64 + bit);
+        if (at + idx < d) out[at + idx] = make_entry(y, side, tag_of(A.tinfo[y], k));
+        ++idx;
+      }
+      if (l == 0) sc[jj] = 0;
+    }
+    carry += tot;
+    __syncthreads();
+  }
+  if (tid == 0) B.cnt[1] = 0;
+  __syncthreads();
+  if (bad) B.cnt[1] = 1;
+  __syncthreads();
+  const bool ok = B.cnt[1] == 0 && carry == d;
+  __syncthreads();
+  if (!ok) {
+    if (tid == 0) raise_error(A, kErrGather, k, 2000000 + carry - d);
+    return false;
+  }
+  return true;
+}
+
 constexpr int kBatch = 4;   // items per thread whose atomics are in flight together
 
 __device__ void big_trade(const TradeArgs& A, int32_t k, BigLds& B, uint64_t* slot,
                           unsigned long long* counters) {
+  const uint64_t t_begin = now_ticks();
   const int tid = threadIdx.x;
   const int nt = blockDim.x;
   const int32_t u = A.perm[2 * k], v = A.perm[2 * k + 1];
@@ -460,41 +571,64 @@ __device__ void big_trade(const TradeArgs& A, int32_t k, BigLds& B, uint64_t* sl
     if (tid == 0) raise_error(A, kErrCapacity);
     return;
   }
-  const bool in_lds = s <= A.big_lds_max;
+  const int32_t gu = A.gs.giant_id[u], gv = A.gs.giant_id[v];
+  const bool giant = gu >= 0 || gv >= 0;
+  const bool in_lds = !giant && s <= A.big_lds_max;
   uint64_t* E = in_lds ? B.u.tile.E : slot;
   int32_t* D = in_lds ? B.u.tile.D : (int32_t*)(slot + 2 * A.smax);
   const int32_t niu = load_agent(&A.inbox_cur[u]);
   const int32_t niv = load_agent(&A.inbox_cur[v]);
 
-  // ---- gather (any order: the list is sorted next)
-  for (int side = 0; side < 2; ++side) {
-    const int64_t b = side ? bv : bu;
-    const int32_t d = side ? dv : du;
-    const int32_t off = side ? du : 0;
-    const int32_t ni = side ? niv : niu;
-    if (tid == 0) B.cnt[0] = 0;
-    __syncthreads();
-    for (int32_t e = tid; e < d; e += nt) {
-      const int32_t t = A.col_t[b + e];
-      if (t >= k) {
-        const int32_t p = atomicAdd(&B.cnt[0], 1);
-        E[off + p] = make_entry(A.col[b + e], side, tag_of(t, k));
+  if (giant) {
+    // Both lists sorted separately (a giant's straight from its bitmap, the
+    // other in LDS), then merged into the slot.
+    uint64_t* L2 = slot + A.smax;   // u's list at [0, du), v's at [du, s)
+    for (int side = 0; side < 2; ++side) {
+      const int32_t gi = side ? gv : gu;
+      const int32_t d = side ? dv : du;
+      const int32_t off = side ? du : 0;
+      if (gi >= 0) {
+        if (!extract_giant(A, k, gi, side, d, L2 + off, B)) return;
+      } else if (d <= kBigCap) {
+        if (!gather_list(A, k, side ? bv : bu, d, side ? niv : niu, side, B.u.tile.E, B)) return;
+        block_bitonic_sort(B.u.tile.E, (uint32_t)d);
+        for (int32_t i = tid; i < d; i += nt) L2[off + i] = B.u.tile.E[i];
+      } else {
+        // the other node is too large for LDS (giant degree set above kBigCap)
+        if (!gather_list(A, k, side ? bv : bu, d, side ? niv : niu, side, L2 + off, B)) return;
+        __syncthreads();
+        const uint64_t* sorted = block_radix_sort<uint64_t>(L2 + off, E, d, A.keybits, B.u.R);
+        if (sorted != L2 + off)
+          for (int32_t i = tid; i < d; i += nt) L2[off + i] = sorted[i];
       }
+      __syncthreads();
+    }
+    // position in the merged list = own index + members of the other list below
+    for (int32_t i = tid; i < s; i += nt) {
+      const bool first = i < du;
+      const uint64_t e = L2[i];
+      const uint64_t* other = first ? L2 + du : L2;
+      int32_t lo = 0, hi = first ? dv : du;
+      while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (other[mid] < e) lo = mid + 1; else hi = mid;
+      }
+      E[(first ? i : i - du) + lo] = e;
     }
     __syncthreads();
-    const int32_t nf = B.cnt[0];
-    __syncthreads();
-    if (nf + ni != d) {
-      if (tid == 0) raise_error(A, kErrGather);
-      return;
+  } else {
+    for (int side = 0; side < 2; ++side) {
+      if (!gather_list(A, k, side ? bv : bu, side ? dv : du, side ? niv : niu, side,
+                       E + (side ? du : 0), B))
+        return;
     }
-    for (int32_t j = tid; j < ni; j += nt) E[off + nf + j] = make_entry(A.inbox[b + j], side, kTagEmit);
+    __syncthreads();
+    if (in_lds) block_bitonic_sort(E, (uint32_t)s);
+    else E = block_radix_sort<uint64_t>(E, slot + A.smax, s, A.keybits, B.u.R);
+    __syncthreads();
   }
-  __syncthreads();
-  if (in_lds) block_bitonic_sort(E, (uint32_t)s);
-  else E = block_radix_sort<uint64_t>(E, slot + A.smax, s, A.keybits, B.u.R);
-  __syncthreads();
 
+  const uint64_t t_gathered = now_ticks();
   // ---- classify; compact the disjoint set (ascending); a = |A_u minus shared|
   int32_t nD = 0, a = 0;
   for (int32_t c = 0; c < s; c += nt) {
@@ -518,6 +652,7 @@ __device__ void big_trade(const TradeArgs& A, int32_t k, BigLds& B, uint64_t* sl
   if (tid == 0) split_serial<int32_t>(D, nD, a, A.seed, A.round, k);
   __syncthreads();
 
+  const uint64_t t_split = now_ticks();
   // ---- own-row slots: one reservation per owner for the whole trade
   const int32_t items = s + nD;
   int32_t own_u = 0, own_v = 0;   // own-row items of this thread
@@ -554,7 +689,7 @@ __device__ void big_trade(const TradeArgs& A, int32_t k, BigLds& B, uint64_t* sl
           const bool ou = towner[r] == u;
           const int32_t p = ou ? pos_u++ : pos_v++;
           if (p < (ou ? du : dv)) A.col_out[(ou ? bu : bv) + p] = tx[r];
-          else raise_error(A, kErrOut);
+          else raise_error(A, kErrOut, k, -2 - towner[r]);
         }
         if (ttag[r] == kTagEmit) tp[r] = atomic_add(&A.out_cur[tx[r]], 1);
         else if (ttag[r] >= 2u) tp[r] = atomic_add(&A.inbox_cur[tx[r]], 1);
@@ -567,13 +702,15 @@ __device__ void big_trade(const TradeArgs& A, int32_t k, BigLds& B, uint64_t* sl
       if (tx[r] < 0 || ttag[r] == kTagPartner) continue;
       const int64_t rx = A.rp[tx[r]];
       const int32_t dx = (int32_t)(A.rp[tx[r] + 1] - rx);
-      if (tp[r] >= dx) { raise_error(A, ttag[r] == kTagEmit ? kErrOut : kErrInbox); continue; }
+      if (tp[r] >= dx) { raise_error(A, ttag[r] == kTagEmit ? kErrOut : kErrInbox, k, tx[r]); continue; }
       if (ttag[r] == kTagEmit) { A.col_out[rx + tp[r]] = towner[r]; ++nemit; }
-      else { A.inbox[rx + tp[r]] = towner[r]; ++nfwd; }
+      else if (ttag[r] & kTagGiant) { giant_insert(A.gs, A.gs.giant_id[tx[r]], towner[r]); ++nfwd; }
+      else { store_agent(&A.inbox[rx + tp[r]], towner[r]); ++nfwd; }
     }
   }
   __syncthreads();
-  fence_release();
+  publish_wait();
+  const uint64_t t_written = now_ticks();
 
   // ---- unlock later trades
   for (int32_t o0 = tid; o0 < items; o0 += nt * kBatch) {
@@ -585,22 +722,28 @@ __device__ void big_trade(const TradeArgs& A, int32_t k, BigLds& B, uint64_t* sl
       uint32_t tag;
       tt[r] = -1;
       if (o < items && trade_item(E, D, s, a, u, v, o, &owner, &x, &tag) && tag >= 2u) {
-        tt[r] = (int32_t)(tag - 2u);
+        tt[r] = tag_trade(tag);
         old[r] = atomic_add(&A.dep[tt[r]], -1);
       }
     }
 #pragma unroll
     for (int r = 0; r < kBatch; ++r) {
       if (tt[r] < 0) continue;
-      if (old[r] <= 0) raise_error(A, kErrDep);
+      if (old[r] <= 0) raise_error(A, kErrDep, tt[r], k);
       if (old[r] == 1) {
-        fence_acq_rel();
+        publish_wait();
         queue_push(A, A.qs, kCwQsTail0, (int)((blockIdx.x * 7 + tid) % kQsShards), tt[r]);
         counters[2] += 1;
       }
     }
   }
-  if (tid == 0) counters[0] += (unsigned long long)s;
+  if (tid == 0) {
+    counters[0] += (unsigned long long)s;
+    counters[4] += t_gathered - t_begin;
+    counters[5] += t_split - t_gathered;
+    counters[6] += t_written - t_split;
+    counters[7] += now_ticks() - t_written;
+  }
   counters[1] += (unsigned long long)nfwd;
   counters[3] += (unsigned long long)nemit;
   __syncthreads();
@@ -609,8 +752,10 @@ __device__ void big_trade(const TradeArgs& A, int32_t k, BigLds& B, uint64_t* sl
 __device__ void big_worker(const TradeArgs& A, BigLds& B) {
   const int tid = threadIdx.x;
   uint64_t* slot = A.slots + (int64_t)blockIdx.x * A.slot_elems;
-  // per-thread partial counters: work, forwarded, pushes, emitted
-  unsigned long long counters[4] = {0, 0, 0, 0};
+  // per-thread partial counters: work, forwarded, pushes, emitted, then
+  // (thread 0) ticks of gather, split, write, release
+  unsigned long long counters[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  unsigned long long max_ticks = 0;
   unsigned long long n_big = 0;
   Watchdog wd{0, 0};
   int32_t backoff = 1;
@@ -639,8 +784,11 @@ __device__ void big_worker(const TradeArgs& A, BigLds& B) {
       continue;
     }
     backoff = 1;
-    fence_acquire();
+    consume_order();
+    const uint64_t t0 = now_ticks();
     big_trade(A, k, B, slot, counters);
+    const uint64_t dt = now_ticks() - t0;
+    if (dt > max_ticks) max_ticks = dt;
     if (tid == 0) {
       atomic_add(&A.ctrl[cw(kCwDone)], 1);
       n_big += 1;
@@ -652,6 +800,15 @@ __device__ void big_worker(const TradeArgs& A, BigLds& B) {
   if (counters[2]) atomicAdd(&A.stats[kStatPush], counters[2]);
   if (counters[3]) atomicAdd(&A.stats[kStatEmit], counters[3]);
   if (tid == 0 && n_big) atomicAdd(&A.stats[kStatBig], n_big);
+  if (tid == 0) {
+    const unsigned long long busy = counters[4] + counters[5] + counters[6] + counters[7];
+    if (busy) atomicAdd(&A.stats[kStatBigTicks], busy);
+    if (counters[4]) atomicAdd(&A.stats[kStatBigGather], counters[4]);
+    if (counters[5]) atomicAdd(&A.stats[kStatBigSplit], counters[5]);
+    if (counters[6]) atomicAdd(&A.stats[kStatBigWrite], counters[6]);
+    if (counters[7]) atomicAdd(&A.stats[kStatBigRelease], counters[7]);
+    if (max_ticks) atomicMax(&A.stats[kStatBigMaxTicks], max_ticks);
+  }
 }
 
 __global__ void __launch_bounds__(kTradeBlock) k_trade(TradeArgs A) {

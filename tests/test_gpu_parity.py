@@ -48,7 +48,10 @@ TIERS = {"default": {}, "all_workgroup": {cb.OPT_SMALL_MAX: 0},
          "all_global": {cb.OPT_SMALL_MAX: 0, cb.OPT_BIG_LDS_MAX: 0},
          "mixed_global": {cb.OPT_SMALL_MAX: 64, cb.OPT_BIG_LDS_MAX: 200},
          "tiny_wave": {cb.OPT_SMALL_MAX: 8, cb.OPT_BIG_WORKERS: 1},
-         "no_stack": {cb.OPT_LOCAL_STACK: 0}}
+         "no_stack": {cb.OPT_LOCAL_STACK: 0},
+         "giant8": {cb.OPT_GIANT_DEG: 8},
+         "giant8_all_workgroup": {cb.OPT_GIANT_DEG: 8, cb.OPT_SMALL_MAX: 0},
+         "giant40_global": {cb.OPT_GIANT_DEG: 40, cb.OPT_BIG_LDS_MAX: 0}}
 
 
 def _run_and_compare(orc, rp, col, seed, rounds, options=None, form="o1"):
@@ -90,13 +93,26 @@ def _hub_graph():
     return graphgen.edge_list_to_csr(n, sorted(edges))
 
 
-@pytest.mark.parametrize("tier", ["default", "all_global", "all_workgroup"])
+@pytest.mark.parametrize("tier", ["default", "all_global", "all_workgroup", "giant8", "no_giant"])
 def test_hub_above_2_15_entries(orc, tier):
     """Regression: own-row counts of a side above 2^15 entries."""
     _say(f"hub graph tier {tier}")
     rp, col = _hub_graph()
     assert np.diff(rp).max() >= 35000
-    _run_and_compare(orc, rp, col, seed=3, rounds=2, options=TIERS[tier])
+    opts = {cb.OPT_GIANT_DEG: 0} if tier == "no_giant" else TIERS[tier]
+    _run_and_compare(orc, rp, col, seed=3, rounds=2, options=opts)
+
+
+def test_partial_round_then_full_round(orc):
+    """A step-wise round that stops early must not leak state into the next."""
+    rp, col = graphgen.pld_graph(3000, 2, 300, 2.0, 11)
+    g = cb.Graph(rp, col)
+    g.set_option(cb.OPT_GIANT_DEG, 20)
+    g.run_steps(9, 0, cb.STEP_DEPSCAN)
+    g.global_trade(9, 0)
+    ref, _ = orc.global_trade(rp, col, 9, 0)
+    assert np.array_equal(g.download(), ref)
+    g.close()
 
 
 def test_matching_and_depscan_match_oracle(orc):
@@ -119,7 +135,7 @@ def test_matching_and_depscan_match_oracle(orc):
 def test_small_workload_ten_rounds_every_round(orc):
     rp, col = graphgen.workload("small")
     _say(f"small workload n={len(rp)-1} m={len(col)//2}")
-    for tier in ("default", "all_workgroup", "mixed_global"):
+    for tier in ("default", "all_workgroup", "mixed_global", "giant8"):
         _run_and_compare(orc, rp, col, seed=1, rounds=10, options=TIERS[tier])
 
 
