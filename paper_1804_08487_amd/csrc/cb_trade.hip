@@ -498,8 +498,12 @@ __device__ bool gather_list(const TradeArgs& A, int32_t k, int64_t b, int32_t d,
 // Write giant gi's neighbour set, ascending, as entries of `side` of trade k
 // into out[0..d), and clear the bitmap and its counts for the next round.
 // Workgroup-wide; false (error raised) if the set does not hold d members.
+// The bit pass is pure arithmetic (wave w takes 64 superblocks, four at a
+// time); the tags, which need one gather per member, follow in a separate
+// batched pass.
 __device__ bool extract_giant(const TradeArgs& A, int32_t k, int32_t gi, int side, int32_t d,
                               uint64_t* out, BigLds& B) {
+  constexpr int kSbStep = 2;
   const int tid = threadIdx.x;
   const int w = tid >> 6;
   const int l = lane_id();
@@ -516,29 +520,36 @@ __device__ bool extract_giant(const TradeArgs& A, int32_t k, int32_t gi, int sid
     B.sboff[tid] = carry + pre;
     B.sbcnt[tid] = c;
     __syncthreads();
-    // wave w handles superblocks j0 + 64w .. j0 + 64w + 63
-    for (int q = 0; q < kWave; ++q) {
-      const int slot_i = w * kWave + q;
-      const int64_t jj = j0 + slot_i;
-      if (jj >= nsb) break;
-      const int32_t cnt = B.sbcnt[slot_i];
-      if (cnt == 0) continue;
-      const int32_t base = B.sboff[slot_i];
-      const int64_t wi = jj * kWave + l;
-      unsigned long long word = load_agent_u64(&bm[wi]);
-      const int32_t pc = __popcll(word);
-      const int32_t at = base + wave_incl_scan(pc) - pc;
-      if (wave_sum(pc) != cnt) bad = true;
-      if (word) bm[wi] = 0ull;
-      int32_t idx = 0;
-      while (word) {
-        const int bit = __builtin_ctzll(word);
-        word &= word - 1;
-        const int32_t y = (int32_t)(wi * 64 + bit);
-        if (at + idx < d) out[at + idx] = make_entry(y, side, tag_of(A.tinfo[y], k));
-        ++idx;
+    for (int q = 0; q < kWave; q += kSbStep) {
+      unsigned long long word[kSbStep];
+#pragma unroll
+      for (int t = 0; t < kSbStep; ++t) {
+        const int slot_i = w * kWave + q + t;
+        const int64_t jj = j0 + slot_i;
+        word[t] = (jj < nsb && B.sbcnt[slot_i] > 0) ? load_agent_u64(&bm[jj * kWave + l]) : 0ull;
       }
-      if (l == 0) sc[jj] = 0;
+#pragma unroll
+      for (int t = 0; t < kSbStep; ++t) {
+        const int slot_i = w * kWave + q + t;
+        const int64_t jj = j0 + slot_i;
+        if (jj >= nsb) break;
+        const int32_t cnt = B.sbcnt[slot_i];
+        if (cnt == 0) continue;
+        const int64_t wi = jj * kWave + l;
+        unsigned long long bits = word[t];
+        const int32_t pc = __popcll(bits);
+        const int32_t at = B.sboff[slot_i] + wave_incl_scan(pc) - pc;
+        if (wave_sum(pc) != cnt) bad = true;
+        if (bits) bm[wi] = 0ull;
+        int32_t idx = 0;
+        while (bits) {
+          const int bit = __builtin_ctzll(bits);
+          bits &= bits - 1;
+          if (at + idx < d) out[at + idx] = make_entry((int32_t)(wi * 64 + bit), side, 0u);
+          ++idx;
+        }
+        if (l == 0) sc[jj] = 0;
+      }
     }
     carry += tot;
     __syncthreads();
@@ -553,10 +564,26 @@ __device__ bool extract_giant(const TradeArgs& A, int32_t k, int32_t gi, int sid
     if (tid == 0) raise_error(A, kErrGather, k, 2000000 + carry - d);
     return false;
   }
+  // tags of the members (one gather each, four in flight per thread)
+  for (int32_t i0 = tid; i0 < d; i0 += blockDim.x * 4) {
+    int32_t ti[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int32_t i = i0 + r * blockDim.x;
+      ti[r] = i < d ? A.tinfo[ent_node(out[i])] : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int32_t i = i0 + r * blockDim.x;
+      if (i < d) out[i] |= tag_of(ti[r], k);
+    }
+  }
+  __syncthreads();
   return true;
 }
 
 constexpr int kBatch = 4;   // items per thread whose atomics are in flight together
+constexpr int kPer = 8;     // consecutive entries per thread in the classification scan
 
 __device__ void big_trade(const TradeArgs& A, int32_t k, BigLds& B, uint64_t* slot,
                           unsigned long long* counters) {
@@ -603,11 +630,15 @@ __device__ void big_trade(const TradeArgs& A, int32_t k, BigLds& B, uint64_t* sl
       }
       __syncthreads();
     }
-    // position in the merged list = own index + members of the other list below
+    // position in the merged list = own index + members of the other list
+    // below; a non-giant list is searched in its LDS copy
+    const int lds_side = (gu >= 0) == (gv >= 0) ? -1 : (gu >= 0 ? 1 : 0);
+    const bool lds_ok = lds_side >= 0 && (lds_side ? dv : du) <= kBigCap;
     for (int32_t i = tid; i < s; i += nt) {
       const bool first = i < du;
       const uint64_t e = L2[i];
-      const uint64_t* other = first ? L2 + du : L2;
+      const int other_side = first ? 1 : 0;
+      const uint64_t* other = (lds_ok && other_side == lds_side) ? B.u.tile.E : (first ? L2 + du : L2);
       int32_t lo = 0, hi = first ? dv : du;
       while (lo < hi) {
         const int32_t mid = (lo + hi) >> 1;
@@ -630,75 +661,99 @@ __device__ void big_trade(const TradeArgs& A, int32_t k, BigLds& B, uint64_t* sl
 
   const uint64_t t_gathered = now_ticks();
   // ---- classify; compact the disjoint set (ascending); a = |A_u minus shared|
+  // Each thread takes kPer consecutive entries, so one workgroup scan covers
+  // kPer * blockDim entries.
   int32_t nD = 0, a = 0;
-  for (int32_t c = 0; c < s; c += nt) {
-    const int32_t i = c + tid;
-    int32_t flags = 0;   // bit 0: disjoint, bit 16: disjoint and on u's side
-    if (i < s) {
-      const uint64_t e = E[i];
-      const int32_t x = ent_node(e);
-      const bool isP = ent_tag(e) == kTagPartner;
-      const bool isC = !isP && ((i > 0 && ent_node(E[i - 1]) == x) ||
-                                (i + 1 < s && ent_node(E[i + 1]) == x));
-      if (!isP && !isC) flags = ent_side(e) == 0 ? 0x10001 : 1;
+  for (int32_t c = 0; c < s; c += nt * kPer) {
+    const int32_t i0 = c + tid * kPer;
+    int32_t nodes[kPer + 2];
+    uint32_t meta[kPer];   // bit 0: tag is partner, bit 1: side
+#pragma unroll
+    for (int r = 0; r < kPer + 2; ++r) {
+      const int32_t i = i0 - 1 + r;
+      nodes[r] = (i >= 0 && i < s) ? ent_node(E[i]) : -1;
+    }
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+      const int32_t i = i0 + r;
+      meta[r] = 0;
+      if (i < s) {
+        const uint64_t e = E[i];
+        meta[r] = (ent_tag(e) == kTagPartner ? 1u : 0u) | ((uint32_t)ent_side(e) << 1);
+      }
+    }
+    int32_t cnt = 0, cntu = 0;
+    uint32_t dmask = 0;
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+      const int32_t i = i0 + r;
+      if (i >= s) continue;
+      const bool isP = meta[r] & 1u;
+      const bool isC = !isP && (nodes[r] == nodes[r + 1] || nodes[r + 2] == nodes[r + 1]);
+      if (!isP && !isC) {
+        dmask |= 1u << r;
+        ++cnt;
+        if (!(meta[r] & 2u)) ++cntu;
+      }
     }
     int32_t tot;
-    const int32_t pre = block_excl_scan(flags, B.scan, &tot);
-    if (flags) D[nD + (pre & 0xFFFF)] = i;
+    const int32_t pre = block_excl_scan(cnt | (cntu << 16), B.scan, &tot);
+    int32_t pos = nD + (pre & 0xFFFF);
+#pragma unroll
+    for (int r = 0; r < kPer; ++r)
+      if (dmask & (1u << r)) D[pos++] = i0 + r;
     nD += tot & 0xFFFF;
     a += tot >> 16;
   }
   __syncthreads();
   if (tid == 0) split_serial<int32_t>(D, nD, a, A.seed, A.round, k);
+  if (tid == 0) { B.cnt[1] = 0; B.cnt[2] = 0; }
   __syncthreads();
 
   const uint64_t t_split = now_ticks();
-  // ---- own-row slots: one reservation per owner for the whole trade
+  // ---- write: own rows at positions from workgroup counters (no other trade
+  // writes these two rows before this one publishes), other rows and inboxes
+  // by batched atomics
   const int32_t items = s + nD;
-  int32_t own_u = 0, own_v = 0;   // own-row items of this thread
-  for (int32_t o = tid; o < items; o += nt) {
-    int32_t owner, x;
-    uint32_t tag;
-    if (trade_item(E, D, s, a, u, v, o, &owner, &x, &tag) && tag <= kTagPartner) {
-      if (owner == u) ++own_u; else ++own_v;
-    }
-  }
-  int32_t tot_u, tot_v;
-  const int32_t pre_u = block_excl_scan(own_u, B.scan, &tot_u);
-  const int32_t pre_v = block_excl_scan(own_v, B.scan, &tot_v);
-  if (tid == 0) {
-    B.base[0] = tot_u ? atomic_add(&A.out_cur[u], tot_u) : 0;
-    B.base[1] = tot_v ? atomic_add(&A.out_cur[v], tot_v) : 0;
-  }
-  __syncthreads();
-  int32_t pos_u = B.base[0] + pre_u;
-  int32_t pos_v = B.base[1] + pre_v;
-
-  // ---- write: own rows directly, other rows and inboxes by batched atomics
   int32_t nfwd = 0, nemit = 0;
+  const int l = lane_id();
   for (int32_t o0 = tid; o0 < items; o0 += nt * kBatch) {
     int32_t tx[kBatch], towner[kBatch], tp[kBatch];
     uint32_t ttag[kBatch];
+    bool own[kBatch];
+    int32_t nu = 0, nv = 0;
+    uint64_t mu[kBatch], mv[kBatch];
 #pragma unroll
     for (int r = 0; r < kBatch; ++r) {
       const int32_t o = o0 + r * nt;
       tx[r] = -1;
       tp[r] = 0;
-      if (o < items && trade_item(E, D, s, a, u, v, o, &towner[r], &tx[r], &ttag[r])) {
-        if (ttag[r] <= kTagPartner) {
-          const bool ou = towner[r] == u;
-          const int32_t p = ou ? pos_u++ : pos_v++;
-          if (p < (ou ? du : dv)) A.col_out[(ou ? bu : bv) + p] = tx[r];
-          else raise_error(A, kErrOut, k, -2 - towner[r]);
-        }
-        if (ttag[r] == kTagEmit) tp[r] = atomic_add(&A.out_cur[tx[r]], 1);
-        else if (ttag[r] >= 2u) tp[r] = atomic_add(&A.inbox_cur[tx[r]], 1);
-      } else {
-        tx[r] = -1;
-      }
+      if (!(o < items && trade_item(E, D, s, a, u, v, o, &towner[r], &tx[r], &ttag[r]))) tx[r] = -1;
+      own[r] = tx[r] >= 0 && ttag[r] <= kTagPartner;
+      mu[r] = ballot(own[r] && towner[r] == u);
+      mv[r] = ballot(own[r] && towner[r] == v);
+      nu += popc64(mu[r]);
+      nv += popc64(mv[r]);
+      if (tx[r] >= 0 && ttag[r] == kTagEmit) tp[r] = atomic_add(&A.out_cur[tx[r]], 1);
+      else if (tx[r] >= 0 && ttag[r] >= 2u) tp[r] = atomic_add(&A.inbox_cur[tx[r]], 1);
     }
+    int32_t bu_own = 0, bv_own = 0;
+    if (l == 0) {
+      if (nu) bu_own = atomicAdd(&B.cnt[1], nu);
+      if (nv) bv_own = atomicAdd(&B.cnt[2], nv);
+    }
+    bu_own = wave_bcast(bu_own, 0);
+    bv_own = wave_bcast(bv_own, 0);
 #pragma unroll
     for (int r = 0; r < kBatch; ++r) {
+      if (own[r]) {
+        const bool ou = towner[r] == u;
+        const int32_t p = ou ? bu_own + rank_below(mu[r]) : bv_own + rank_below(mv[r]);
+        if (p < (ou ? du : dv)) A.col_out[(ou ? bu : bv) + p] = tx[r];
+        else raise_error(A, kErrOut, k, -2 - towner[r]);
+      }
+      bu_own += popc64(mu[r]);
+      bv_own += popc64(mv[r]);
       if (tx[r] < 0 || ttag[r] == kTagPartner) continue;
       const int64_t rx = A.rp[tx[r]];
       const int32_t dx = (int32_t)(A.rp[tx[r] + 1] - rx);
@@ -707,6 +762,12 @@ __device__ void big_trade(const TradeArgs& A, int32_t k, BigLds& B, uint64_t* sl
       else if (ttag[r] & kTagGiant) { giant_insert(A.gs, A.gs.giant_id[tx[r]], towner[r]); ++nfwd; }
       else { store_agent(&A.inbox[rx + tp[r]], towner[r]); ++nfwd; }
     }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    // the own rows start empty this round: anything else means an ordering bug
+    if (B.cnt[1] && atomic_add(&A.out_cur[u], B.cnt[1]) != 0) raise_error(A, kErrOut, k, -2 - u);
+    if (B.cnt[2] && atomic_add(&A.out_cur[v], B.cnt[2]) != 0) raise_error(A, kErrOut, k, -2 - v);
   }
   __syncthreads();
   publish_wait();
