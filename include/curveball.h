@@ -121,9 +121,22 @@ cb_status global_trade_steps(cb_graph* g, uint64_t seed, uint32_t round, int32_t
 #define CB_STATE_COL      4  /* int32[nnz]: current adjacency (rows ascending) */
 #define CB_STATE_OUT_CUR  5  /* int32[n]: final edges written per row this round */
 #define CB_STATE_INBOX_CUR 6 /* int32[n]: edges handed to each row this round */
+#define CB_STATE_TRACE    7  /* int64[16 * floor(n/2)] (CB_OPT_TRACE): per trade k
+                                at 16k + i: i=0 tick at which it became ready
+                                (-1: a source), 1 start and 2 end of its
+                                execution, 3 trade whose release made it ready
+                                (-1: a source); for trades run by a workgroup
+                                also 4 both lists collected, 5 sorted or merged,
+                                6 classified, 7 split and own rows reserved,
+                                8 deg u + deg v, 9 kind (1 giant node, 2 in LDS,
+                                3 in global scratch), 10 deg u, 11 deg v,
+                                12 disjoint entries, 13 of which u's. Ticks of
+                                the device's constant 100 MHz clock; -1 where
+                                not recorded */
 
-/* Synchronise and copy `count` elements of state `which` to host memory.
- * Also valid on a poisoned handle (diagnosis after a device error). */
+/* Synchronise and copy `count` elements of state `which` to host memory
+ * (elements are int32 except for CB_STATE_TRACE, int64). Also valid on a
+ * poisoned handle (diagnosis after a device error). */
 cb_status graph_download_state(cb_graph* g, int32_t which, void* host, int64_t count);
 
 /* ---- options ------------------------------------------------------------ */
@@ -139,6 +152,11 @@ cb_status graph_download_state(cb_graph* g, int32_t which, void* host, int64_t c
                                    stay in LDS (0..12288); larger ones use a
                                    global scratch slot. Default 12288. */
 #define CB_OPT_DEBUG_CHECKS  9  /* 1: extra invariant checks between kernels */
+#define CB_OPT_HELP_MIN     11  /* workgroup trades with deg u + deg v >= this
+                                   let idle wavefronts of the kernel share their
+                                   write phase (0 = never). Default 8192. */
+#define CB_OPT_TRACE        10  /* 1: record per-trade times (CB_STATE_TRACE);
+                                   allocates 128 bytes per trade on first use */
 #define CB_OPT_GIANT_DEG     8  /* nodes of at least this degree keep the edges
                                    handed to them in a bitmap over all node ids
                                    (n/8 bytes each) instead of a list; 0 = none.
@@ -163,8 +181,9 @@ typedef struct {
     double big_busy_us;      /* summed time workgroups spent inside trades */
     double big_gather_us;    /* ... collecting and sorting the two lists */
     double big_split_us;     /* ... classifying and splitting */
-    double big_write_us;     /* ... writing final edges and forwarding */
-    double big_release_us;   /* ... unlocking later trades */
+    double big_write_us;     /* ... writing final edges, forwarding and
+                                unlocking later trades */
+    double big_release_us;   /* 0: unlocking is part of the write phase */
     double big_max_us;       /* longest single workgroup trade */
 } cb_round_stats;
 

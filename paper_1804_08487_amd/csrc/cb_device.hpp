@@ -69,6 +69,21 @@ __device__ __forceinline__ int64_t load_agent64(const int64_t* p) {
 __device__ __forceinline__ unsigned long long load_agent_u64(const unsigned long long* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ void store_agent_u64(unsigned long long* p, unsigned long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_agent64(int64_t* p, int64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t atomic_and(int32_t* p, int32_t v) {
+  return __hip_atomic_fetch_and(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// On failure *expected receives the current value.
+__device__ __forceinline__ bool atomic_cas_u64(unsigned long long* p, unsigned long long* expected,
+                                               unsigned long long desired) {
+  return __hip_atomic_compare_exchange_strong(p, expected, desired, __ATOMIC_RELAXED,
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // Ordering between trades. Every datum one trade hands to another inside
 // the trade kernel (inbox entries, bitmap words, counters, queue slots) is

@@ -70,6 +70,9 @@ struct cb_graph {
   uint64_t* mkey = nullptr;
   int32_t* dep = nullptr;
   int32_t* src_list = nullptr;
+  int32_t* tsz = nullptr;
+  HelpJob* jobs = nullptr;
+  int64_t* trace = nullptr;     // allocated when tracing is first switched on
   int32_t* qs = nullptr;
   int32_t* qb = nullptr;
   int32_t* bcount = nullptr;
@@ -99,9 +102,11 @@ struct cb_graph {
   int32_t nbig_alloc = 0;    // slots allocated
   int32_t grid_blocks = 0;   // 0: automatic
   int32_t stack_cap = 8;
+  int32_t help_min = kHelpMinItems;
   int64_t watchdog_ms = 20000;
   bool timing = false;
   bool debug_checks = false;
+  bool tracing = false;
 
   bool poisoned = false;
   std::string poison_msg;
@@ -280,6 +285,12 @@ int32_t trade_grid(const cb_graph* g) {
   return std::max(blocks, effective_nbig(g) + 1);
 }
 
+// Trades above this size run on a workgroup (a giant node never runs on a
+// wavefront).
+int32_t effective_small_max(const cb_graph* g) {
+  return g->giant_deg > 0 ? (int32_t)std::min<int64_t>(g->small_max, g->giant_deg - 1) : g->small_max;
+}
+
 cb_status enqueue_round(cb_graph* g, uint64_t seed, uint32_t round, int last_step) {
   if (!g) return fail(CB_EINVAL, "null graph");
   if (g->poisoned) return fail(CB_EPOISONED, "graph handle poisoned: " + g->poison_msg);
@@ -334,7 +345,8 @@ cb_status enqueue_round(cb_graph* g, uint64_t seed, uint32_t round, int last_ste
                          giant_sets(g), g->ctrl);
     if (L > 0)
       hipLaunchKernelGGL(k_sources, dim3(grid_for(L, 256, 8192)), dim3(256), 0, st, L, g->dep,
-                         g->src_list, g->ctrl, g->stats);
+                         g->perm, g->rp, effective_small_max(g), g->tsz, g->src_list, g->qb,
+                         g->ctrl, g->stats);
   }
   if (timed) (void)hipEventRecord(evs.ev[2], st);
   if (last_step >= CB_STEP_TRADE && L > 0) {
@@ -352,6 +364,14 @@ cb_status enqueue_round(cb_graph* g, uint64_t seed, uint32_t round, int last_ste
     A.out_cur = g->out_cur;
     A.dep = g->dep;
     A.src_list = g->src_list;
+    A.tsz = g->tsz;
+    A.jobs = g->jobs;
+    A.trace = g->tracing ? g->trace : nullptr;
+    if (g->tracing) {
+      std::string msg;
+      if (!hip_ok(hipMemsetAsync(g->trace, 0xFF, (size_t)L * kTraceFields * sizeof(int64_t), st), &msg, "clear trace"))
+        return fail(CB_EDEVICE, msg);
+    }
     A.qs = g->qs;
     A.qb = g->qb;
     A.ctrl = g->ctrl;
@@ -361,7 +381,8 @@ cb_status enqueue_round(cb_graph* g, uint64_t seed, uint32_t round, int last_ste
     A.smax = g->smax;
     A.n = n;
     A.L = L;
-    A.small_max = g->giant_deg > 0 ? std::min<int64_t>(g->small_max, g->giant_deg - 1) : g->small_max;
+    A.small_max = effective_small_max(g);
+    A.help_min = g->help_min;
     A.big_lds_max = g->big_lds_max;
     A.nbig = effective_nbig(g);
     A.stack_cap = g->stack_cap;
@@ -486,7 +507,8 @@ cb_status graph_upload(int64_t n, const int64_t* row_ptr, const int32_t* col, vo
             alloc_into(g, &g->trade_of, n) && alloc_into(g, &g->tinfo, n) &&
             alloc_into(g, &g->giant_id, n) && alloc_into(g, &g->mtmp, n) &&
             alloc_into(g, &g->mkey, n) && alloc_into(g, &g->dep, g->L) &&
-            alloc_into(g, &g->src_list, g->L) && alloc_into(g, &g->qs, (int64_t)kQsShards * std::max<int64_t>(g->L, 1)) &&
+            alloc_into(g, &g->src_list, g->L) && alloc_into(g, &g->tsz, g->L) &&
+            alloc_into(g, &g->jobs, kMaxJobs) && alloc_into(g, &g->qs, (int64_t)kQsShards * std::max<int64_t>(g->L, 1)) &&
             alloc_into(g, &g->qb, (int64_t)kQbShards * std::max<int64_t>(g->L, 1)) && alloc_into(g, &g->bcount, g->nb) &&
             alloc_into(g, &g->bstart, g->nb + 1) && alloc_into(g, &g->bcur, g->nb) &&
             alloc_into(g, &g->ctrl, kCtrlInts) && alloc_into(g, &g->stats, kStatCount) &&
@@ -505,6 +527,7 @@ cb_status graph_upload(int64_t n, const int64_t* row_ptr, const int32_t* col, vo
        (rm.empty() || hip_ok(hipMemcpyAsync(g->rows_mid, rm.data(), rm.size() * sizeof(int32_t), hipMemcpyHostToDevice, st), &msg, "copy rows")) &&
        (rb.empty() || hip_ok(hipMemcpyAsync(g->rows_big, rb.data(), rb.size() * sizeof(int32_t), hipMemcpyHostToDevice, st), &msg, "copy rows")) &&
        hip_ok(hipMemsetAsync(g->ctrl, 0, kCtrlInts * sizeof(int32_t), st), &msg, "clear ctrl") &&
+       hip_ok(hipMemsetAsync(g->jobs, 0, kMaxJobs * sizeof(HelpJob), st), &msg, "clear jobs") &&
        hip_ok(hipMemsetAsync(g->qs, 0xFF, (size_t)kQsShards * std::max<int64_t>(g->L, 1) * sizeof(int32_t), st), &msg, "clear queues") &&
        hip_ok(hipMemsetAsync(g->qb, 0xFF, (size_t)kQbShards * std::max<int64_t>(g->L, 1) * sizeof(int32_t), st), &msg, "clear queues");
   if (ok && (flags & CB_VALIDATE) && nnz > 0) {
@@ -592,7 +615,12 @@ cb_status graph_download_state(cb_graph* g, int32_t which, void* host, int64_t c
   if (count < 0 || (count > 0 && !host)) return fail(CB_EINVAL, "bad buffer");
   const void* src = nullptr;
   int64_t avail = 0;
+  size_t elem = sizeof(int32_t);
   switch (which) {
+    case CB_STATE_TRACE:
+      if (!g->trace) return fail(CB_EINVAL, "tracing was never switched on");
+      src = g->trace; avail = kTraceFields * (int64_t)g->L; elem = sizeof(int64_t);
+      break;
     case CB_STATE_PERM: src = g->perm; avail = g->n; break;
     case CB_STATE_TRADE_OF: src = g->trade_of; avail = g->n; break;
     case CB_STATE_DEP: src = g->dep; avail = g->L; break;
@@ -604,7 +632,7 @@ cb_status graph_download_state(cb_graph* g, int32_t which, void* host, int64_t c
   if (count > avail) return fail(CB_EINVAL, "count exceeds the state size");
   std::string msg;
   if (!hip_ok(hipStreamSynchronize(g->stream), &msg, "hipStreamSynchronize")) return fail(CB_EDEVICE, msg);
-  if (count > 0 && !hip_ok(hipMemcpy(host, src, (size_t)count * sizeof(int32_t), hipMemcpyDeviceToHost), &msg, "download state"))
+  if (count > 0 && !hip_ok(hipMemcpy(host, src, (size_t)count * elem, hipMemcpyDeviceToHost), &msg, "download state"))
     return fail(CB_EDEVICE, msg);
   return CB_OK;
 }
@@ -634,6 +662,11 @@ cb_status graph_set_option(cb_graph* g, int32_t option, int64_t value) {
     case CB_OPT_DEBUG_CHECKS:
       g->debug_checks = value != 0;
       return CB_OK;
+    case CB_OPT_TRACE:
+      if (value != 0 && !g->trace && !alloc_into(g, &g->trace, kTraceFields * (int64_t)g->L))
+        return fail(CB_ENOMEM, "trace buffer allocation failed");
+      g->tracing = value != 0;
+      return CB_OK;
     case CB_OPT_BIG_LDS_MAX:
       if (value < 0 || value > kBigCap) return fail(CB_EINVAL, "big_lds_max must be in [0, 12288]");
       g->big_lds_max = (int32_t)value;
@@ -647,6 +680,10 @@ cb_status graph_set_option(cb_graph* g, int32_t option, int64_t value) {
         return fail(CB_EDEVICE, msg);
       return setup_giants(g, value, rp.data());
     }
+    case CB_OPT_HELP_MIN:
+      if (value < 0 || value > INT32_MAX) return fail(CB_EINVAL, "help_min must be in [0, 2^31 - 1]");
+      g->help_min = (int32_t)value;
+      return CB_OK;
     case CB_OPT_LOCAL_STACK:
       if (value < 0 || value > kStackCap) return fail(CB_EINVAL, "local stack must be in [0, 16]");
       g->stack_cap = (int32_t)value;

@@ -27,7 +27,9 @@ enum CtrlWord : int {
   kCwQsTail0 = kCwQsHead0 + kQsShards,
   kCwQbHead0 = kCwQsTail0 + kQsShards,
   kCwQbTail0 = kCwQbHead0 + kQbShards,
-  kCwCount = kCwQbTail0 + kQbShards
+  kCwJobMask0 = kCwQbTail0 + kQbShards,   // write jobs open to helpers: workgroups 0..31
+  kCwJobMask1,                            // ... and 32..63
+  kCwCount
 };
 __host__ __device__ constexpr int cw(int word) { return word * kCtrlStride; }
 constexpr int kCtrlInts = kCwCount * kCtrlStride;
@@ -51,6 +53,32 @@ constexpr int kGiantMinDeg = kBigCap / 2;   // default giant degree: any other p
 constexpr int kTradeBlock = 1024;     // threads per trade-kernel workgroup
 constexpr int kWavesPerBlock = kTradeBlock / 64;
 constexpr int kStackCap = 16;         // ready trades a wavefront may keep
+constexpr int kTraceFields = 16;      // int64 per trade of the optional trace
+constexpr int kMaxJobs = 64;          // workgroups that can open their write phase to helpers
+constexpr int32_t kHelpChunk = 1024;  // output items per claimed chunk
+constexpr int32_t kHelpMinItems = 8192;   // default: smaller trades write alone
+
+// Write phase of one large trade, open to helper wavefronts (one per
+// workgroup worker, reused trade after trade). The owner publishes the
+// fields, then a new generation in the ticket; a wavefront claims chunk c of
+// generation g by moving the ticket from (g, c) to (g, c + 1), and reports it
+// in `done`. The fields of generation g stay unchanged until every chunk of
+// it is reported, so a successful claim guarantees that the fields read
+// before it belong to g.
+struct HelpJob {
+  struct alignas(128) {
+    unsigned long long ticket;   // (generation << 32) | next chunk
+  } t;
+  struct alignas(128) {
+    int32_t done;                // chunks written
+    int32_t own[2];              // own-row positions handed out for u and v
+  } c;
+  struct alignas(128) {
+    int64_t bu, bv;              // row offsets of u and v
+    int64_t e_off;               // entry array = owner's slot + e_off
+    int32_t k, u, v, s, nD, a, du, dv, nchunks;
+  } f;
+};
 constexpr int kMatchCap = 2048;       // bucket size sorted in LDS by k_match_sort
 constexpr int kMatchBlock = 256;
 constexpr int kScanChunk = 2048;      // CSR entries per workgroup in k_depscan/k_validate
@@ -92,6 +120,9 @@ struct TradeArgs {
   int32_t* out_cur;
   int32_t* dep;
   const int32_t* src_list;
+  const int32_t* tsz;       // deg u + deg v per trade, from k_sources
+  int64_t* trace;           // optional: per trade ready, start, end tick and releasing trade
+  HelpJob* jobs;            // kMaxJobs write jobs
   int32_t* qs;              // kQsShards ready queues of L slots (-1 = empty)
   int32_t* qb;              // kQbShards ready queues of large trades
   int32_t* ctrl;
@@ -103,6 +134,7 @@ struct TradeArgs {
   int64_t n;
   int32_t L;
   int32_t small_max;
+  int32_t help_min;         // trades of at least this many items open their write phase (0: none)
   int32_t big_lds_max;
   int32_t nbig;
   int32_t stack_cap;
@@ -130,8 +162,9 @@ __global__ void k_match_sort(int64_t n, uint64_t seed, uint32_t round, int32_t n
 __global__ void k_depscan(int64_t n, int64_t nnz, const int64_t* rp, const int32_t* col,
                           const int32_t* trade_of, const int32_t* tinfo, int32_t* col_t,
                           int32_t* dep, GiantSets gs, const int32_t* ctrl);
-__global__ void k_sources(int32_t L, const int32_t* dep, int32_t* src_list, int32_t* ctrl,
-                          unsigned long long* stats);
+__global__ void k_sources(int32_t L, const int32_t* dep, const int32_t* perm, const int64_t* rp,
+                          int32_t small_max, int32_t* tsz, int32_t* src_list, int32_t* qb,
+                          int32_t* ctrl, unsigned long long* stats);
 __global__ void k_trade(TradeArgs A);
 __global__ void k_check_giants_empty(int64_t total_sb, const int32_t* sc, int32_t* ctrl);
 __global__ void k_check_rows(int64_t n, const int64_t* rp, const int32_t* out_cur,

@@ -237,23 +237,40 @@ __global__ void k_check_giants_empty(int64_t total_sb, const int32_t* sc, int32_
     }
 }
 
-__global__ void k_sources(int32_t L, const int32_t* dep, int32_t* src_list, int32_t* ctrl,
-                          unsigned long long* stats) {
+// Per trade: its size deg u + deg v, and whether it is a source (no
+// dependency). Small sources go to the source list of the wavefront workers;
+// large ones straight into the workgroup queues.
+__global__ void k_sources(int32_t L, const int32_t* dep, const int32_t* perm, const int64_t* rp,
+                          int32_t small_max, int32_t* tsz, int32_t* src_list, int32_t* qb,
+                          int32_t* ctrl, unsigned long long* stats) {
   if (ctrl[cw(kCwErr)]) return;
   const int32_t stride = gridDim.x * blockDim.x;
-  // trip count is uniform across a wavefront (ballot below)
+  // trip count is uniform across a wavefront (ballots below)
   for (int32_t base = blockIdx.x * blockDim.x; base < L; base += stride) {
     const int32_t k = base + threadIdx.x;
-    const bool src = k < L && dep[k] == 0;
-    const uint64_t m = ballot(src);
-    if (m == 0) continue;
-    int32_t pos = 0;
+    int32_t s = 0;
+    bool src = false;
+    if (k < L) {
+      const int32_t u = perm[2 * k], v = perm[2 * k + 1];
+      s = (int32_t)((rp[u + 1] - rp[u]) + (rp[v + 1] - rp[v]));
+      tsz[k] = s;
+      src = dep[k] == 0;
+    }
+    const bool big = src && s > small_max;
+    const uint64_t ms = ballot(src && !big);
+    const uint64_t mb = ballot(big);
+    if ((ms | mb) == 0) continue;
+    int32_t pos = 0, posb = 0;
+    const int shard = (int)((uint32_t)base / 64u) % kQbShards;
     if (lane_id() == 0) {
-      pos = atomic_add(&ctrl[cw(kCwSrcCount)], popc64(m));
-      atomicAdd(&stats[kStatSources], (unsigned long long)popc64(m));
+      if (ms) pos = atomic_add(&ctrl[cw(kCwSrcCount)], popc64(ms));
+      if (mb) posb = atomic_add(&ctrl[cw(kCwQbTail0 + shard)], popc64(mb));
+      atomicAdd(&stats[kStatSources], (unsigned long long)popc64(ms | mb));
     }
     pos = wave_bcast(pos, 0);
-    if (src) src_list[pos + rank_below(m)] = k;
+    posb = wave_bcast(posb, 0);
+    if (src && !big) src_list[pos + rank_below(ms)] = k;
+    if (big) qb[(int64_t)shard * L + posb + rank_below(mb)] = k;
   }
 }
 

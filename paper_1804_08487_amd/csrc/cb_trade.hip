@@ -57,6 +57,7 @@ __device__ __forceinline__ int32_t tag_trade(uint32_t tag) { return (int32_t)((t
 struct WaveLds {
   uint64_t E[kSmallCap];
   int32_t D[kSmallCap];
+  uint16_t R[kSmallCap / 2];   // swap partners of the split, one per step
   int32_t stack[kStackCap];
 };
 
@@ -71,11 +72,19 @@ struct BigLds {
   int32_t scan[kWavesPerBlock + 1];
   int32_t next;
   int32_t cnt[4];
+  int32_t own_cp[2];   // shared / partner entries per side that are final now
+  int32_t emit_d;      // disjoint entries that are final now
+  int32_t emit_lo;     // ... of which on the smaller side of the split
+  uint32_t gen;        // generation of this workgroup's current write job
   int32_t base[2];
   int32_t ndone;
-  int32_t sboff[kTradeBlock];   // giant extraction: output offset per superblock
-  int32_t sbcnt[kTradeBlock];   // giant extraction: members per superblock
+  // giant extraction: output offset and members per superblock; the split
+  // reuses both as one buffer of 2 * kTradeBlock swap partners
+  int32_t sboff[kTradeBlock];
+  int32_t sbcnt[kTradeBlock];
 };
+static_assert(offsetof(BigLds, sbcnt) == offsetof(BigLds, sboff) + kTradeBlock * sizeof(int32_t),
+              "split buffer spans sboff and sbcnt");
 
 union TradeLds {
   WaveLds wave[kWavesPerBlock];
@@ -92,23 +101,71 @@ __device__ __forceinline__ void raise_error(const TradeArgs& A, int32_t bits, in
   store_agent(&A.ctrl[cw(kCwAbort)], 1);
 }
 
-// Split of the ascending disjoint set (indices into the entry array) in
-// place; u receives D[0..a), v receives D[a..N).
-template <typename Idx>
-__device__ __forceinline__ void split_serial(Idx* D, int64_t N, int64_t a, uint64_t seed,
-                                             uint32_t round, int32_t k) {
-  if (a <= N - a) {
-    for (int64_t j = 0; j < a; ++j) {
-      const uint64_t x = philox64(seed, (uint32_t)k, round, (uint32_t)j, kTagSplit);
-      const int64_t r = j + (int64_t)bounded(x, (uint64_t)(N - j));
-      const Idx t = D[j]; D[j] = D[r]; D[r] = t;
+// Split of the ascending disjoint set D (N indices into the entry array) in
+// place; u receives D[0..a), v receives D[a..N). Partial Durstenfeld shuffle
+// of the smaller side (Sec. 4, trade procedure): with T = min(a, N - a)
+// steps t = 0..T-1 at position j(t) = t (a <= N - a) or N - 1 - t (else),
+// swapping D[j] with D[partner(t)], partner drawn from
+// philox64(seed; k, round, j, split tag). The draws do not depend on the
+// swaps, so they are computed in parallel first; only the swaps run in
+// order, on one lane.
+__device__ __forceinline__ int32_t split_steps(int32_t N, int32_t a) { return a <= N - a ? a : N - a; }
+
+__device__ __forceinline__ int32_t split_partner(int32_t N, int32_t a, int32_t t, uint64_t seed,
+                                                 uint32_t round, int32_t k) {
+  const bool fwd = a <= N - a;
+  const int32_t j = fwd ? t : N - 1 - t;
+  const uint64_t x = philox64(seed, (uint32_t)k, round, (uint32_t)j, kTagSplit);
+  return fwd ? j + (int32_t)bounded(x, (uint64_t)(N - j)) : (int32_t)bounded(x, (uint64_t)(j + 1));
+}
+
+// Apply steps t0 .. t0+tc-1 given their partners R[0..tc) (single lane).
+template <typename Idx, typename RT>
+__device__ __forceinline__ void split_apply(Idx* D, int32_t N, int32_t a, int32_t t0, int32_t tc,
+                                            const RT* R) {
+  const bool fwd = a <= N - a;
+  int32_t t = 0;
+  for (; t + 4 <= tc; t += 4) {
+    int32_t r[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) r[q] = (int32_t)R[t + q];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int32_t j = fwd ? t0 + t + q : N - 1 - (t0 + t + q);
+      const Idx x = D[j], y = D[r[q]];
+      D[j] = y;
+      D[r[q]] = x;
     }
-  } else {
-    for (int64_t j = N - 1; j >= a; --j) {
-      const uint64_t x = philox64(seed, (uint32_t)k, round, (uint32_t)j, kTagSplit);
-      const int64_t r = (int64_t)bounded(x, (uint64_t)(j + 1));
-      const Idx t = D[j]; D[j] = D[r]; D[r] = t;
-    }
+  }
+  for (; t < tc; ++t) {
+    const int32_t j = fwd ? t0 + t : N - 1 - (t0 + t);
+    const int32_t rr = (int32_t)R[t];
+    const Idx x = D[j], y = D[rr];
+    D[j] = y;
+    D[rr] = x;
+  }
+}
+
+// One wavefront, N <= kSmallCap (so at most kSmallCap / 2 steps).
+__device__ void wave_split(int32_t* D, int32_t N, int32_t a, uint64_t seed, uint32_t round,
+                           int32_t k, uint16_t* R) {
+  const int32_t T = split_steps(N, a);
+  for (int32_t t = lane_id(); t < T; t += kWave) R[t] = (uint16_t)split_partner(N, a, t, seed, round, k);
+  wave_sync();
+  if (lane_id() == 0) split_apply<int32_t, uint16_t>(D, N, a, 0, T, R);
+  wave_sync();
+}
+
+// Whole workgroup; the partners go through R (cap entries) in chunks.
+__device__ void block_split(int32_t* D, int32_t N, int32_t a, uint64_t seed, uint32_t round,
+                            int32_t k, int32_t* R, int32_t cap) {
+  const int32_t T = split_steps(N, a);
+  for (int32_t t0 = 0; t0 < T; t0 += cap) {
+    const int32_t tc = T - t0 < cap ? T - t0 : cap;
+    for (int32_t i = threadIdx.x; i < tc; i += blockDim.x) R[i] = split_partner(N, a, t0 + i, seed, round, k);
+    __syncthreads();
+    if (threadIdx.x == 0) split_apply<int32_t, int32_t>(D, N, a, t0, tc, R);
+    __syncthreads();
   }
 }
 
@@ -191,6 +248,199 @@ __device__ __forceinline__ void route_edge(const TradeArgs& A, int32_t owner, in
   }
 }
 
+// ============================================================ write phase of large trades
+
+constexpr int kBatch = 4;   // items per lane in flight in the write phase
+
+// Output items of a large trade after the split: D[0..nD) are the disjoint
+// entries (u receives positions below a), D[nD..s) the kept ones (shared
+// neighbours and the partner); item o is entry E[D[o]].
+struct ItemSrc {
+  const uint64_t* E;
+  const int32_t* D;
+  int32_t k, u, v, s, nD, a, du, dv;
+  int64_t bu, bv;
+};
+
+struct WriteCounts {   // per lane
+  unsigned long long fwd, emit, push;
+};
+
+template <bool kShared>
+__device__ __forceinline__ uint64_t item_entry(const ItemSrc& S, int32_t o) {
+  if (kShared)
+    return load_agent_u64(reinterpret_cast<const unsigned long long*>(S.E) + load_agent(&S.D[o]));
+  return S.E[S.D[o]];
+}
+
+// Write items first, first + step, ... below end (a wavefront handles kBatch
+// * 64 consecutive items per step): own-row entries at positions drawn from
+// own_ctr[0] (u) and own_ctr[1] (v), final entries of other rows, inbox
+// entries of later trades; each forwarded item then drops its target trade's
+// counter once this wave's writes are complete, and a trade that becomes
+// ready is queued. kShared: the arrays and own_ctr are in global memory,
+// written by another workgroup.
+template <bool kShared>
+__device__ void write_range(const TradeArgs& A, const ItemSrc& S, int32_t first, int32_t end,
+                            int32_t step, int32_t* own_ctr, WriteCounts& W) {
+  const int l = lane_id();
+  for (int32_t base = first; base < end; base += step) {
+    int32_t tx[kBatch], towner[kBatch], tp[kBatch];
+    uint32_t ttag[kBatch];
+    uint64_t mu[kBatch], mv[kBatch];
+    int32_t nu = 0, nv = 0;
+#pragma unroll
+    for (int r = 0; r < kBatch; ++r) {
+      const int32_t o = base + r * kWave + l;
+      tx[r] = -1;
+      tp[r] = 0;
+      ttag[r] = 0;
+      towner[r] = S.u;
+      if (o < end) {
+        const uint64_t e = item_entry<kShared>(S, o);
+        tx[r] = ent_node(e);
+        ttag[r] = ent_tag(e);
+        towner[r] = o < S.nD ? (o < S.a ? S.u : S.v) : (ent_side(e) ? S.v : S.u);
+      }
+      const bool own = tx[r] >= 0 && ttag[r] <= kTagPartner;
+      mu[r] = ballot(own && towner[r] == S.u);
+      mv[r] = ballot(own && towner[r] == S.v);
+      nu += popc64(mu[r]);
+      nv += popc64(mv[r]);
+      if (tx[r] >= 0 && ttag[r] == kTagEmit) tp[r] = atomic_add(&A.out_cur[tx[r]], 1);
+      else if (tx[r] >= 0 && ttag[r] >= 2u) tp[r] = atomic_add(&A.inbox_cur[tx[r]], 1);
+    }
+    int32_t pu = 0, pv = 0;
+    if (l == 0) {
+      if (kShared) {
+        if (nu) pu = atomic_add(&own_ctr[0], nu);
+        if (nv) pv = atomic_add(&own_ctr[1], nv);
+      } else {
+        if (nu) pu = atomicAdd(&own_ctr[0], nu);
+        if (nv) pv = atomicAdd(&own_ctr[1], nv);
+      }
+    }
+    pu = wave_bcast(pu, 0);
+    pv = wave_bcast(pv, 0);
+    bool fwd[kBatch];
+#pragma unroll
+    for (int r = 0; r < kBatch; ++r) {
+      fwd[r] = false;
+      const bool ou = (mu[r] >> l) & 1ull, ov = (mv[r] >> l) & 1ull;
+      if (ou || ov) {
+        const int32_t p = ou ? pu + rank_below(mu[r]) : pv + rank_below(mv[r]);
+        if (p < (ou ? S.du : S.dv)) A.col_out[(ou ? S.bu : S.bv) + p] = tx[r];
+        else raise_error(A, kErrOut, S.k, -2 - towner[r]);
+      }
+      pu += popc64(mu[r]);
+      pv += popc64(mv[r]);
+      if (tx[r] < 0 || ttag[r] == kTagPartner) continue;
+      const int64_t rx = A.rp[tx[r]];
+      const int32_t dx = (int32_t)(A.rp[tx[r] + 1] - rx);
+      if (tp[r] >= dx) { raise_error(A, ttag[r] == kTagEmit ? kErrOut : kErrInbox, S.k, tx[r]); continue; }
+      if (ttag[r] == kTagEmit) {
+        A.col_out[rx + tp[r]] = towner[r];
+        W.emit += 1;
+      } else {
+        if (ttag[r] & kTagGiant) giant_insert(A.gs, A.gs.giant_id[tx[r]], towner[r]);
+        else store_agent(&A.inbox[rx + tp[r]], towner[r]);
+        fwd[r] = true;
+        W.fwd += 1;
+      }
+    }
+    // this wave's inbox and bitmap writes are complete before any counter
+    // they unlock
+    publish_wait();
+    int32_t old[kBatch];
+#pragma unroll
+    for (int r = 0; r < kBatch; ++r)
+      if (fwd[r]) old[r] = atomic_add(&A.dep[tag_trade(ttag[r])], -1);
+#pragma unroll
+    for (int r = 0; r < kBatch; ++r) {
+      if (!fwd[r]) continue;
+      const int32_t t = tag_trade(ttag[r]);
+      if (old[r] <= 0) raise_error(A, kErrDep, t, S.k);
+      if (old[r] == 1) {
+        const bool big = A.tsz[t] > A.small_max;
+        if (A.trace) {
+          A.trace[kTraceFields * (int64_t)t] = (int64_t)now_ticks();
+          A.trace[kTraceFields * (int64_t)t + 3] = S.k;
+        }
+        const int sh = (int)((blockIdx.x * 7 + threadIdx.x) % kQsShards);
+        if (big) queue_push(A, A.qb, kCwQbTail0, sh % kQbShards, t);
+        else queue_push(A, A.qs, kCwQsTail0, sh, t);
+        W.push += 1;
+      }
+    }
+  }
+}
+
+// Claim a chunk of the write job (single lane). The ticket only grows
+// within a generation, so a claim is one fetch-and-add; its result names the
+// generation and chunk taken (a chunk at or beyond the job's count is
+// nothing). A claim that lands just after the owner opened a newer
+// generation takes a chunk of that one, whose fields are already published.
+__device__ __forceinline__ unsigned long long claim_chunk(HelpJob* J) {
+  return __hip_atomic_fetch_add(&J->t.ticket, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int32_t* job_mask(const TradeArgs& A, int owner) {
+  return &A.ctrl[cw(owner < 32 ? kCwJobMask0 : kCwJobMask1)];
+}
+
+// Helper groups: workgroup b helps only the jobs of owners j with
+// j % kHelpGroups == b % kHelpGroups, so a job is shared by a bounded set of
+// workgroups and claims of different jobs do not meet on one word.
+constexpr int kHelpGroups = 8;
+
+// An idle wavefront of workgroup b writes one chunk of an open write job of
+// its group, if there is one.
+__device__ __forceinline__ bool try_help(const TradeArgs& A, int32_t b, WriteCounts& W) {
+  const int l = lane_id();
+  int32_t j = -1;
+  unsigned long long t = ~0ull;
+  if (l == 0) {
+    const uint64_t group = 0x0101010101010101ull << (b % kHelpGroups);
+    const uint64_t m = ((uint64_t)(uint32_t)load_agent(&A.ctrl[cw(kCwJobMask0)]) |
+                        ((uint64_t)(uint32_t)load_agent(&A.ctrl[cw(kCwJobMask1)]) << 32)) & group;
+    if (m) {
+      // spread the waves of one workgroup over the open jobs of its group
+      const int rot = (int)((threadIdx.x >> 6) * 8) & 63;
+      const uint64_t rm = rot ? ((m >> rot) | (m << (64 - rot))) : m;
+      j = (int32_t)((__builtin_ctzll(rm) + rot) & 63);
+      t = claim_chunk(A.jobs + j);
+    }
+  }
+  j = wave_bcast(j, 0);
+  if (j < 0) return false;
+  const int32_t c = wave_bcast((int32_t)(uint32_t)t, 0);
+  consume_order();
+  HelpJob* J = A.jobs + j;
+  // the fields of the claimed generation stay put until this chunk is reported
+  const int32_t nchunks = load_agent(&J->f.nchunks);
+  if (c >= nchunks) return false;
+  const uint64_t* slot = A.slots + (int64_t)j * A.slot_elems;
+  ItemSrc S;
+  S.E = slot + load_agent64(&J->f.e_off);
+  S.D = reinterpret_cast<const int32_t*>(slot + 2 * A.smax);
+  S.k = load_agent(&J->f.k);
+  S.u = load_agent(&J->f.u);
+  S.v = load_agent(&J->f.v);
+  S.s = load_agent(&J->f.s);
+  S.nD = load_agent(&J->f.nD);
+  S.a = load_agent(&J->f.a);
+  S.du = load_agent(&J->f.du);
+  S.dv = load_agent(&J->f.dv);
+  S.bu = load_agent64(&J->f.bu);
+  S.bv = load_agent64(&J->f.bv);
+  const int32_t first = c * kHelpChunk;
+  const int32_t end = first + kHelpChunk < S.s ? first + kHelpChunk : S.s;
+  write_range<true>(A, S, first, end, kWave * kBatch, J->c.own, W);
+  publish_wait();
+  if (l == 0) atomic_add(&J->c.done, 1);
+  return true;
+}
+
 // ============================================================ small trades
 
 struct WaveState {
@@ -200,10 +450,11 @@ struct WaveState {
   unsigned long long n_small, n_push, work, fwd, emit, ticks;
 };
 
-// Drops the dependency counters of later trades reached by this trade's
-// output; ready trades go to the local stack or the global queue.
+// Drops the dependency counters of later trades reached by trade k's
+// output; a ready small trade goes to the local stack or the global queue,
+// a ready large one to the workgroup queues.
 __device__ __forceinline__ void wave_release_item(const TradeArgs& A, WaveLds& W, WaveState& S,
-                                                  bool fwd, uint32_t tag) {
+                                                  bool fwd, uint32_t tag, int32_t k) {
   bool ready = false;
   int32_t t = -1;
   if (fwd) {
@@ -212,17 +463,25 @@ __device__ __forceinline__ void wave_release_item(const TradeArgs& A, WaveLds& W
     if (old <= 0) raise_error(A, kErrDep, t, -1 - old);
     ready = old == 1;
   }
-  const uint64_t m = ballot(ready);
-  if (m == 0) return;
+  if (ballot(ready) == 0) return;
+  bool big = false;
+  if (ready) {
+    big = A.tsz[t] > A.small_max;
+    if (A.trace) {
+      A.trace[kTraceFields * (int64_t)t] = (int64_t)now_ticks();
+      A.trace[kTraceFields * (int64_t)t + 3] = k;
+    }
+  }
+  const bool keep = ready && !big;
+  const uint64_t m = ballot(keep);
   const int cnt = popc64(m);
   const int room = A.stack_cap - S.top;
   const int r = rank_below(m);
-  const uint64_t spill = ballot(ready && r >= room);
+  const uint64_t spill = ballot((keep && r >= room) || big);
   if (spill) publish_wait();
-  if (ready) {
-    if (r < room) W.stack[S.top + r] = t;
-    else queue_push(A, A.qs, kCwQsTail0, S.shard, t);
-  }
+  if (keep && r < room) W.stack[S.top + r] = t;
+  else if (keep) queue_push(A, A.qs, kCwQsTail0, S.shard, t);
+  else if (big) queue_push(A, A.qb, kCwQbTail0, S.shard % kQbShards, t);
   wave_sync();
   S.top += cnt < room ? cnt : (room > 0 ? room : 0);
   S.n_push += (unsigned long long)popc64(spill);
@@ -284,10 +543,11 @@ __device__ void small_trade(const TradeArgs& A, int32_t k, int32_t u, int32_t v,
     a += popc64(ballot(isD && side == 0));
   }
   wave_sync();
-  if (l == 0) split_serial<int32_t>(W.D, nD, a, A.seed, A.round, k);
-  wave_sync();
+  wave_split(W.D, nD, a, A.seed, A.round, k, W.R);
 
-  // ---- write: own-row finals, other-row finals, forwards
+  // ---- write: own-row finals, other-row finals, forwards; each chunk's
+  // forwards then drop their target trades' counters once the chunk's
+  // writes are complete
   int32_t nfwd = 0, nemit = 0;
 #pragma unroll
   for (int pass = 0; pass < 2; ++pass) {
@@ -330,33 +590,14 @@ __device__ void small_trade(const TradeArgs& A, int32_t k, int32_t u, int32_t v,
         if (p < dd) A.col_out[(owner == u ? bu : bv) + p] = x; else raise_error(A, kErrOut, k, -2 - owner);
       }
       if (valid) route_edge(A, owner, x, tag, k);
-      nfwd += popc64(ballot(valid && tag >= 2u));
+      const bool fwd = valid && tag >= 2u;
+      const uint64_t mf = ballot(fwd);
+      nfwd += popc64(mf);
       nemit += popc64(ballot(valid && tag == kTagEmit));
-    }
-  }
-  // every write above is visible before any counter it unlocks
-  publish_wait();
-#pragma unroll
-  for (int pass = 0; pass < 2; ++pass) {
-    const int32_t count = pass ? nD : s;
-    for (int32_t c = 0; c < count; c += kWave) {
-      const int32_t o = c + l;
-      bool fwd = false;
-      uint32_t tag = 0;
-      if (o < count) {
-        if (pass == 0) {
-          const uint64_t e = W.E[o];
-          const int32_t x = ent_node(e);
-          tag = ent_tag(e);
-          const bool isC = tag != kTagPartner && ((o > 0 && ent_node(W.E[o - 1]) == x) ||
-                                                  (o + 1 < s && ent_node(W.E[o + 1]) == x));
-          fwd = isC && tag >= 2u;
-        } else {
-          tag = ent_tag(W.E[W.D[o]]);
-          fwd = tag >= 2u;
-        }
+      if (mf) {
+        publish_wait();
+        wave_release_item(A, W, S, fwd, tag, k);
       }
-      wave_release_item(A, W, S, fwd, tag);
     }
   }
   S.n_small += 1;
@@ -381,7 +622,7 @@ __device__ void wave_flush(const TradeArgs& A, WaveState& S) {
 
 constexpr int32_t kFlushEvery = 32;   // trades between progress flushes
 
-__device__ void small_worker(const TradeArgs& A, WaveLds& W) {
+__device__ __forceinline__ void small_worker(const TradeArgs& A, WaveLds& W) {
   const int l = lane_id();
   const int32_t wid = (int32_t)(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6));
   WaveState S{};
@@ -427,7 +668,12 @@ __device__ void small_worker(const TradeArgs& A, WaveLds& W) {
     consume_order();
     const uint64_t t_start = now_ticks();
     small_trade(A, k, u, v, W, S);
-    S.ticks += now_ticks() - t_start;
+    const uint64_t t_end = now_ticks();
+    S.ticks += t_end - t_start;
+    if (A.trace && l == 0) {
+      A.trace[kTraceFields * (int64_t)k + 1] = (int64_t)t_start;
+      A.trace[kTraceFields * (int64_t)k + 2] = (int64_t)t_end;
+    }
     S.ndone += 1;
     if (S.ndone >= kFlushEvery) wave_flush(A, S);
     int32_t ab = 0;
@@ -440,31 +686,6 @@ __device__ void small_worker(const TradeArgs& A, WaveLds& W) {
 // ============================================================ large trades
 // One workgroup per trade. Entries live in LDS when deg u + deg v <= kBigCap,
 // otherwise in this workgroup's global scratch slot (sorted by radix sort).
-
-// Output item o of a trade: o < s is entry o of the sorted list (used when it
-// is shared or the partner); o >= s is position o - s of the split disjoint
-// set. Returns false for entries that are not items.
-__device__ __forceinline__ bool trade_item(const uint64_t* E, const int32_t* D, int32_t s, int32_t a,
-                                           int32_t u, int32_t v, int32_t o, int32_t* owner,
-                                           int32_t* x, uint32_t* tag) {
-  uint64_t e;
-  if (o < s) {
-    e = E[o];
-    const int32_t nx = ent_node(e);
-    const bool isP = ent_tag(e) == kTagPartner;
-    const bool isC = !isP && ((o > 0 && ent_node(E[o - 1]) == nx) ||
-                              (o + 1 < s && ent_node(E[o + 1]) == nx));
-    if (!isP && !isC) return false;
-    *owner = ent_side(e) ? v : u;
-  } else {
-    const int32_t j = o - s;
-    e = E[D[j]];
-    *owner = j < a ? u : v;
-  }
-  *x = ent_node(e);
-  *tag = ent_tag(e);
-  return true;
-}
 
 // Collect one list of trade k (in any order): the round-start neighbours of
 // later trades (plus partner and left-out node) from the CSR row, then the
@@ -582,10 +803,10 @@ __device__ bool extract_giant(const TradeArgs& A, int32_t k, int32_t gi, int sid
   return true;
 }
 
-constexpr int kBatch = 4;   // items per thread whose atomics are in flight together
+   // items per thread whose atomics are in flight together
 constexpr int kPer = 8;     // consecutive entries per thread in the classification scan
 
-__device__ void big_trade(const TradeArgs& A, int32_t k, BigLds& B, uint64_t* slot,
+__device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds& B, uint64_t* slot,
                           unsigned long long* counters) {
   const uint64_t t_begin = now_ticks();
   const int tid = threadIdx.x;
@@ -605,6 +826,7 @@ __device__ void big_trade(const TradeArgs& A, int32_t k, BigLds& B, uint64_t* sl
   int32_t* D = in_lds ? B.u.tile.D : (int32_t*)(slot + 2 * A.smax);
   const int32_t niu = load_agent(&A.inbox_cur[u]);
   const int32_t niv = load_agent(&A.inbox_cur[v]);
+  uint64_t t_lists = 0;
 
   if (giant) {
     // Both lists sorted separately (a giant's straight from its bitmap, the
@@ -630,6 +852,7 @@ __device__ void big_trade(const TradeArgs& A, int32_t k, BigLds& B, uint64_t* sl
       }
       __syncthreads();
     }
+    t_lists = now_ticks();
     // position in the merged list = own index + members of the other list
     // below; a non-giant list is searched in its LDS copy
     const int lds_side = (gu >= 0) == (gv >= 0) ? -1 : (gu >= 0 ? 1 : 0);
@@ -654,20 +877,25 @@ __device__ void big_trade(const TradeArgs& A, int32_t k, BigLds& B, uint64_t* sl
         return;
     }
     __syncthreads();
+    t_lists = now_ticks();
     if (in_lds) block_bitonic_sort(E, (uint32_t)s);
     else E = block_radix_sort<uint64_t>(E, slot + A.smax, s, A.keybits, B.u.R);
     __syncthreads();
   }
 
   const uint64_t t_gathered = now_ticks();
-  // ---- classify; compact the disjoint set (ascending); a = |A_u minus shared|
-  // Each thread takes kPer consecutive entries, so one workgroup scan covers
-  // kPer * blockDim entries.
+  // ---- classify: disjoint entries go to D[0..nD) in ascending order, kept
+  // ones (shared neighbours, partner) to D[nD..s) from the back; a = entries
+  // of u among the disjoint ones. Each thread takes kPer consecutive
+  // entries, so one workgroup scan covers kPer * blockDim entries.
   int32_t nD = 0, a = 0;
+  if (tid == 0) { B.own_cp[0] = 0; B.own_cp[1] = 0; B.emit_d = 0; B.emit_lo = 0; }
+  __syncthreads();
+  int32_t own_cp0 = 0, own_cp1 = 0, emit_d = 0;
   for (int32_t c = 0; c < s; c += nt * kPer) {
     const int32_t i0 = c + tid * kPer;
     int32_t nodes[kPer + 2];
-    uint32_t meta[kPer];   // bit 0: tag is partner, bit 1: side
+    uint32_t meta[kPer];   // bit 0: tag is partner, bit 1: side, bit 2: tag is emit
 #pragma unroll
     for (int r = 0; r < kPer + 2; ++r) {
       const int32_t i = i0 - 1 + r;
@@ -679,7 +907,8 @@ __device__ void big_trade(const TradeArgs& A, int32_t k, BigLds& B, uint64_t* sl
       meta[r] = 0;
       if (i < s) {
         const uint64_t e = E[i];
-        meta[r] = (ent_tag(e) == kTagPartner ? 1u : 0u) | ((uint32_t)ent_side(e) << 1);
+        meta[r] = (ent_tag(e) == kTagPartner ? 1u : 0u) | ((uint32_t)ent_side(e) << 1) |
+                  (ent_tag(e) == kTagEmit ? 4u : 0u);
       }
     }
     int32_t cnt = 0, cntu = 0;
@@ -694,123 +923,162 @@ __device__ void big_trade(const TradeArgs& A, int32_t k, BigLds& B, uint64_t* sl
         dmask |= 1u << r;
         ++cnt;
         if (!(meta[r] & 2u)) ++cntu;
+        if (meta[r] & 4u) ++emit_d;
+      } else if (isP || (meta[r] & 4u)) {
+        if (meta[r] & 2u) ++own_cp1; else ++own_cp0;
       }
     }
     int32_t tot;
     const int32_t pre = block_excl_scan(cnt | (cntu << 16), B.scan, &tot);
     int32_t pos = nD + (pre & 0xFFFF);
+    // entries before this thread's first: i0 (all earlier ones are placed)
+    int32_t kpos = (i0 < s ? i0 : s) - pos;
 #pragma unroll
-    for (int r = 0; r < kPer; ++r)
+    for (int r = 0; r < kPer; ++r) {
+      if (i0 + r >= s) break;
       if (dmask & (1u << r)) D[pos++] = i0 + r;
+      else D[s - 1 - kpos++] = i0 + r;
+    }
     nD += tot & 0xFFFF;
     a += tot >> 16;
   }
+  own_cp0 = wave_sum(own_cp0);
+  own_cp1 = wave_sum(own_cp1);
+  emit_d = wave_sum(emit_d);
+  if (lane_id() == 0) {
+    if (own_cp0) atomicAdd(&B.own_cp[0], own_cp0);
+    if (own_cp1) atomicAdd(&B.own_cp[1], own_cp1);
+    if (emit_d) atomicAdd(&B.emit_d, emit_d);
+  }
   __syncthreads();
-  if (tid == 0) split_serial<int32_t>(D, nD, a, A.seed, A.round, k);
-  if (tid == 0) { B.cnt[1] = 0; B.cnt[2] = 0; }
-  __syncthreads();
+  const uint64_t t_classified = now_ticks();
+  block_split(D, nD, a, A.seed, A.round, k, B.sboff, 2 * kTradeBlock);
+  // Own-row entries are reserved before anything is released: a later trade
+  // released below may emit into these two rows at once.
+  {
+    const bool lo_is_u = a <= nD - a;
+    int32_t ce = 0;
+    for (int32_t j = (lo_is_u ? 0 : a) + tid; j < (lo_is_u ? a : nD); j += nt)
+      ce += ent_tag(E[D[j]]) == kTagEmit ? 1 : 0;
+    ce = wave_sum(ce);
+    if (lane_id() == 0 && ce) atomicAdd(&B.emit_lo, ce);
+    __syncthreads();
+    if (tid == 0) {
+      const int32_t eu = lo_is_u ? B.emit_lo : B.emit_d - B.emit_lo;
+      const int32_t ou = B.own_cp[0] + eu, ov = B.own_cp[1] + (B.emit_d - eu);
+      B.own_cp[0] = ou;
+      B.own_cp[1] = ov;
+      // the own rows are untouched this round until now
+      if (ou && atomic_add(&A.out_cur[u], ou) != 0) raise_error(A, kErrOut, k, -2 - u);
+      if (ov && atomic_add(&A.out_cur[v], ov) != 0) raise_error(A, kErrOut, k, -2 - v);
+      B.cnt[1] = 0;
+      B.cnt[2] = 0;
+    }
+    __syncthreads();
+  }
 
   const uint64_t t_split = now_ticks();
-  // ---- write: own rows at positions from workgroup counters (no other trade
-  // writes these two rows before this one publishes), other rows and inboxes
-  // by batched atomics
-  const int32_t items = s + nD;
-  int32_t nfwd = 0, nemit = 0;
-  const int l = lane_id();
-  for (int32_t o0 = tid; o0 < items; o0 += nt * kBatch) {
-    int32_t tx[kBatch], towner[kBatch], tp[kBatch];
-    uint32_t ttag[kBatch];
-    bool own[kBatch];
-    int32_t nu = 0, nv = 0;
-    uint64_t mu[kBatch], mv[kBatch];
-#pragma unroll
-    for (int r = 0; r < kBatch; ++r) {
-      const int32_t o = o0 + r * nt;
-      tx[r] = -1;
-      tp[r] = 0;
-      if (!(o < items && trade_item(E, D, s, a, u, v, o, &towner[r], &tx[r], &ttag[r]))) tx[r] = -1;
-      own[r] = tx[r] >= 0 && ttag[r] <= kTagPartner;
-      mu[r] = ballot(own[r] && towner[r] == u);
-      mv[r] = ballot(own[r] && towner[r] == v);
-      nu += popc64(mu[r]);
-      nv += popc64(mv[r]);
-      if (tx[r] >= 0 && ttag[r] == kTagEmit) tp[r] = atomic_add(&A.out_cur[tx[r]], 1);
-      else if (tx[r] >= 0 && ttag[r] >= 2u) tp[r] = atomic_add(&A.inbox_cur[tx[r]], 1);
+  // ---- write and release (s items). Large trades open this phase to idle
+  // wavefronts of the whole kernel through their write job.
+  WriteCounts W{0, 0, 0};
+  const int w = tid >> 6;
+  ItemSrc S{E, D, k, u, v, s, nD, a, du, dv, bu, bv};
+  if (A.help_min == 0 || s < A.help_min || (int)blockIdx.x >= kMaxJobs) {
+    write_range<false>(A, S, w * kWave * kBatch, s, kWavesPerBlock * kWave * kBatch, B.cnt + 1, W);
+  } else {
+    // publish both arrays where other workgroups can read them
+    unsigned long long* Eg = reinterpret_cast<unsigned long long*>(in_lds ? slot : E);
+    int32_t* Dg = reinterpret_cast<int32_t*>(slot + 2 * A.smax);
+    for (int32_t i = tid; i < s; i += nt) {
+      store_agent_u64(&Eg[i], E[i]);
+      store_agent(&Dg[i], D[i]);
     }
-    int32_t bu_own = 0, bv_own = 0;
-    if (l == 0) {
-      if (nu) bu_own = atomicAdd(&B.cnt[1], nu);
-      if (nv) bv_own = atomicAdd(&B.cnt[2], nv);
+    publish_wait();
+    __syncthreads();
+    HelpJob* J = A.jobs + blockIdx.x;
+    const int32_t nchunks = (s + kHelpChunk - 1) / kHelpChunk;
+    if (tid == 0) {
+      store_agent64(&J->f.bu, bu);
+      store_agent64(&J->f.bv, bv);
+      store_agent64(&J->f.e_off, (int64_t)(reinterpret_cast<uint64_t*>(Eg) - slot));
+      store_agent(&J->f.k, k);
+      store_agent(&J->f.u, u);
+      store_agent(&J->f.v, v);
+      store_agent(&J->f.s, s);
+      store_agent(&J->f.nD, nD);
+      store_agent(&J->f.a, a);
+      store_agent(&J->f.du, du);
+      store_agent(&J->f.dv, dv);
+      store_agent(&J->f.nchunks, nchunks);
+      store_agent(&J->c.done, 0);
+      store_agent(&J->c.own[0], 0);
+      store_agent(&J->c.own[1], 0);
+      publish_wait();
+      const uint32_t gen = (uint32_t)(load_agent_u64(&J->t.ticket) >> 32) + 1u;
+      store_agent_u64(&J->t.ticket, (unsigned long long)gen << 32);
+      publish_wait();
+      atomic_or(job_mask(A, blockIdx.x), (int32_t)(1u << (blockIdx.x & 31)));
+      B.gen = gen;
     }
-    bu_own = wave_bcast(bu_own, 0);
-    bv_own = wave_bcast(bv_own, 0);
-#pragma unroll
-    for (int r = 0; r < kBatch; ++r) {
-      if (own[r]) {
-        const bool ou = towner[r] == u;
-        const int32_t p = ou ? bu_own + rank_below(mu[r]) : bv_own + rank_below(mv[r]);
-        if (p < (ou ? du : dv)) A.col_out[(ou ? bu : bv) + p] = tx[r];
-        else raise_error(A, kErrOut, k, -2 - towner[r]);
+    __syncthreads();
+    const uint32_t gen = B.gen;
+    S.E = reinterpret_cast<const uint64_t*>(Eg);
+    S.D = Dg;
+    for (;;) {
+      int32_t c = -1;
+      if (lane_id() == 0) {
+        const unsigned long long t = claim_chunk(J);
+        c = (uint32_t)(t >> 32) == gen && (int32_t)(uint32_t)t < nchunks ? (int32_t)(uint32_t)t : -1;
       }
-      bu_own += popc64(mu[r]);
-      bv_own += popc64(mv[r]);
-      if (tx[r] < 0 || ttag[r] == kTagPartner) continue;
-      const int64_t rx = A.rp[tx[r]];
-      const int32_t dx = (int32_t)(A.rp[tx[r] + 1] - rx);
-      if (tp[r] >= dx) { raise_error(A, ttag[r] == kTagEmit ? kErrOut : kErrInbox, k, tx[r]); continue; }
-      if (ttag[r] == kTagEmit) { A.col_out[rx + tp[r]] = towner[r]; ++nemit; }
-      else if (ttag[r] & kTagGiant) { giant_insert(A.gs, A.gs.giant_id[tx[r]], towner[r]); ++nfwd; }
-      else { store_agent(&A.inbox[rx + tp[r]], towner[r]); ++nfwd; }
+      c = wave_bcast(c, 0);
+      if (c < 0) break;
+      const int32_t first = c * kHelpChunk;
+      write_range<true>(A, S, first, first + kHelpChunk < s ? first + kHelpChunk : s, kWave * kBatch,
+                        J->c.own, W);
+      publish_wait();
+      if (lane_id() == 0) atomic_add(&J->c.done, 1);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      // every chunk is claimed: close the job, wait for the helpers
+      atomic_and(job_mask(A, blockIdx.x), (int32_t)~(1u << (blockIdx.x & 31)));
+      while (load_agent(&J->c.done) < nchunks) {
+        if (load_agent(&A.ctrl[cw(kCwAbort)])) break;
+        __builtin_amdgcn_s_sleep(2);
+      }
+      B.cnt[1] = load_agent(&J->c.own[0]);
+      B.cnt[2] = load_agent(&J->c.own[1]);
     }
   }
   __syncthreads();
   if (tid == 0) {
-    // the own rows start empty this round: anything else means an ordering bug
-    if (B.cnt[1] && atomic_add(&A.out_cur[u], B.cnt[1]) != 0) raise_error(A, kErrOut, k, -2 - u);
-    if (B.cnt[2] && atomic_add(&A.out_cur[v], B.cnt[2]) != 0) raise_error(A, kErrOut, k, -2 - v);
-  }
-  __syncthreads();
-  publish_wait();
-  const uint64_t t_written = now_ticks();
-
-  // ---- unlock later trades
-  for (int32_t o0 = tid; o0 < items; o0 += nt * kBatch) {
-    int32_t tt[kBatch], old[kBatch];
-#pragma unroll
-    for (int r = 0; r < kBatch; ++r) {
-      const int32_t o = o0 + r * nt;
-      int32_t owner, x;
-      uint32_t tag;
-      tt[r] = -1;
-      if (o < items && trade_item(E, D, s, a, u, v, o, &owner, &x, &tag) && tag >= 2u) {
-        tt[r] = tag_trade(tag);
-        old[r] = atomic_add(&A.dep[tt[r]], -1);
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < kBatch; ++r) {
-      if (tt[r] < 0) continue;
-      if (old[r] <= 0) raise_error(A, kErrDep, tt[r], k);
-      if (old[r] == 1) {
-        publish_wait();
-        queue_push(A, A.qs, kCwQsTail0, (int)((blockIdx.x * 7 + tid) % kQsShards), tt[r]);
-        counters[2] += 1;
-      }
-    }
-  }
-  if (tid == 0) {
+    if ((B.cnt[1] != B.own_cp[0] || B.cnt[2] != B.own_cp[1]) && !load_agent(&A.ctrl[cw(kCwAbort)]))
+      raise_error(A, kErrOut, k, -1);
     counters[0] += (unsigned long long)s;
     counters[4] += t_gathered - t_begin;
     counters[5] += t_split - t_gathered;
-    counters[6] += t_written - t_split;
-    counters[7] += now_ticks() - t_written;
+    counters[6] += now_ticks() - t_split;
+    if (A.trace) {
+      int64_t* T = A.trace + kTraceFields * (int64_t)k;
+      T[4] = (int64_t)t_lists;
+      T[5] = (int64_t)t_gathered;
+      T[6] = (int64_t)t_classified;
+      T[7] = (int64_t)t_split;
+      T[8] = s;
+      T[9] = giant ? 1 : (in_lds ? 2 : 3);
+      T[10] = du;
+      T[11] = dv;
+      T[12] = nD;
+      T[13] = a;
+    }
   }
-  counters[1] += (unsigned long long)nfwd;
-  counters[3] += (unsigned long long)nemit;
+  counters[1] += W.fwd;
+  counters[2] += W.push;
+  counters[3] += W.emit;
   __syncthreads();
 }
 
-__device__ void big_worker(const TradeArgs& A, BigLds& B) {
+__device__ __forceinline__ void big_worker(const TradeArgs& A, BigLds& B) {
   const int tid = threadIdx.x;
   uint64_t* slot = A.slots + (int64_t)blockIdx.x * A.slot_elems;
   // per-thread partial counters: work, forwarded, pushes, emitted, then
@@ -840,16 +1108,30 @@ __device__ void big_worker(const TradeArgs& A, BigLds& B) {
     __syncthreads();
     if (k == -2) break;
     if (k < 0) {
-      idle_backoff(backoff);
-      backoff = backoff < 16 ? backoff * 2 : 16;
+      WriteCounts H{0, 0, 0};
+      const bool helped = try_help(A, (int32_t)blockIdx.x, H);
+      counters[1] += H.fwd;
+      counters[2] += H.push;
+      counters[3] += H.emit;
+      if (helped) {
+        backoff = 1;
+      } else {
+        idle_backoff(backoff);
+        backoff = backoff < 16 ? backoff * 2 : 16;
+      }
       continue;
     }
     backoff = 1;
     consume_order();
     const uint64_t t0 = now_ticks();
     big_trade(A, k, B, slot, counters);
-    const uint64_t dt = now_ticks() - t0;
+    const uint64_t t1 = now_ticks();
+    const uint64_t dt = t1 - t0;
     if (dt > max_ticks) max_ticks = dt;
+    if (A.trace && tid == 0) {
+      A.trace[kTraceFields * (int64_t)k + 1] = (int64_t)t0;
+      A.trace[kTraceFields * (int64_t)k + 2] = (int64_t)t1;
+    }
     if (tid == 0) {
       atomic_add(&A.ctrl[cw(kCwDone)], 1);
       n_big += 1;

@@ -51,7 +51,11 @@ TIERS = {"default": {}, "all_workgroup": {cb.OPT_SMALL_MAX: 0},
          "no_stack": {cb.OPT_LOCAL_STACK: 0},
          "giant8": {cb.OPT_GIANT_DEG: 8},
          "giant8_all_workgroup": {cb.OPT_GIANT_DEG: 8, cb.OPT_SMALL_MAX: 0},
-         "giant40_global": {cb.OPT_GIANT_DEG: 40, cb.OPT_BIG_LDS_MAX: 0}}
+         "giant40_global": {cb.OPT_GIANT_DEG: 40, cb.OPT_BIG_LDS_MAX: 0},
+         "help_all": {cb.OPT_SMALL_MAX: 0, cb.OPT_HELP_MIN: 1},
+         "help_global": {cb.OPT_SMALL_MAX: 0, cb.OPT_BIG_LDS_MAX: 0, cb.OPT_HELP_MIN: 1},
+         "help_giant8": {cb.OPT_GIANT_DEG: 8, cb.OPT_SMALL_MAX: 0, cb.OPT_HELP_MIN: 1},
+         "no_help": {cb.OPT_SMALL_MAX: 0, cb.OPT_HELP_MIN: 0}}
 
 
 def _run_and_compare(orc, rp, col, seed, rounds, options=None, form="o1"):
@@ -93,7 +97,8 @@ def _hub_graph():
     return graphgen.edge_list_to_csr(n, sorted(edges))
 
 
-@pytest.mark.parametrize("tier", ["default", "all_global", "all_workgroup", "giant8", "no_giant"])
+@pytest.mark.parametrize("tier", ["default", "all_global", "all_workgroup", "giant8", "no_giant",
+                                  "no_help", "help_all"])
 def test_hub_above_2_15_entries(orc, tier):
     """Regression: own-row counts of a side above 2^15 entries."""
     _say(f"hub graph tier {tier}")
@@ -135,7 +140,7 @@ def test_matching_and_depscan_match_oracle(orc):
 def test_small_workload_ten_rounds_every_round(orc):
     rp, col = graphgen.workload("small")
     _say(f"small workload n={len(rp)-1} m={len(col)//2}")
-    for tier in ("default", "all_workgroup", "mixed_global", "giant8"):
+    for tier in ("default", "all_workgroup", "mixed_global", "giant8", "help_all"):
         _run_and_compare(orc, rp, col, seed=1, rounds=10, options=TIERS[tier])
 
 
