@@ -114,7 +114,7 @@ template <> __device__ __forceinline__ uint32_t radix_key<int32_t>(int32_t e) { 
 // s elements each). Returns the buffer that holds the sorted sequence.
 // Workgroup-wide (blockDim a multiple of 64, at most 1024); barriers inside.
 template <typename T>
-__device__ T* block_radix_sort(T* a, T* b, int64_t s, int keybits, RadixLds& R) {
+__device__ __forceinline__ T* block_radix_sort(T* a, T* b, int64_t s, int keybits, RadixLds& R) {
   const int tid = threadIdx.x;
   const int w = tid >> 6;
   const int nw = blockDim.x >> 6;

@@ -50,7 +50,7 @@ enum Stat : int {
 constexpr int kSmallCap = 512;        // largest deg u + deg v on one wavefront
 constexpr int kBigCap = 12288;        // largest deg u + deg v held in LDS by one workgroup
 constexpr int kGiantMinDeg = kBigCap / 2;   // default giant degree: any other pair fits LDS
-constexpr int kTradeBlock = 1024;     // threads per trade-kernel workgroup
+constexpr int kTradeBlock = 512;      // threads per trade-kernel workgroup (one per CU: 256 VGPRs each)
 constexpr int kWavesPerBlock = kTradeBlock / 64;
 constexpr int kStackCap = 16;         // ready trades a wavefront may keep
 constexpr int kTraceFields = 16;      // int64 per trade of the optional trace

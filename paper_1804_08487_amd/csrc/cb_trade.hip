@@ -147,7 +147,7 @@ __device__ __forceinline__ void split_apply(Idx* D, int32_t N, int32_t a, int32_
 }
 
 // One wavefront, N <= kSmallCap (so at most kSmallCap / 2 steps).
-__device__ void wave_split(int32_t* D, int32_t N, int32_t a, uint64_t seed, uint32_t round,
+__device__ __forceinline__ void wave_split(int32_t* D, int32_t N, int32_t a, uint64_t seed, uint32_t round,
                            int32_t k, uint16_t* R) {
   const int32_t T = split_steps(N, a);
   for (int32_t t = lane_id(); t < T; t += kWave) R[t] = (uint16_t)split_partner(N, a, t, seed, round, k);
@@ -157,7 +157,7 @@ __device__ void wave_split(int32_t* D, int32_t N, int32_t a, uint64_t seed, uint
 }
 
 // Whole workgroup; the partners go through R (cap entries) in chunks.
-__device__ void block_split(int32_t* D, int32_t N, int32_t a, uint64_t seed, uint32_t round,
+__device__ __forceinline__ void block_split(int32_t* D, int32_t N, int32_t a, uint64_t seed, uint32_t round,
                             int32_t k, int32_t* R, int32_t cap) {
   const int32_t T = split_steps(N, a);
   for (int32_t t0 = 0; t0 < T; t0 += cap) {
@@ -173,7 +173,7 @@ __device__ void block_split(int32_t* D, int32_t N, int32_t a, uint64_t seed, uin
 // reserves a slot with its shard's tail counter and fills it; a popper takes
 // a slot with a compare-and-swap on the head, waits for the fill, and
 // resets the slot to -1 so the queues are clean for the next round.
-__device__ int32_t queue_pop(const TradeArgs& A, int32_t* q, int shards, int head0, int tail0,
+__device__ __forceinline__ int32_t queue_pop(const TradeArgs& A, int32_t* q, int shards, int head0, int tail0,
                              int start) {
   for (int i = 0; i < shards; ++i) {
     const int sh = (start + i) % shards;
@@ -220,7 +220,7 @@ __device__ __forceinline__ void idle_backoff(int32_t level) {
 struct Watchdog {
   int32_t last_done;
   uint64_t since;
-  __device__ bool stalled(const TradeArgs& A, int32_t done) {
+  __device__ __forceinline__ bool stalled(const TradeArgs& A, int32_t done) {
     const uint64_t now = now_ticks();
     if (since == 0 || done != last_done) {
       last_done = done;
@@ -250,7 +250,7 @@ __device__ __forceinline__ void route_edge(const TradeArgs& A, int32_t owner, in
 
 // ============================================================ write phase of large trades
 
-constexpr int kBatch = 4;   // items per lane in flight in the write phase
+constexpr int kBatch = 8;   // items per lane in flight in the write phase
 
 // Output items of a large trade after the split: D[0..nD) are the disjoint
 // entries (u receives positions below a), D[nD..s) the kept ones (shared
@@ -281,7 +281,7 @@ __device__ __forceinline__ uint64_t item_entry(const ItemSrc& S, int32_t o) {
 // ready is queued. kShared: the arrays and own_ctr are in global memory,
 // written by another workgroup.
 template <bool kShared>
-__device__ void write_range(const TradeArgs& A, const ItemSrc& S, int32_t first, int32_t end,
+__device__ __forceinline__ void write_range(const TradeArgs& A, const ItemSrc& S, int32_t first, int32_t end,
                             int32_t step, int32_t* own_ctr, WriteCounts& W) {
   const int l = lane_id();
   for (int32_t base = first; base < end; base += step) {
@@ -487,7 +487,7 @@ __device__ __forceinline__ void wave_release_item(const TradeArgs& A, WaveLds& W
   S.n_push += (unsigned long long)popc64(spill);
 }
 
-__device__ void small_trade(const TradeArgs& A, int32_t k, int32_t u, int32_t v, WaveLds& W,
+__device__ __forceinline__ void small_trade(const TradeArgs& A, int32_t k, int32_t u, int32_t v, WaveLds& W,
                             WaveState& S) {
   const int l = lane_id();
   const int64_t bu = A.rp[u], bv = A.rp[v];
@@ -691,7 +691,7 @@ __device__ __forceinline__ void small_worker(const TradeArgs& A, WaveLds& W) {
 // later trades (plus partner and left-out node) from the CSR row, then the
 // arrivals from the inbox. Workgroup-wide; false (error raised) on a size
 // mismatch.
-__device__ bool gather_list(const TradeArgs& A, int32_t k, int64_t b, int32_t d, int32_t ni,
+__device__ __forceinline__ bool gather_list(const TradeArgs& A, int32_t k, int64_t b, int32_t d, int32_t ni,
                             int side, uint64_t* out, BigLds& B) {
   const int tid = threadIdx.x;
   if (tid == 0) B.cnt[0] = 0;
@@ -722,9 +722,9 @@ __device__ bool gather_list(const TradeArgs& A, int32_t k, int64_t b, int32_t d,
 // The bit pass is pure arithmetic (wave w takes 64 superblocks, four at a
 // time); the tags, which need one gather per member, follow in a separate
 // batched pass.
-__device__ bool extract_giant(const TradeArgs& A, int32_t k, int32_t gi, int side, int32_t d,
+__device__ __forceinline__ bool extract_giant(const TradeArgs& A, int32_t k, int32_t gi, int side, int32_t d,
                               uint64_t* out, BigLds& B) {
-  constexpr int kSbStep = 2;
+  constexpr int kSbStep = 8;
   const int tid = threadIdx.x;
   const int w = tid >> 6;
   const int l = lane_id();
