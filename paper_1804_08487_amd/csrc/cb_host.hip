@@ -81,6 +81,8 @@ struct cb_graph {
   int32_t* ctrl = nullptr;
   unsigned long long* stats = nullptr;
   uint64_t* slots = nullptr;
+  int32_t* sbpre = nullptr;
+  int64_t sbpre_stride = 1;
   int32_t* rows_small = nullptr;
   int32_t* rows_mid = nullptr;
   int32_t* rows_big = nullptr;
@@ -378,6 +380,8 @@ cb_status enqueue_round(cb_graph* g, uint64_t seed, uint32_t round, int last_ste
     A.stats = g->stats;
     A.slots = g->slots;
     A.slot_elems = g->slot_elems;
+    A.sbpre = g->sbpre;
+    A.sbpre_stride = g->sbpre_stride;
     A.smax = g->smax;
     A.n = n;
     A.L = L;
@@ -484,7 +488,8 @@ cb_status graph_upload(int64_t n, const int64_t* row_ptr, const int32_t* col, vo
   g->keybits_node = std::max(1, bitlen((uint64_t)std::max<int64_t>(n - 1, 1)));
   g->keybits_entry = std::max(1, bitlen((uint64_t)std::max<int64_t>(2 * n - 1, 1)));
   g->smax = std::max<int64_t>(d1 + d2, 1);
-  g->slot_elems = 2 * g->smax + g->smax / 2 + 1;
+  g->slot_elems = 3 * g->smax + g->smax / 2 + 1;
+  g->sbpre_stride = (n + 4095) / 4096 + 1;
   g->nbig_alloc = std::max(1, g->cu_count / 2);
 
   // size classes of the per-row rebuild (degrees never change)
@@ -513,6 +518,7 @@ cb_status graph_upload(int64_t n, const int64_t* row_ptr, const int32_t* col, vo
             alloc_into(g, &g->bstart, g->nb + 1) && alloc_into(g, &g->bcur, g->nb) &&
             alloc_into(g, &g->ctrl, kCtrlInts) && alloc_into(g, &g->stats, kStatCount) &&
             alloc_into(g, &g->slots, (int64_t)g->nbig_alloc * g->slot_elems) &&
+            alloc_into(g, &g->sbpre, (int64_t)g->nbig_alloc * g->sbpre_stride) &&
             alloc_into(g, &g->rows_small, g->n_small) && alloc_into(g, &g->rows_mid, g->n_mid) &&
             alloc_into(g, &g->rows_big, g->n_big);
   if (!ok) {

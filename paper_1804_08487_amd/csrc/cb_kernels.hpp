@@ -56,18 +56,21 @@ constexpr int kStackCap = 16;         // ready trades a wavefront may keep
 constexpr int kTraceFields = 16;      // int64 per trade of the optional trace
 constexpr int kMaxJobs = 64;          // workgroups that can open their write phase to helpers
 constexpr int32_t kHelpChunk = 1024;  // output items per claimed chunk
-constexpr int32_t kHelpMinItems = 8192;   // default: smaller trades write alone
+constexpr int32_t kHelpMinItems = 8192;   // default: smaller trades work alone
+constexpr int32_t kSbChunk = 16;      // bitmap superblocks per claimed extraction chunk
 
-// Write phase of one large trade, open to helper wavefronts (one per
-// workgroup worker, reused trade after trade). The owner publishes the
-// fields, then a new generation in the ticket; a wavefront claims chunk c of
-// generation g by moving the ticket from (g, c) to (g, c + 1), and reports it
-// in `done`. The fields of generation g stay unchanged until every chunk of
-// it is reported, so a successful claim guarantees that the fields read
-// before it belong to g.
+// A phase of one large trade open to helper wavefronts (one job per
+// workgroup worker, reused phase after phase): phase 1 extracts a giant
+// node's neighbour set from its bitmap, phase 2 writes the trade's output.
+// The owner publishes the fields, then the ticket of a new generation g with
+// n chunks; a wavefront claims chunk c by moving the ticket's counter from c
+// to c + 1, and the value it gets back alone says whether it holds a chunk
+// (c < n). The fields of g stay unchanged until every chunk of it is
+// reported in `done`, so a wavefront holding a chunk reads g's fields.
+constexpr int kTicketCountBits = 24;   // chunk counter and chunk count per ticket
 struct HelpJob {
   struct alignas(128) {
-    unsigned long long ticket;   // (generation << 32) | next chunk
+    unsigned long long ticket;   // generation (16 bits) | chunks (24) | next chunk (24)
   } t;
   struct alignas(128) {
     int32_t done;                // chunks written
@@ -75,8 +78,10 @@ struct HelpJob {
   } c;
   struct alignas(128) {
     int64_t bu, bv;              // row offsets of u and v
-    int64_t e_off;               // entry array = owner's slot + e_off
-    int32_t k, u, v, s, nD, a, du, dv, nchunks;
+    int64_t e_off;               // phase 2: entries at owner's slot + e_off;
+                                 // phase 1: output list there
+    int32_t k, u, v, s, nD, a, du, dv;
+    int32_t phase, gi, side, d;  // phase 1: giant id, side and size of the list
   } f;
 };
 constexpr int kMatchCap = 2048;       // bucket size sorted in LDS by k_match_sort
@@ -129,7 +134,9 @@ struct TradeArgs {
   unsigned long long* stats;
   GiantSets gs;
   uint64_t* slots;          // large-trade scratch, slot_elems u64 per workgroup
-  int64_t slot_elems;       // = 2 * smax + smax / 2 + 1
+  int64_t slot_elems;       // = 3 * smax + smax / 2 + 1: entries, lists, D, shared list
+  int32_t* sbpre;           // per workgroup: prefix of a giant's superblock counts
+  int64_t sbpre_stride;     // = superblocks + 1
   int64_t smax;             // largest possible deg u + deg v
   int64_t n;
   int32_t L;

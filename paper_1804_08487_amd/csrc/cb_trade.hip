@@ -75,7 +75,7 @@ struct BigLds {
   int32_t own_cp[2];   // shared / partner entries per side that are final now
   int32_t emit_d;      // disjoint entries that are final now
   int32_t emit_lo;     // ... of which on the smaller side of the split
-  uint32_t gen;        // generation of this workgroup's current write job
+  int32_t flag;        // workgroup-wide decision
   int32_t base[2];
   int32_t ndone;
   // giant extraction: output offset and members per superblock; the split
@@ -375,17 +375,165 @@ __device__ __forceinline__ void write_range(const TradeArgs& A, const ItemSrc& S
   }
 }
 
-// Claim a chunk of the write job (single lane). The ticket only grows
-// within a generation, so a claim is one fetch-and-add; its result names the
-// generation and chunk taken (a chunk at or beyond the job's count is
-// nothing). A claim that lands just after the owner opened a newer
-// generation takes a chunk of that one, whose fields are already published.
-__device__ __forceinline__ unsigned long long claim_chunk(HelpJob* J) {
-  return __hip_atomic_fetch_add(&J->t.ticket, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Ticket fields.
+constexpr unsigned long long kTicketMask = (1ull << kTicketCountBits) - 1;
+__device__ __forceinline__ uint32_t ticket_gen(unsigned long long t) { return (uint32_t)(t >> (2 * kTicketCountBits)); }
+__device__ __forceinline__ int32_t ticket_chunks(unsigned long long t) { return (int32_t)((t >> kTicketCountBits) & kTicketMask); }
+__device__ __forceinline__ int32_t ticket_next(unsigned long long t) { return (int32_t)(t & kTicketMask); }
+
+// Claim a chunk of a job (single lane): the chunk index, or -1 when the job
+// has none left. A job whose chunks are all taken is not incremented again
+// except by claims racing with the last one.
+__device__ __forceinline__ int32_t claim_chunk(HelpJob* J) {
+  const unsigned long long seen = load_agent_u64(&J->t.ticket);
+  if (ticket_next(seen) >= ticket_chunks(seen)) return -1;
+  const unsigned long long t =
+      __hip_atomic_fetch_add(&J->t.ticket, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return ticket_next(t) < ticket_chunks(t) ? ticket_next(t) : -1;
 }
 
 __device__ __forceinline__ int32_t* job_mask(const TradeArgs& A, int owner) {
   return &A.ctrl[cw(owner < 32 ? kCwJobMask0 : kCwJobMask1)];
+}
+
+// Extraction of a giant's neighbour set shared with helper wavefronts is
+// switched off: a run with it on (every workgroup trade sharing its phases,
+// one giant node) did not finish and its cause is not found yet.
+constexpr bool kSharedExtraction = false;
+
+// Offset of the shared list (written only with agent-scope stores, by the
+// owner and by helpers) within a slot.
+__device__ __forceinline__ int64_t shared_list_off(const TradeArgs& A) { return 2 * A.smax + A.smax / 2 + 1; }
+
+// Open the calling workgroup's job, of nchunks chunks, with its fields
+// already stored (thread 0).
+__device__ __forceinline__ void open_job(const TradeArgs& A, HelpJob* J, int32_t nchunks) {
+  store_agent(&J->c.done, 0);
+  store_agent(&J->c.own[0], 0);
+  store_agent(&J->c.own[1], 0);
+  publish_wait();
+  const unsigned long long gen = (ticket_gen(load_agent_u64(&J->t.ticket)) + 1u) & 0xFFFFull;
+  store_agent_u64(&J->t.ticket, (gen << (2 * kTicketCountBits)) |
+                                    ((unsigned long long)nchunks << kTicketCountBits));
+  publish_wait();
+  atomic_or(job_mask(A, blockIdx.x), (int32_t)(1u << (blockIdx.x & 31)));
+}
+
+// Every chunk is claimed: close the job and wait for the helpers (thread 0).
+__device__ __forceinline__ void close_job(const TradeArgs& A, HelpJob* J, int32_t nchunks) {
+  atomic_and(job_mask(A, blockIdx.x), (int32_t)~(1u << (blockIdx.x & 31)));
+  while (load_agent(&J->c.done) < nchunks) {
+    if (load_agent(&A.ctrl[cw(kCwAbort)])) break;
+    __builtin_amdgcn_s_sleep(2);
+  }
+}
+
+// Phase 1 chunk c (one wavefront): the members of giant gi in superblocks
+// [c * kSbChunk, ...), as entries of `side` of trade k, at their positions
+// pre[j] + rank in X; their bitmap words and counts are cleared.
+__device__ __forceinline__ void extract_chunk(const TradeArgs& A, int32_t k, int32_t gi, int side,
+                                              int32_t nsb, const int32_t* pre, unsigned long long* X,
+                                              int32_t c) {
+  constexpr int kStep = 4;
+  const int l = lane_id();
+  unsigned long long* bm = A.gs.bm + (int64_t)gi * A.gs.gwords;
+  int32_t* sc = A.gs.sc + (int64_t)gi * nsb;
+  const int32_t sb0 = c * kSbChunk;
+  const int32_t sb1 = sb0 + kSbChunk < nsb ? sb0 + kSbChunk : nsb;
+  bool bad = false;
+  for (int32_t j0 = sb0; j0 < sb1; j0 += kStep) {
+    unsigned long long word[kStep];
+    int32_t lo[kStep], hi[kStep];
+#pragma unroll
+    for (int t = 0; t < kStep; ++t) {
+      const int32_t jj = j0 + t;
+      const bool valid = jj < sb1;
+      word[t] = valid ? load_agent_u64(&bm[(int64_t)jj * kWave + l]) : 0ull;
+      lo[t] = valid ? load_agent(&pre[jj]) : 0;
+      hi[t] = valid ? load_agent(&pre[jj + 1]) : 0;
+    }
+#pragma unroll
+    for (int t = 0; t < kStep; ++t) {
+      const int32_t jj = j0 + t;
+      if (jj >= sb1) break;
+      unsigned long long bits = word[t];
+      const int32_t pc = __popcll(bits);
+      const int32_t at = lo[t] + wave_incl_scan(pc) - pc;
+      if (wave_sum(pc) != hi[t] - lo[t]) bad = true;
+      const int64_t wi = (int64_t)jj * kWave + l;
+      if (bits) bm[wi] = 0ull;
+      int32_t idx = 0;
+      while (bits) {
+        const int bit = __builtin_ctzll(bits);
+        bits &= bits - 1;
+        const int32_t x = (int32_t)(wi * 64 + bit);
+        const int32_t ti = A.tinfo[x];
+        if (at + idx < hi[t]) store_agent_u64(&X[at + idx], make_entry(x, side, tag_of(ti, k)));
+        ++idx;
+      }
+      if (l == 0) sc[jj] = 0;
+    }
+  }
+  if (ballot(bad) && l == 0) raise_error(A, kErrGather, k, 4000000 + c);
+}
+
+// Giant gi's neighbour set (d members) as ascending entries of `side` of
+// trade k in the shared list of this workgroup's slot, extracted by this
+// workgroup and idle helper wavefronts. Workgroup-wide; false on an error.
+__device__ __forceinline__ bool extract_giant_shared(const TradeArgs& A, int32_t k, int32_t gi, int side,
+                                                     int32_t d, BigLds& B) {
+  const int tid = threadIdx.x;
+  const int nt = blockDim.x;
+  const int32_t nsb = (int32_t)(A.gs.gwords >> 6);
+  const int32_t* sc = A.gs.sc + (int64_t)gi * nsb;
+  int32_t* pre = A.sbpre + (int64_t)blockIdx.x * A.sbpre_stride;
+  int32_t carry = 0;
+  for (int32_t j0 = 0; j0 < nsb; j0 += nt) {
+    const int32_t j = j0 + tid;
+    const int32_t cnt = j < nsb ? load_agent(&sc[j]) : 0;
+    int32_t tot;
+    const int32_t p = block_excl_scan(cnt, B.scan, &tot);
+    if (j < nsb) store_agent(&pre[j], carry + p);
+    carry += tot;
+  }
+  if (carry != d) {
+    if (tid == 0) raise_error(A, kErrGather, k, 3000000 + carry - d);
+    return false;
+  }
+  if (tid == 0) store_agent(&pre[nsb], carry);
+  HelpJob* J = A.jobs + blockIdx.x;
+  const int32_t nchunks = (nsb + kSbChunk - 1) / kSbChunk;
+  publish_wait();
+  __syncthreads();
+  if (tid == 0) {
+    store_agent(&J->f.phase, 1);
+    store_agent(&J->f.k, k);
+    store_agent(&J->f.gi, gi);
+    store_agent(&J->f.side, side);
+    store_agent(&J->f.d, d);
+    store_agent64(&J->f.e_off, shared_list_off(A));
+    open_job(A, J, nchunks);
+  }
+  __syncthreads();
+  unsigned long long* X =
+      reinterpret_cast<unsigned long long*>(A.slots + (int64_t)blockIdx.x * A.slot_elems + shared_list_off(A));
+  for (;;) {
+    int32_t c = -1;
+    if (lane_id() == 0) c = claim_chunk(J);
+    c = wave_bcast(c, 0);
+    if (c < 0) break;
+    extract_chunk(A, k, gi, side, nsb, pre, X, c);
+    publish_wait();
+    if (lane_id() == 0) atomic_add(&J->c.done, 1);
+  }
+  __syncthreads();
+  // one decision for the whole workgroup: the abort word may change meanwhile
+  if (tid == 0) {
+    close_job(A, J, nchunks);
+    B.flag = load_agent(&A.ctrl[cw(kCwAbort)]);
+  }
+  __syncthreads();
+  return B.flag == 0;
 }
 
 // Helper groups: workgroup b helps only the jobs of owners j with
@@ -397,8 +545,7 @@ constexpr int kHelpGroups = 8;
 // its group, if there is one.
 __device__ __forceinline__ bool try_help(const TradeArgs& A, int32_t b, WriteCounts& W) {
   const int l = lane_id();
-  int32_t j = -1;
-  unsigned long long t = ~0ull;
+  int32_t j = -1, c = -1;
   if (l == 0) {
     const uint64_t group = 0x0101010101010101ull << (b % kHelpGroups);
     const uint64_t m = ((uint64_t)(uint32_t)load_agent(&A.ctrl[cw(kCwJobMask0)]) |
@@ -408,18 +555,25 @@ __device__ __forceinline__ bool try_help(const TradeArgs& A, int32_t b, WriteCou
       const int rot = (int)((threadIdx.x >> 6) * 8) & 63;
       const uint64_t rm = rot ? ((m >> rot) | (m << (64 - rot))) : m;
       j = (int32_t)((__builtin_ctzll(rm) + rot) & 63);
-      t = claim_chunk(A.jobs + j);
+      c = claim_chunk(A.jobs + j);
     }
   }
+  c = wave_bcast(c, 0);
+  if (c < 0) return false;
   j = wave_bcast(j, 0);
-  if (j < 0) return false;
-  const int32_t c = wave_bcast((int32_t)(uint32_t)t, 0);
   consume_order();
   HelpJob* J = A.jobs + j;
   // the fields of the claimed generation stay put until this chunk is reported
-  const int32_t nchunks = load_agent(&J->f.nchunks);
-  if (c >= nchunks) return false;
   const uint64_t* slot = A.slots + (int64_t)j * A.slot_elems;
+  if (load_agent(&J->f.phase) == 1) {
+    extract_chunk(A, load_agent(&J->f.k), load_agent(&J->f.gi), load_agent(&J->f.side),
+                  (int32_t)(A.gs.gwords >> 6), A.sbpre + (int64_t)j * A.sbpre_stride,
+                  reinterpret_cast<unsigned long long*>(const_cast<uint64_t*>(slot) + load_agent64(&J->f.e_off)),
+                  c);
+    publish_wait();
+    if (l == 0) atomic_add(&J->c.done, 1);
+    return true;
+  }
   ItemSrc S;
   S.E = slot + load_agent64(&J->f.e_off);
   S.D = reinterpret_cast<const int32_t*>(slot + 2 * A.smax);
@@ -829,19 +983,30 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
   uint64_t t_lists = 0;
 
   if (giant) {
-    // Both lists sorted separately (a giant's straight from its bitmap, the
-    // other in LDS), then merged into the slot.
-    uint64_t* L2 = slot + A.smax;   // u's list at [0, du), v's at [du, s)
+    // Both lists sorted separately (a giant's straight from its bitmap, a
+    // small other side in LDS), then merged into the slot. The larger giant
+    // side is extracted together with idle helper wavefronts into the shared
+    // list of the slot.
+    uint64_t* L2 = slot + A.smax;   // lists kept by this workgroup: u's at [0, du), v's at [du, s)
+    const unsigned long long* X = reinterpret_cast<const unsigned long long*>(slot + shared_list_off(A));
+    int xside = -1, lds_side = -1;
+    if (kSharedExtraction && A.help_min > 0 && (int)blockIdx.x < kMaxJobs) {
+      if (gu >= 0 && (gv < 0 || du >= dv)) xside = 0;
+      else if (gv >= 0) xside = 1;
+      if (xside >= 0 && (xside ? dv : du) < A.help_min) xside = -1;
+    }
     for (int side = 0; side < 2; ++side) {
       const int32_t gi = side ? gv : gu;
       const int32_t d = side ? dv : du;
       const int32_t off = side ? du : 0;
-      if (gi >= 0) {
+      if (side == xside) {
+        if (!extract_giant_shared(A, k, gi, side, d, B)) return;
+      } else if (gi >= 0) {
         if (!extract_giant(A, k, gi, side, d, L2 + off, B)) return;
       } else if (d <= kBigCap) {
         if (!gather_list(A, k, side ? bv : bu, d, side ? niv : niu, side, B.u.tile.E, B)) return;
         block_bitonic_sort(B.u.tile.E, (uint32_t)d);
-        for (int32_t i = tid; i < d; i += nt) L2[off + i] = B.u.tile.E[i];
+        lds_side = side;
       } else {
         // the other node is too large for LDS (giant degree set above kBigCap)
         if (!gather_list(A, k, side ? bv : bu, d, side ? niv : niu, side, L2 + off, B)) return;
@@ -853,21 +1018,22 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
       __syncthreads();
     }
     t_lists = now_ticks();
-    // position in the merged list = own index + members of the other list
-    // below; a non-giant list is searched in its LDS copy
-    const int lds_side = (gu >= 0) == (gv >= 0) ? -1 : (gu >= 0 ? 1 : 0);
-    const bool lds_ok = lds_side >= 0 && (lds_side ? dv : du) <= kBigCap;
+    auto list_at = [&](int sd, int32_t i) -> uint64_t {
+      if (sd == lds_side) return B.u.tile.E[i];
+      if (sd == xside) return load_agent_u64(&X[i]);
+      return L2[(sd ? du : 0) + i];
+    };
+    // position in the merged list = own index + members of the other list below
     for (int32_t i = tid; i < s; i += nt) {
-      const bool first = i < du;
-      const uint64_t e = L2[i];
-      const int other_side = first ? 1 : 0;
-      const uint64_t* other = (lds_ok && other_side == lds_side) ? B.u.tile.E : (first ? L2 + du : L2);
-      int32_t lo = 0, hi = first ? dv : du;
+      const int sd = i < du ? 0 : 1;
+      const int32_t idx = sd ? i - du : i;
+      const uint64_t e = list_at(sd, idx);
+      int32_t lo = 0, hi = sd ? du : dv;
       while (lo < hi) {
         const int32_t mid = (lo + hi) >> 1;
-        if (other[mid] < e) lo = mid + 1; else hi = mid;
+        if (list_at(1 - sd, mid) < e) lo = mid + 1; else hi = mid;
       }
-      E[(first ? i : i - du) + lo] = e;
+      E[idx + lo] = e;
     }
     __syncthreads();
   } else {
@@ -1009,27 +1175,15 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
       store_agent(&J->f.a, a);
       store_agent(&J->f.du, du);
       store_agent(&J->f.dv, dv);
-      store_agent(&J->f.nchunks, nchunks);
-      store_agent(&J->c.done, 0);
-      store_agent(&J->c.own[0], 0);
-      store_agent(&J->c.own[1], 0);
-      publish_wait();
-      const uint32_t gen = (uint32_t)(load_agent_u64(&J->t.ticket) >> 32) + 1u;
-      store_agent_u64(&J->t.ticket, (unsigned long long)gen << 32);
-      publish_wait();
-      atomic_or(job_mask(A, blockIdx.x), (int32_t)(1u << (blockIdx.x & 31)));
-      B.gen = gen;
+      store_agent(&J->f.phase, 2);
+      open_job(A, J, nchunks);
     }
     __syncthreads();
-    const uint32_t gen = B.gen;
     S.E = reinterpret_cast<const uint64_t*>(Eg);
     S.D = Dg;
     for (;;) {
       int32_t c = -1;
-      if (lane_id() == 0) {
-        const unsigned long long t = claim_chunk(J);
-        c = (uint32_t)(t >> 32) == gen && (int32_t)(uint32_t)t < nchunks ? (int32_t)(uint32_t)t : -1;
-      }
+      if (lane_id() == 0) c = claim_chunk(J);
       c = wave_bcast(c, 0);
       if (c < 0) break;
       const int32_t first = c * kHelpChunk;
@@ -1040,12 +1194,7 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
     }
     __syncthreads();
     if (tid == 0) {
-      // every chunk is claimed: close the job, wait for the helpers
-      atomic_and(job_mask(A, blockIdx.x), (int32_t)~(1u << (blockIdx.x & 31)));
-      while (load_agent(&J->c.done) < nchunks) {
-        if (load_agent(&A.ctrl[cw(kCwAbort)])) break;
-        __builtin_amdgcn_s_sleep(2);
-      }
+      close_job(A, J, nchunks);
       B.cnt[1] = load_agent(&J->c.own[0]);
       B.cnt[2] = load_agent(&J->c.own[1]);
     }
