@@ -121,26 +121,28 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <typename T>
-__device__ __forceinline__ T wave_bcast(T v, int src_lane) {
-  return __shfl(v, src_lane, kWave);
+// Value of a 32-bit variable in lane src_lane (the same for every lane).
+__device__ __forceinline__ int32_t wave_bcast(int32_t v, int src_lane) {
+  return __builtin_amdgcn_readlane(v, src_lane);
 }
 
-// Inclusive prefix sum across the wavefront.
+// Inclusive prefix sum across the wavefront (every lane active), in
+// registers: shifts by 1, 2, 4 and 8 lanes inside each row of 16, then the
+// total of row 0 added to row 1 and of row 2 to row 3 (broadcast of lane 15),
+// then the total of rows 0-1 added to rows 2-3 (broadcast of lane 31).
 __device__ __forceinline__ int32_t wave_incl_scan(int32_t v) {
-  const int l = lane_id();
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const int32_t t = __shfl_up(v, d, kWave);
-    if (l >= d) v += t;
-  }
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
   return v;
 }
 
+// Sum over the wavefront (every lane active), the same in every lane.
 __device__ __forceinline__ int32_t wave_sum(int32_t v) {
-#pragma unroll
-  for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
-  return v;
+  return __builtin_amdgcn_readlane(wave_incl_scan(v), kWave - 1);
 }
 
 __device__ __forceinline__ uint32_t next_pow2(uint32_t x) {

@@ -850,12 +850,17 @@ __device__ __forceinline__ bool gather_list(const TradeArgs& A, int32_t k, int64
   const int tid = threadIdx.x;
   if (tid == 0) B.cnt[0] = 0;
   __syncthreads();
-  for (int32_t e = tid; e < d; e += blockDim.x) {
-    const int32_t t = A.col_t[b + e];
-    if (tinfo_trade(t) >= k) {
-      const int32_t p = atomicAdd(&B.cnt[0], 1);
-      out[p] = make_entry(A.col[b + e], side, tag_of(t, k));
-    }
+  // one LDS counter update per wavefront and chunk (trip count is uniform
+  // across a wavefront: the bound is rounded up to whole wavefronts)
+  const int32_t dr = (d + kWave - 1) / kWave * kWave;
+  for (int32_t e = tid; e < dr; e += blockDim.x) {
+    const int32_t t = e < d ? A.col_t[b + e] : 0;
+    const bool fresh = e < d && tinfo_trade(t) >= k;
+    const uint64_t m = ballot(fresh);
+    int32_t base = 0;
+    if (lane_id() == 0 && m) base = atomicAdd(&B.cnt[0], popc64(m));
+    base = wave_bcast(base, 0);
+    if (fresh) out[base + rank_below(m)] = make_entry(A.col[b + e], side, tag_of(t, k));
   }
   __syncthreads();
   const int32_t nf = B.cnt[0];
@@ -873,12 +878,12 @@ __device__ __forceinline__ bool gather_list(const TradeArgs& A, int32_t k, int64
 // Write giant gi's neighbour set, ascending, as entries of `side` of trade k
 // into out[0..d), and clear the bitmap and its counts for the next round.
 // Workgroup-wide; false (error raised) if the set does not hold d members.
-// The bit pass is pure arithmetic (wave w takes 64 superblocks, four at a
-// time); the tags, which need one gather per member, follow in a separate
+// The bit pass is pure arithmetic (wave w takes 64 superblocks, 16 loaded at
+// a time); the tags, which need one gather per member, follow in a separate
 // batched pass.
 __device__ __forceinline__ bool extract_giant(const TradeArgs& A, int32_t k, int32_t gi, int side, int32_t d,
                               uint64_t* out, BigLds& B) {
-  constexpr int kSbStep = 8;
+  constexpr int kSbStep = 16;
   const int tid = threadIdx.x;
   const int w = tid >> 6;
   const int l = lane_id();
@@ -939,18 +944,25 @@ __device__ __forceinline__ bool extract_giant(const TradeArgs& A, int32_t k, int
     if (tid == 0) raise_error(A, kErrGather, k, 2000000 + carry - d);
     return false;
   }
-  // tags of the members (one gather each, four in flight per thread)
-  for (int32_t i0 = tid; i0 < d; i0 += blockDim.x * 4) {
-    int32_t ti[4];
+  // tags of the members (one gather each, eight in flight per thread)
+  constexpr int kTagBatch = 8;
+  for (int32_t i0 = tid; i0 < d; i0 += blockDim.x * kTagBatch) {
+    uint64_t e[kTagBatch];
+    int32_t ti[kTagBatch];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < kTagBatch; ++r) {
       const int32_t i = i0 + r * blockDim.x;
-      ti[r] = i < d ? A.tinfo[ent_node(out[i])] : 0;
+      e[r] = i < d ? out[i] : 0ull;
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < kTagBatch; ++r) {
       const int32_t i = i0 + r * blockDim.x;
-      if (i < d) out[i] |= tag_of(ti[r], k);
+      ti[r] = i < d ? A.tinfo[ent_node(e[r])] : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < kTagBatch; ++r) {
+      const int32_t i = i0 + r * blockDim.x;
+      if (i < d) out[i] = e[r] | tag_of(ti[r], k);
     }
   }
   __syncthreads();
