@@ -29,10 +29,13 @@ _u32p = ctypes.POINTER(ctypes.c_uint32)
 class Stats(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in (
         "trades", "work", "common", "disjoint", "moved", "uv_edges", "max_s",
-        "unmatched", "dep_mismatch")]
+        "unmatched", "dep_mismatch")] + [("setup_seconds", ctypes.c_double),
+                                         ("trade_seconds", ctypes.c_double),
+                                         ("rebuild_seconds", ctypes.c_double)]
 
     def as_dict(self):
-        return {name: int(getattr(self, name)) for name, _ in self._fields_}
+        return {name: (float if typ is ctypes.c_double else int)(getattr(self, name))
+                for name, typ in self._fields_}
 
 
 def build(src: str = _SRC, out: str = LIB_PATH, extra_flags=()) -> str:

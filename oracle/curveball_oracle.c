@@ -21,10 +21,20 @@
  *    once, at the endpoint traded first; a trade pushes each resulting edge
  *    to the endpoint whose trade comes next.
  */
+#define _POSIX_C_SOURCE 199309L
+#include <time.h>
 #include "curveball_oracle.h"
 
 #include <stdlib.h>
 #include <string.h>
+
+/* Wall-clock seconds (timing of the IM-CB form's phases only). */
+static double orc_now(void)
+{
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
 
 /* ------------------------------------------------------------------ */
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).                  */
@@ -388,6 +398,7 @@ int orc_global_trade_o2(int64_t n, const int64_t* row_ptr, int32_t* col,
                         uint64_t seed, uint32_t round, orc_stats* st,
                         int64_t max_trades)
 {
+    const double t_begin = orc_now();
     int rc = 0;
     int64_t L = n / 2;
     int64_t nnz = row_ptr[n];
@@ -437,6 +448,8 @@ int orc_global_trade_o2(int64_t n, const int64_t* row_ptr, int32_t* col,
     }
 
     int64_t limit = (max_trades >= 0 && max_trades < L) ? max_trades : L;
+    const double t_trades = orc_now();
+    s.setup_seconds = t_trades - t_begin;
     for (int64_t i = 0; i < limit; ++i) {
         int32_t u = order[2 * i], v = order[2 * i + 1];
         int64_t du = row_ptr[u + 1] - row_ptr[u];
@@ -494,6 +507,8 @@ int orc_global_trade_o2(int64_t n, const int64_t* row_ptr, int32_t* col,
         s.uv_edges += info[3];
         if (du + dv > s.max_s) s.max_s = du + dv;
     }
+    s.trade_seconds = orc_now() - t_trades;
+    const double t_rebuild = orc_now();
     if (limit == L) {
         /* Rebuild the symmetric CSR from the single stored copies: node y's
          * stored edges are AG[row_ptr[y] .. fill[y]). */
@@ -516,6 +531,7 @@ int orc_global_trade_o2(int64_t n, const int64_t* row_ptr, int32_t* col,
         }
         free(cur);
     }
+    s.rebuild_seconds = orc_now() - t_rebuild;
     if (st) *st = s;
 out:
     free(order); free(trade_of); free(tau); free(fill); free(recv); free(dep); free(AG);

@@ -43,6 +43,9 @@ typedef struct {
     int64_t max_s;     /* max over trades of deg(u) + deg(v) */
     int64_t unmatched; /* node left out when n is odd, else -1 */
     int64_t dep_mismatch; /* O2 only: trades whose received count != depcount */
+    double setup_seconds; /* O2 only: wall time before the first trade */
+    double trade_seconds; /* O2 only: wall time of the trades run */
+    double rebuild_seconds; /* O2 only: wall time of the final row rebuild */
 } orc_stats;
 
 /* Philox4x32-10, one block. */
