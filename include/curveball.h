@@ -121,8 +121,8 @@ cb_status global_trade_steps(cb_graph* g, uint64_t seed, uint32_t round, int32_t
 #define CB_STATE_COL      4  /* int32[nnz]: current adjacency (rows ascending) */
 #define CB_STATE_OUT_CUR  5  /* int32[n]: final edges written per row this round */
 #define CB_STATE_INBOX_CUR 6 /* int32[n]: edges handed to each row this round */
-#define CB_STATE_TRACE    7  /* int64[16 * floor(n/2)] (CB_OPT_TRACE): per trade k
-                                at 16k + i: i=0 tick at which it became ready
+#define CB_STATE_TRACE    7  /* int64[20 * floor(n/2)] (CB_OPT_TRACE): per trade k
+                                at 20k + i: i=0 tick at which it became ready
                                 (-1: a source), 1 start and 2 end of its
                                 execution, 3 trade whose release made it ready
                                 (-1: a source); for trades run by a workgroup
@@ -130,7 +130,12 @@ cb_status global_trade_steps(cb_graph* g, uint64_t seed, uint32_t round, int32_t
                                 6 classified, 7 split and own rows reserved,
                                 8 deg u + deg v, 9 kind (1 giant node, 2 in LDS,
                                 3 in global scratch), 10 deg u, 11 deg v,
-                                12 disjoint entries, 13 of which u's. Ticks of
+                                12 disjoint entries, 13 of which u's, 14 and 15
+                                end of the bit pass and of the tag pass of a
+                                giant node's list (the last one taken); for a
+                                write phase shared with helpers 16 arrays
+                                published, 17 own chunks done, 18 all chunks
+                                done, 19 chunks written by the owner. Ticks of
                                 the device's constant 100 MHz clock; -1 where
                                 not recorded */
 
@@ -155,8 +160,11 @@ cb_status graph_download_state(cb_graph* g, int32_t which, void* host, int64_t c
 #define CB_OPT_HELP_MIN     11  /* workgroup trades with deg u + deg v >= this
                                    let idle wavefronts of the kernel share their
                                    write phase (0 = never). Default 8192. */
+#define CB_OPT_HELP_GROUPS  12  /* workgroup workers help the shared phases of
+                                   owners in their residue class modulo this
+                                   (a divisor of 64; default 2) */
 #define CB_OPT_TRACE        10  /* 1: record per-trade times (CB_STATE_TRACE);
-                                   allocates 128 bytes per trade on first use */
+                                   allocates 160 bytes per trade on first use */
 #define CB_OPT_GIANT_DEG     8  /* nodes of at least this degree keep the edges
                                    handed to them in a bitmap over all node ids
                                    (n/8 bytes each) instead of a list; 0 = none.

@@ -105,6 +105,7 @@ struct cb_graph {
   int32_t grid_blocks = 0;   // 0: automatic
   int32_t stack_cap = 8;
   int32_t help_min = kHelpMinItems;
+  int32_t help_groups = 2;
   int64_t watchdog_ms = 20000;
   bool timing = false;
   bool debug_checks = false;
@@ -387,6 +388,7 @@ cb_status enqueue_round(cb_graph* g, uint64_t seed, uint32_t round, int last_ste
     A.L = L;
     A.small_max = effective_small_max(g);
     A.help_min = g->help_min;
+    A.help_groups = g->help_groups;
     A.big_lds_max = g->big_lds_max;
     A.nbig = effective_nbig(g);
     A.stack_cap = g->stack_cap;
@@ -689,6 +691,11 @@ cb_status graph_set_option(cb_graph* g, int32_t option, int64_t value) {
     case CB_OPT_HELP_MIN:
       if (value < 0 || value > INT32_MAX) return fail(CB_EINVAL, "help_min must be in [0, 2^31 - 1]");
       g->help_min = (int32_t)value;
+      return CB_OK;
+    case CB_OPT_HELP_GROUPS:
+      if (value < 1 || value > kMaxJobs || kMaxJobs % value != 0)
+        return fail(CB_EINVAL, "help groups must divide 64");
+      g->help_groups = (int32_t)value;
       return CB_OK;
     case CB_OPT_LOCAL_STACK:
       if (value < 0 || value > kStackCap) return fail(CB_EINVAL, "local stack must be in [0, 16]");

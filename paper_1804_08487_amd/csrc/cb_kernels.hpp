@@ -53,9 +53,9 @@ constexpr int kGiantMinDeg = kBigCap / 2;   // default giant degree: any other p
 constexpr int kTradeBlock = 512;      // threads per trade-kernel workgroup (one per CU: 256 VGPRs each)
 constexpr int kWavesPerBlock = kTradeBlock / 64;
 constexpr int kStackCap = 16;         // ready trades a wavefront may keep
-constexpr int kTraceFields = 16;      // int64 per trade of the optional trace
+constexpr int kTraceFields = 20;      // int64 per trade of the optional trace
 constexpr int kMaxJobs = 64;          // workgroups that can open their write phase to helpers
-constexpr int32_t kHelpChunk = 1024;  // output items per claimed chunk
+constexpr int32_t kHelpChunk = 512;   // output items per claimed chunk
 constexpr int32_t kHelpMinItems = 8192;   // default: smaller trades work alone
 constexpr int32_t kSbChunk = 16;      // bitmap superblocks per claimed extraction chunk
 
@@ -78,7 +78,7 @@ struct HelpJob {
   } c;
   struct alignas(128) {
     int64_t bu, bv;              // row offsets of u and v
-    int64_t e_off;               // phase 2: entries at owner's slot + e_off;
+    int64_t e_off;               // phase 2: items at owner's slot + e_off;
                                  // phase 1: output list there
     int32_t k, u, v, s, nD, a, du, dv;
     int32_t phase, gi, side, d;  // phase 1: giant id, side and size of the list
@@ -142,6 +142,7 @@ struct TradeArgs {
   int32_t L;
   int32_t small_max;
   int32_t help_min;         // trades of at least this many items open their write phase (0: none)
+  int32_t help_groups;      // workgroup b helps owners j with j % help_groups == b % help_groups
   int32_t big_lds_max;
   int32_t nbig;
   int32_t stack_cap;

@@ -76,6 +76,7 @@ struct BigLds {
   int32_t emit_d;      // disjoint entries that are final now
   int32_t emit_lo;     // ... of which on the smaller side of the split
   int32_t flag;        // workgroup-wide decision
+  uint64_t tick[2];    // trace: end of a giant's bit pass and of its tag pass
   int32_t base[2];
   int32_t ndone;
   // giant extraction: output offset and members per superblock; the split
@@ -254,7 +255,8 @@ constexpr int kBatch = 8;   // items per lane in flight in the write phase
 
 // Output items of a large trade after the split: D[0..nD) are the disjoint
 // entries (u receives positions below a), D[nD..s) the kept ones (shared
-// neighbours and the partner); item o is entry E[D[o]].
+// neighbours and the partner); item o is entry E[D[o]]. A shared write phase
+// reads them from one published array instead (E = items, D unused).
 struct ItemSrc {
   const uint64_t* E;
   const int32_t* D;
@@ -266,11 +268,14 @@ struct WriteCounts {   // per lane
   unsigned long long fwd, emit, push;
 };
 
+// Item o: its entry, with the side bit replaced by the side of its owner
+// (0: u, 1: v). Shared: read from the published item array S.E[o].
 template <bool kShared>
 __device__ __forceinline__ uint64_t item_entry(const ItemSrc& S, int32_t o) {
-  if (kShared)
-    return load_agent_u64(reinterpret_cast<const unsigned long long*>(S.E) + load_agent(&S.D[o]));
-  return S.E[S.D[o]];
+  if (kShared) return load_agent_u64(reinterpret_cast<const unsigned long long*>(S.E) + o);
+  const uint64_t e = S.E[S.D[o]];
+  const uint64_t own = o < S.nD ? (o < S.a ? 0ull : 1ull) : (uint64_t)ent_side(e);
+  return (e & ~(1ull << 32)) | (own << 32);
 }
 
 // Write items first, first + step, ... below end (a wavefront handles kBatch
@@ -300,7 +305,7 @@ __device__ __forceinline__ void write_range(const TradeArgs& A, const ItemSrc& S
         const uint64_t e = item_entry<kShared>(S, o);
         tx[r] = ent_node(e);
         ttag[r] = ent_tag(e);
-        towner[r] = o < S.nD ? (o < S.a ? S.u : S.v) : (ent_side(e) ? S.v : S.u);
+        towner[r] = ent_side(e) ? S.v : S.u;
       }
       const bool own = tx[r] >= 0 && ttag[r] <= kTagPartner;
       mu[r] = ballot(own && towner[r] == S.u);
@@ -537,9 +542,14 @@ __device__ __forceinline__ bool extract_giant_shared(const TradeArgs& A, int32_t
 }
 
 // Helper groups: workgroup b helps only the jobs of owners j with
-// j % kHelpGroups == b % kHelpGroups, so a job is shared by a bounded set of
-// workgroups and claims of different jobs do not meet on one word.
-constexpr int kHelpGroups = 8;
+// j % G == b % G (G = help_groups, a divisor of 64), so a job is shared by a
+// bounded set of workgroups and claims of different jobs do not meet on one
+// word.
+__device__ __forceinline__ uint64_t help_group_mask(int32_t b, int32_t groups) {
+  uint64_t m = 0;
+  for (int j = b % groups; j < kMaxJobs; j += groups) m |= 1ull << j;
+  return m;
+}
 
 // An idle wavefront of workgroup b writes one chunk of an open write job of
 // its group, if there is one.
@@ -547,12 +557,12 @@ __device__ __forceinline__ bool try_help(const TradeArgs& A, int32_t b, WriteCou
   const int l = lane_id();
   int32_t j = -1, c = -1;
   if (l == 0) {
-    const uint64_t group = 0x0101010101010101ull << (b % kHelpGroups);
+    const uint64_t group = help_group_mask(b, A.help_groups);
     const uint64_t m = ((uint64_t)(uint32_t)load_agent(&A.ctrl[cw(kCwJobMask0)]) |
                         ((uint64_t)(uint32_t)load_agent(&A.ctrl[cw(kCwJobMask1)]) << 32)) & group;
     if (m) {
       // spread the waves of one workgroup over the open jobs of its group
-      const int rot = (int)((threadIdx.x >> 6) * 8) & 63;
+      const int rot = (int)((threadIdx.x >> 6) * A.help_groups) & 63;
       const uint64_t rm = rot ? ((m >> rot) | (m << (64 - rot))) : m;
       j = (int32_t)((__builtin_ctzll(rm) + rot) & 63);
       c = claim_chunk(A.jobs + j);
@@ -576,7 +586,7 @@ __device__ __forceinline__ bool try_help(const TradeArgs& A, int32_t b, WriteCou
   }
   ItemSrc S;
   S.E = slot + load_agent64(&J->f.e_off);
-  S.D = reinterpret_cast<const int32_t*>(slot + 2 * A.smax);
+  S.D = nullptr;
   S.k = load_agent(&J->f.k);
   S.u = load_agent(&J->f.u);
   S.v = load_agent(&J->f.v);
@@ -878,12 +888,12 @@ __device__ __forceinline__ bool gather_list(const TradeArgs& A, int32_t k, int64
 // Write giant gi's neighbour set, ascending, as entries of `side` of trade k
 // into out[0..d), and clear the bitmap and its counts for the next round.
 // Workgroup-wide; false (error raised) if the set does not hold d members.
-// The bit pass is pure arithmetic (wave w takes 64 superblocks, 16 loaded at
-// a time); the tags, which need one gather per member, follow in a separate
-// batched pass.
+// The bit pass is pure arithmetic (wave w takes 64 superblocks of each block
+// of superblocks, 32 loaded at a time, a lane covering 8 words); the tags,
+// which need one gather per member, follow in a separate batched pass.
 __device__ __forceinline__ bool extract_giant(const TradeArgs& A, int32_t k, int32_t gi, int side, int32_t d,
                               uint64_t* out, BigLds& B) {
-  constexpr int kSbStep = 16;
+  constexpr int kGroups = 4;   // groups of 8 superblocks loaded per wavefront step
   const int tid = threadIdx.x;
   const int w = tid >> 6;
   const int l = lane_id();
@@ -900,35 +910,54 @@ __device__ __forceinline__ bool extract_giant(const TradeArgs& A, int32_t k, int
     B.sboff[tid] = carry + pre;
     B.sbcnt[tid] = c;
     __syncthreads();
-    for (int q = 0; q < kWave; q += kSbStep) {
-      unsigned long long word[kSbStep];
+    // Lane l covers words 8 * (l % 8) .. + 7 of superblock l / 8 of its
+    // group, so one wavefront instruction covers 8 superblocks; a wavefront
+    // takes the 64 superblocks w * 64 .. of this block in kGroups groups of 8
+    // per step.
+    const int seg = l >> 3;           // superblock of this lane within a group
+    const int part = l & 7;           // its 8-word part of the superblock
+    const int seg0 = l & ~7;          // first lane of the segment
+    for (int q = 0; q < kWave; q += 8 * kGroups) {
+      unsigned long long word[kGroups][8];
 #pragma unroll
-      for (int t = 0; t < kSbStep; ++t) {
-        const int slot_i = w * kWave + q + t;
-        const int64_t jj = j0 + slot_i;
-        word[t] = (jj < nsb && B.sbcnt[slot_i] > 0) ? load_agent_u64(&bm[jj * kWave + l]) : 0ull;
+      for (int g = 0; g < kGroups; ++g) {
+        const int sbi = w * kWave + q + g * 8 + seg;
+        const int64_t jj = j0 + sbi;
+        const bool valid = jj < nsb && B.sbcnt[sbi] > 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          word[g][i] = valid ? load_agent_u64(&bm[jj * kWave + part * 8 + i]) : 0ull;
       }
 #pragma unroll
-      for (int t = 0; t < kSbStep; ++t) {
-        const int slot_i = w * kWave + q + t;
-        const int64_t jj = j0 + slot_i;
-        if (jj >= nsb) break;
-        const int32_t cnt = B.sbcnt[slot_i];
-        if (cnt == 0) continue;
-        const int64_t wi = jj * kWave + l;
-        unsigned long long bits = word[t];
-        const int32_t pc = __popcll(bits);
-        const int32_t at = B.sboff[slot_i] + wave_incl_scan(pc) - pc;
-        if (wave_sum(pc) != cnt) bad = true;
-        if (bits) bm[wi] = 0ull;
+      for (int g = 0; g < kGroups; ++g) {
+        const int sbi = w * kWave + q + g * 8 + seg;
+        const int64_t jj = j0 + sbi;
+        const bool valid = jj < nsb;
+        int32_t pc = 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) pc += __popcll(word[g][i]);
+        // exclusive prefix of pc inside the 8-lane segment, and its total
+        const int32_t incl = wave_incl_scan(pc);
+        const int32_t before = __shfl(incl, seg0 > 0 ? seg0 - 1 : 0, kWave);
+        const int32_t seg_end = __shfl(incl, seg0 + 7, kWave);
+        const int32_t base = seg0 > 0 ? before : 0;
+        if (valid && seg_end - base != B.sbcnt[sbi]) bad = true;
+        const int32_t at = (valid ? B.sboff[sbi] : 0) + incl - pc - base;
         int32_t idx = 0;
-        while (bits) {
-          const int bit = __builtin_ctzll(bits);
-          bits &= bits - 1;
-          if (at + idx < d) out[at + idx] = make_entry((int32_t)(wi * 64 + bit), side, 0u);
-          ++idx;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          unsigned long long bits = word[g][i];
+          if (!bits) continue;
+          const int64_t wi = jj * kWave + part * 8 + i;
+          bm[wi] = 0ull;
+          while (bits) {
+            const int bit = __builtin_ctzll(bits);
+            bits &= bits - 1;
+            if (at + idx < d) out[at + idx] = make_entry((int32_t)(wi * 64 + bit), side, 0u);
+            ++idx;
+          }
         }
-        if (l == 0) sc[jj] = 0;
+        if (valid && part == 0 && B.sbcnt[sbi] > 0) sc[jj] = 0;
       }
     }
     carry += tot;
@@ -944,6 +973,7 @@ __device__ __forceinline__ bool extract_giant(const TradeArgs& A, int32_t k, int
     if (tid == 0) raise_error(A, kErrGather, k, 2000000 + carry - d);
     return false;
   }
+  if (tid == 0) B.tick[0] = now_ticks();
   // tags of the members (one gather each, eight in flight per thread)
   constexpr int kTagBatch = 8;
   for (int32_t i0 = tid; i0 < d; i0 += blockDim.x * kTagBatch) {
@@ -966,6 +996,7 @@ __device__ __forceinline__ bool extract_giant(const TradeArgs& A, int32_t k, int
     }
   }
   __syncthreads();
+  if (tid == 0) B.tick[1] = now_ticks();
   return true;
 }
 
@@ -993,6 +1024,7 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
   const int32_t niu = load_agent(&A.inbox_cur[u]);
   const int32_t niv = load_agent(&A.inbox_cur[v]);
   uint64_t t_lists = 0;
+  if (tid == 0) { B.tick[0] = 0; B.tick[1] = 0; }
 
   if (giant) {
     // Both lists sorted separately (a giant's straight from its bitmap, a
@@ -1151,6 +1183,7 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
       if (ov && atomic_add(&A.out_cur[v], ov) != 0) raise_error(A, kErrOut, k, -2 - v);
       B.cnt[1] = 0;
       B.cnt[2] = 0;
+      B.cnt[3] = 0;
     }
     __syncthreads();
   }
@@ -1164,21 +1197,19 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
   if (A.help_min == 0 || s < A.help_min || (int)blockIdx.x >= kMaxJobs) {
     write_range<false>(A, S, w * kWave * kBatch, s, kWavesPerBlock * kWave * kBatch, B.cnt + 1, W);
   } else {
-    // publish both arrays where other workgroups can read them
-    unsigned long long* Eg = reinterpret_cast<unsigned long long*>(in_lds ? slot : E);
-    int32_t* Dg = reinterpret_cast<int32_t*>(slot + 2 * A.smax);
-    for (int32_t i = tid; i < s; i += nt) {
-      store_agent_u64(&Eg[i], E[i]);
-      store_agent(&Dg[i], D[i]);
-    }
+    // publish the items where other workgroups can read them, in the slot
+    // region that is only ever written with agent-scope stores
+    unsigned long long* Ig = reinterpret_cast<unsigned long long*>(slot + shared_list_off(A));
+    for (int32_t o = tid; o < s; o += nt) store_agent_u64(&Ig[o], item_entry<false>(S, o));
     publish_wait();
     __syncthreads();
+    if (A.trace && tid == 0) A.trace[kTraceFields * (int64_t)k + 16] = (int64_t)now_ticks();
     HelpJob* J = A.jobs + blockIdx.x;
     const int32_t nchunks = (s + kHelpChunk - 1) / kHelpChunk;
     if (tid == 0) {
       store_agent64(&J->f.bu, bu);
       store_agent64(&J->f.bv, bv);
-      store_agent64(&J->f.e_off, (int64_t)(reinterpret_cast<uint64_t*>(Eg) - slot));
+      store_agent64(&J->f.e_off, shared_list_off(A));
       store_agent(&J->f.k, k);
       store_agent(&J->f.u, u);
       store_agent(&J->f.v, v);
@@ -1191,8 +1222,8 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
       open_job(A, J, nchunks);
     }
     __syncthreads();
-    S.E = reinterpret_cast<const uint64_t*>(Eg);
-    S.D = Dg;
+    S.E = reinterpret_cast<const uint64_t*>(Ig);
+    S.D = nullptr;
     for (;;) {
       int32_t c = -1;
       if (lane_id() == 0) c = claim_chunk(J);
@@ -1202,11 +1233,19 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
       write_range<true>(A, S, first, first + kHelpChunk < s ? first + kHelpChunk : s, kWave * kBatch,
                         J->c.own, W);
       publish_wait();
-      if (lane_id() == 0) atomic_add(&J->c.done, 1);
+      if (lane_id() == 0) {
+        atomic_add(&J->c.done, 1);
+        if (A.trace) atomicAdd(&B.cnt[3], 1);
+      }
     }
     __syncthreads();
     if (tid == 0) {
+      if (A.trace) A.trace[kTraceFields * (int64_t)k + 17] = (int64_t)now_ticks();
       close_job(A, J, nchunks);
+      if (A.trace) {
+        A.trace[kTraceFields * (int64_t)k + 18] = (int64_t)now_ticks();
+        A.trace[kTraceFields * (int64_t)k + 19] = B.cnt[3];
+      }
       B.cnt[1] = load_agent(&J->c.own[0]);
       B.cnt[2] = load_agent(&J->c.own[1]);
     }
@@ -1231,6 +1270,8 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
       T[11] = dv;
       T[12] = nD;
       T[13] = a;
+      T[14] = B.tick[0] ? (int64_t)B.tick[0] : -1;
+      T[15] = B.tick[1] ? (int64_t)B.tick[1] : -1;
     }
   }
   counters[1] += W.fwd;

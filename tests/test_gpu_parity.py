@@ -55,7 +55,8 @@ TIERS = {"default": {}, "all_workgroup": {cb.OPT_SMALL_MAX: 0},
          "help_all": {cb.OPT_SMALL_MAX: 0, cb.OPT_HELP_MIN: 1},
          "help_global": {cb.OPT_SMALL_MAX: 0, cb.OPT_BIG_LDS_MAX: 0, cb.OPT_HELP_MIN: 1},
          "help_giant8": {cb.OPT_GIANT_DEG: 8, cb.OPT_SMALL_MAX: 0, cb.OPT_HELP_MIN: 1},
-         "no_help": {cb.OPT_SMALL_MAX: 0, cb.OPT_HELP_MIN: 0}}
+         "no_help": {cb.OPT_SMALL_MAX: 0, cb.OPT_HELP_MIN: 0},
+         "help_one_group": {cb.OPT_SMALL_MAX: 0, cb.OPT_HELP_MIN: 1, cb.OPT_HELP_GROUPS: 1}}
 
 
 def _run_and_compare(orc, rp, col, seed, rounds, options=None, form="o1"):
