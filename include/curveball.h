@@ -119,7 +119,11 @@ cb_status global_trade_steps(cb_graph* g, uint64_t seed, uint32_t round, int32_t
 #define CB_STATE_TRADE_OF 2  /* int32[n]: trade of each node, INT32_MAX if none */
 #define CB_STATE_DEP      3  /* int32[n/2]: dependency counts after DEPSCAN */
 #define CB_STATE_COL      4  /* int32[nnz]: current adjacency (rows ascending) */
-#define CB_STATE_OUT_CUR  5  /* int32[n]: final edges written per row this round */
+#define CB_STATE_OUT_CUR  5  /* int32[n]: final edges written into each row from
+                                its front this round */
+#define CB_STATE_OWN_CUR  8  /* int32[n]: edges a workgroup trade wrote into its
+                                own rows from their back (with OUT_CUR the
+                                degree after a full round) */
 #define CB_STATE_INBOX_CUR 6 /* int32[n]: edges handed to each row this round */
 #define CB_STATE_TRACE    7  /* int64[20 * floor(n/2)] (CB_OPT_TRACE): per trade k
                                 at 20k + i: i=0 tick at which it became ready
@@ -130,9 +134,9 @@ cb_status global_trade_steps(cb_graph* g, uint64_t seed, uint32_t round, int32_t
                                 6 classified, 7 split and own rows reserved,
                                 8 deg u + deg v, 9 kind (1 giant node, 2 in LDS,
                                 3 in global scratch), 10 deg u, 11 deg v,
-                                12 disjoint entries, 13 of which u's, 14 and 15
-                                end of the bit pass and of the tag pass of a
-                                giant node's list (the last one taken); for a
+                                12 disjoint entries, 13 of which u's, 14 end of
+                                the bit pass of a giant node's list (the last
+                                one taken), 15 unused; for a
                                 write phase shared with helpers 16 arrays
                                 published, 17 own chunks done, 18 all chunks
                                 done, 19 chunks written by the owner. Ticks of

@@ -22,7 +22,7 @@ STATUS_NAMES = {0: "CB_OK", 1: "CB_EINVAL", 2: "CB_ENOTSIMPLE", 3: "CB_ENOMEM",
                 4: "CB_EDEVICE", 5: "CB_EWATCHDOG", 6: "CB_EPOISONED"}
 CB_VALIDATE = 1
 STEP_MATCHING, STEP_DEPSCAN, STEP_TRADE, STEP_REBUILD = 1, 2, 3, 4
-STATE_PERM, STATE_TRADE_OF, STATE_DEP, STATE_COL, STATE_OUT_CUR, STATE_INBOX_CUR, STATE_TRACE = range(1, 8)
+STATE_PERM, STATE_TRADE_OF, STATE_DEP, STATE_COL, STATE_OUT_CUR, STATE_INBOX_CUR, STATE_TRACE, STATE_OWN_CUR = range(1, 9)
 (OPT_SMALL_MAX, OPT_BIG_WORKERS, OPT_GRID_BLOCKS, OPT_WATCHDOG_MS, OPT_TIMING, OPT_LOCAL_STACK,
  OPT_BIG_LDS_MAX, OPT_GIANT_DEG, OPT_DEBUG_CHECKS, OPT_TRACE, OPT_HELP_MIN, OPT_HELP_GROUPS) = range(1, 13)
 UNMATCHED = 2**31 - 1
@@ -167,7 +167,7 @@ class Graph:
 
     def state(self, which: int):
         count = {STATE_PERM: self.n, STATE_TRADE_OF: self.n, STATE_DEP: self.n // 2,
-                 STATE_COL: self.nnz, STATE_OUT_CUR: self.n, STATE_INBOX_CUR: self.n,
+                 STATE_COL: self.nnz, STATE_OUT_CUR: self.n, STATE_INBOX_CUR: self.n, STATE_OWN_CUR: self.n,
                  STATE_TRACE: 20 * (self.n // 2)}[which]
         out = np.empty(max(count, 1), np.int64 if which == STATE_TRACE else np.int32)
         _check(lib().graph_download_state(self._h, which, out.ctypes.data, count))

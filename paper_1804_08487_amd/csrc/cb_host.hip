@@ -56,6 +56,7 @@ struct cb_graph {
   int32_t* inbox = nullptr;
   int32_t* inbox_cur = nullptr;
   int32_t* out_cur = nullptr;
+  int32_t* own_cur = nullptr;
   int32_t* perm = nullptr;
   int32_t* trade_of = nullptr;
   int32_t* tinfo = nullptr;
@@ -325,8 +326,8 @@ cb_status enqueue_round(cb_graph* g, uint64_t seed, uint32_t round, int last_ste
   if (last_step < CB_STEP_TRADE && g->ngiant > 0) g->giant_dirty = true;
 
   hipLaunchKernelGGL(k_round_reset, dim3(grid_for(std::max<int64_t>({n, (int64_t)g->nb, (int64_t)kCwCount}), 256, 8192)),
-                     dim3(256), 0, st, n, g->nb, g->inbox_cur, g->out_cur, g->bcount, g->bcur,
-                     g->ctrl, g->stats);
+                     dim3(256), 0, st, n, g->nb, g->inbox_cur, g->out_cur, g->own_cur, g->bcount,
+                     g->bcur, g->ctrl, g->stats);
   // 1. matching
   hipLaunchKernelGGL(k_match_count, dim3(grid_for(n, 256, 16384)), dim3(256), 0, st, n, seed, round,
                      g->nb_log2, g->bcount, g->ctrl);
@@ -365,6 +366,7 @@ cb_status enqueue_round(cb_graph* g, uint64_t seed, uint32_t round, int last_ste
     A.inbox_cur = g->inbox_cur;
     A.col_out = g->col_out;
     A.out_cur = g->out_cur;
+    A.own_cur = g->own_cur;
     A.dep = g->dep;
     A.src_list = g->src_list;
     A.tsz = g->tsz;
@@ -401,7 +403,7 @@ cb_status enqueue_round(cb_graph* g, uint64_t seed, uint32_t round, int last_ste
   if (timed) (void)hipEventRecord(evs.ev[3], st);
   if (last_step >= CB_STEP_TRADE && L > 0)
     hipLaunchKernelGGL(k_check_rows, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, n, g->rp,
-                       g->out_cur, g->ctrl);
+                       g->out_cur, g->own_cur, g->ctrl);
   if (last_step >= CB_STEP_REBUILD && g->nnz > 0) {
     // 4. rebuild: per-row ascending sort of col_out into col
     if (g->n_small)
@@ -510,7 +512,7 @@ cb_status graph_upload(int64_t n, const int64_t* row_ptr, const int32_t* col, vo
   bool ok = alloc_into(g, &g->rp, n + 1) && alloc_into(g, &g->col, nnz) &&
             alloc_into(g, &g->col_t, nnz) && alloc_into(g, &g->col_out, nnz) &&
             alloc_into(g, &g->inbox, nnz) && alloc_into(g, &g->inbox_cur, n) &&
-            alloc_into(g, &g->out_cur, n) && alloc_into(g, &g->perm, n) &&
+            alloc_into(g, &g->out_cur, n) && alloc_into(g, &g->own_cur, n) && alloc_into(g, &g->perm, n) &&
             alloc_into(g, &g->trade_of, n) && alloc_into(g, &g->tinfo, n) &&
             alloc_into(g, &g->giant_id, n) && alloc_into(g, &g->mtmp, n) &&
             alloc_into(g, &g->mkey, n) && alloc_into(g, &g->dep, g->L) &&
@@ -634,6 +636,7 @@ cb_status graph_download_state(cb_graph* g, int32_t which, void* host, int64_t c
     case CB_STATE_DEP: src = g->dep; avail = g->L; break;
     case CB_STATE_COL: src = g->col; avail = g->nnz; break;
     case CB_STATE_OUT_CUR: src = g->out_cur; avail = g->n; break;
+    case CB_STATE_OWN_CUR: src = g->own_cur; avail = g->n; break;
     case CB_STATE_INBOX_CUR: src = g->inbox_cur; avail = g->n; break;
     default: return fail(CB_EINVAL, "unknown state id");
   }

@@ -122,7 +122,8 @@ struct TradeArgs {
   int32_t* inbox;           // CSR-shaped: arrivals for each node's row
   int32_t* inbox_cur;
   int32_t* col_out;         // CSR-shaped: final edges of the round
-  int32_t* out_cur;
+  int32_t* out_cur;         // final entries written into a row from its front
+  int32_t* own_cur;         // entries a workgroup trade wrote into its own rows, from the back
   int32_t* dep;
   const int32_t* src_list;
   const int32_t* tsz;       // deg u + deg v per trade, from k_sources
@@ -154,7 +155,7 @@ struct TradeArgs {
 
 // ---- kernels ---------------------------------------------------------------
 __global__ void k_round_reset(int64_t n, int32_t nb, int32_t* inbox_cur, int32_t* out_cur,
-                              int32_t* bcount, int32_t* bcur, int32_t* ctrl,
+                              int32_t* own_cur, int32_t* bcount, int32_t* bcur, int32_t* ctrl,
                               unsigned long long* stats);
 __global__ void k_match_count(int64_t n, uint64_t seed, uint32_t round, int nb_log2,
                               int32_t* bcount, const int32_t* ctrl);
@@ -176,7 +177,7 @@ __global__ void k_sources(int32_t L, const int32_t* dep, const int32_t* perm, co
 __global__ void k_trade(TradeArgs A);
 __global__ void k_check_giants_empty(int64_t total_sb, const int32_t* sc, int32_t* ctrl);
 __global__ void k_check_rows(int64_t n, const int64_t* rp, const int32_t* out_cur,
-                             int32_t* ctrl);
+                             const int32_t* own_cur, int32_t* ctrl);
 __global__ void k_segsort_small(const int32_t* rows, int64_t nrows, const int64_t* rp,
                                 const int32_t* src, int32_t* dst, const int32_t* ctrl);
 __global__ void k_segsort_mid(const int32_t* rows, int64_t nrows, const int64_t* rp,

@@ -7,13 +7,14 @@
 namespace cbx {
 
 __global__ void k_round_reset(int64_t n, int32_t nb, int32_t* inbox_cur, int32_t* out_cur,
-                              int32_t* bcount, int32_t* bcur, int32_t* ctrl,
+                              int32_t* own_cur, int32_t* bcount, int32_t* bcur, int32_t* ctrl,
                               unsigned long long* stats) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t i = t0; i < n; i += stride) {
     inbox_cur[i] = 0;
     out_cur[i] = 0;
+    own_cur[i] = 0;
   }
   for (int64_t i = t0; i < nb; i += stride) {
     bcount[i] = 0;
@@ -274,11 +275,14 @@ __global__ void k_sources(int32_t L, const int32_t* dep, const int32_t* perm, co
   }
 }
 
-__global__ void k_check_rows(int64_t n, const int64_t* rp, const int32_t* out_cur, int32_t* ctrl) {
+// Every row received exactly its degree: entries from its front plus the
+// own-row entries a workgroup trade wrote from its back.
+__global__ void k_check_rows(int64_t n, const int64_t* rp, const int32_t* out_cur,
+                             const int32_t* own_cur, int32_t* ctrl) {
   if (ctrl[cw(kCwErr)]) return;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += stride)
-    if ((int64_t)out_cur[x] != rp[x + 1] - rp[x]) atomic_or(&ctrl[cw(kCwErr)], kErrRows);
+    if ((int64_t)out_cur[x] + own_cur[x] != rp[x + 1] - rp[x]) atomic_or(&ctrl[cw(kCwErr)], kErrRows);
 }
 
 // ---------------------------------------------------------------- rebuild

@@ -38,6 +38,9 @@ namespace cbx {
 constexpr uint32_t kTagEmit = 0u;
 constexpr uint32_t kTagPartner = 1u;
 constexpr uint32_t kTagGiant = 0x80000000u;
+// Tag of a giant node's member whose trade is looked up only when the edge
+// is written (trade indices stay below 2^30, so no real tag takes this value).
+constexpr uint32_t kTagUnknown = 0x7FFFFFFFu;
 
 __device__ __forceinline__ uint64_t make_entry(int32_t x, int side, uint32_t tag) {
   return ((uint64_t)(((uint32_t)x << 1) | (uint32_t)side) << 32) | tag;
@@ -72,11 +75,8 @@ struct BigLds {
   int32_t scan[kWavesPerBlock + 1];
   int32_t next;
   int32_t cnt[4];
-  int32_t own_cp[2];   // shared / partner entries per side that are final now
-  int32_t emit_d;      // disjoint entries that are final now
-  int32_t emit_lo;     // ... of which on the smaller side of the split
   int32_t flag;        // workgroup-wide decision
-  uint64_t tick[2];    // trace: end of a giant's bit pass and of its tag pass
+  uint64_t tick[1];    // trace: end of a giant's bit pass
   int32_t base[2];
   int32_t ndone;
   // giant extraction: output offset and members per superblock; the split
@@ -307,6 +307,15 @@ __device__ __forceinline__ void write_range(const TradeArgs& A, const ItemSrc& S
         ttag[r] = ent_tag(e);
         towner[r] = ent_side(e) ? S.v : S.u;
       }
+    }
+    // members of a giant node's list learn their tag here, one gather each
+    int32_t tinf[kBatch];
+#pragma unroll
+    for (int r = 0; r < kBatch; ++r)
+      tinf[r] = (tx[r] >= 0 && ttag[r] == kTagUnknown) ? A.tinfo[tx[r]] : 0;
+#pragma unroll
+    for (int r = 0; r < kBatch; ++r) {
+      if (tx[r] >= 0 && ttag[r] == kTagUnknown) ttag[r] = tag_of(tinf[r], S.k);
       const bool own = tx[r] >= 0 && ttag[r] <= kTagPartner;
       mu[r] = ballot(own && towner[r] == S.u);
       mv[r] = ballot(own && towner[r] == S.v);
@@ -334,7 +343,8 @@ __device__ __forceinline__ void write_range(const TradeArgs& A, const ItemSrc& S
       const bool ou = (mu[r] >> l) & 1ull, ov = (mv[r] >> l) & 1ull;
       if (ou || ov) {
         const int32_t p = ou ? pu + rank_below(mu[r]) : pv + rank_below(mv[r]);
-        if (p < (ou ? S.du : S.dv)) A.col_out[(ou ? S.bu : S.bv) + p] = tx[r];
+        const int32_t dd = ou ? S.du : S.dv;
+        if (p < dd) A.col_out[(ou ? S.bu : S.bv) + (dd - 1 - p)] = tx[r];
         else raise_error(A, kErrOut, S.k, -2 - towner[r]);
       }
       pu += popc64(mu[r]);
@@ -472,8 +482,7 @@ __device__ __forceinline__ void extract_chunk(const TradeArgs& A, int32_t k, int
         const int bit = __builtin_ctzll(bits);
         bits &= bits - 1;
         const int32_t x = (int32_t)(wi * 64 + bit);
-        const int32_t ti = A.tinfo[x];
-        if (at + idx < hi[t]) store_agent_u64(&X[at + idx], make_entry(x, side, tag_of(ti, k)));
+        if (at + idx < hi[t]) store_agent_u64(&X[at + idx], make_entry(x, side, kTagUnknown));
         ++idx;
       }
       if (l == 0) sc[jj] = 0;
@@ -888,9 +897,9 @@ __device__ __forceinline__ bool gather_list(const TradeArgs& A, int32_t k, int64
 // Write giant gi's neighbour set, ascending, as entries of `side` of trade k
 // into out[0..d), and clear the bitmap and its counts for the next round.
 // Workgroup-wide; false (error raised) if the set does not hold d members.
-// The bit pass is pure arithmetic (wave w takes 64 superblocks of each block
-// of superblocks, 32 loaded at a time, a lane covering 8 words); the tags,
-// which need one gather per member, follow in a separate batched pass.
+// Wave w takes 64 superblocks of each block of superblocks, 32 loaded at a
+// time, a lane covering 8 words. The members' tags are left unknown: the
+// write phase looks each one up when it routes the edge, in parallel.
 __device__ __forceinline__ bool extract_giant(const TradeArgs& A, int32_t k, int32_t gi, int side, int32_t d,
                               uint64_t* out, BigLds& B) {
   constexpr int kGroups = 4;   // groups of 8 superblocks loaded per wavefront step
@@ -953,7 +962,7 @@ __device__ __forceinline__ bool extract_giant(const TradeArgs& A, int32_t k, int
           while (bits) {
             const int bit = __builtin_ctzll(bits);
             bits &= bits - 1;
-            if (at + idx < d) out[at + idx] = make_entry((int32_t)(wi * 64 + bit), side, 0u);
+            if (at + idx < d) out[at + idx] = make_entry((int32_t)(wi * 64 + bit), side, kTagUnknown);
             ++idx;
           }
         }
@@ -974,29 +983,7 @@ __device__ __forceinline__ bool extract_giant(const TradeArgs& A, int32_t k, int
     return false;
   }
   if (tid == 0) B.tick[0] = now_ticks();
-  // tags of the members (one gather each, eight in flight per thread)
-  constexpr int kTagBatch = 8;
-  for (int32_t i0 = tid; i0 < d; i0 += blockDim.x * kTagBatch) {
-    uint64_t e[kTagBatch];
-    int32_t ti[kTagBatch];
-#pragma unroll
-    for (int r = 0; r < kTagBatch; ++r) {
-      const int32_t i = i0 + r * blockDim.x;
-      e[r] = i < d ? out[i] : 0ull;
-    }
-#pragma unroll
-    for (int r = 0; r < kTagBatch; ++r) {
-      const int32_t i = i0 + r * blockDim.x;
-      ti[r] = i < d ? A.tinfo[ent_node(e[r])] : 0;
-    }
-#pragma unroll
-    for (int r = 0; r < kTagBatch; ++r) {
-      const int32_t i = i0 + r * blockDim.x;
-      if (i < d) out[i] = e[r] | tag_of(ti[r], k);
-    }
-  }
   __syncthreads();
-  if (tid == 0) B.tick[1] = now_ticks();
   return true;
 }
 
@@ -1024,7 +1011,7 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
   const int32_t niu = load_agent(&A.inbox_cur[u]);
   const int32_t niv = load_agent(&A.inbox_cur[v]);
   uint64_t t_lists = 0;
-  if (tid == 0) { B.tick[0] = 0; B.tick[1] = 0; }
+  if (tid == 0) B.tick[0] = 0;
 
   if (giant) {
     // Both lists sorted separately (a giant's straight from its bitmap, a
@@ -1099,13 +1086,10 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
   // of u among the disjoint ones. Each thread takes kPer consecutive
   // entries, so one workgroup scan covers kPer * blockDim entries.
   int32_t nD = 0, a = 0;
-  if (tid == 0) { B.own_cp[0] = 0; B.own_cp[1] = 0; B.emit_d = 0; B.emit_lo = 0; }
-  __syncthreads();
-  int32_t own_cp0 = 0, own_cp1 = 0, emit_d = 0;
   for (int32_t c = 0; c < s; c += nt * kPer) {
     const int32_t i0 = c + tid * kPer;
     int32_t nodes[kPer + 2];
-    uint32_t meta[kPer];   // bit 0: tag is partner, bit 1: side, bit 2: tag is emit
+    uint32_t meta[kPer];   // bit 0: the partner, bit 1: side
 #pragma unroll
     for (int r = 0; r < kPer + 2; ++r) {
       const int32_t i = i0 - 1 + r;
@@ -1117,8 +1101,8 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
       meta[r] = 0;
       if (i < s) {
         const uint64_t e = E[i];
-        meta[r] = (ent_tag(e) == kTagPartner ? 1u : 0u) | ((uint32_t)ent_side(e) << 1) |
-                  (ent_tag(e) == kTagEmit ? 4u : 0u);
+        const int sd = ent_side(e);
+        meta[r] = (ent_node(e) == (sd ? u : v) ? 1u : 0u) | ((uint32_t)sd << 1);
       }
     }
     int32_t cnt = 0, cntu = 0;
@@ -1133,9 +1117,6 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
         dmask |= 1u << r;
         ++cnt;
         if (!(meta[r] & 2u)) ++cntu;
-        if (meta[r] & 4u) ++emit_d;
-      } else if (isP || (meta[r] & 4u)) {
-        if (meta[r] & 2u) ++own_cp1; else ++own_cp0;
       }
     }
     int32_t tot;
@@ -1152,45 +1133,21 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
     nD += tot & 0xFFFF;
     a += tot >> 16;
   }
-  own_cp0 = wave_sum(own_cp0);
-  own_cp1 = wave_sum(own_cp1);
-  emit_d = wave_sum(emit_d);
-  if (lane_id() == 0) {
-    if (own_cp0) atomicAdd(&B.own_cp[0], own_cp0);
-    if (own_cp1) atomicAdd(&B.own_cp[1], own_cp1);
-    if (emit_d) atomicAdd(&B.emit_d, emit_d);
-  }
   __syncthreads();
   const uint64_t t_classified = now_ticks();
   block_split(D, nD, a, A.seed, A.round, k, B.sboff, 2 * kTradeBlock);
-  // Own-row entries are reserved before anything is released: a later trade
-  // released below may emit into these two rows at once.
-  {
-    const bool lo_is_u = a <= nD - a;
-    int32_t ce = 0;
-    for (int32_t j = (lo_is_u ? 0 : a) + tid; j < (lo_is_u ? a : nD); j += nt)
-      ce += ent_tag(E[D[j]]) == kTagEmit ? 1 : 0;
-    ce = wave_sum(ce);
-    if (lane_id() == 0 && ce) atomicAdd(&B.emit_lo, ce);
-    __syncthreads();
-    if (tid == 0) {
-      const int32_t eu = lo_is_u ? B.emit_lo : B.emit_d - B.emit_lo;
-      const int32_t ou = B.own_cp[0] + eu, ov = B.own_cp[1] + (B.emit_d - eu);
-      B.own_cp[0] = ou;
-      B.own_cp[1] = ov;
-      // the own rows are untouched this round until now
-      if (ou && atomic_add(&A.out_cur[u], ou) != 0) raise_error(A, kErrOut, k, -2 - u);
-      if (ov && atomic_add(&A.out_cur[v], ov) != 0) raise_error(A, kErrOut, k, -2 - v);
-      B.cnt[1] = 0;
-      B.cnt[2] = 0;
-      B.cnt[3] = 0;
-    }
-    __syncthreads();
+  if (tid == 0) {
+    B.cnt[1] = 0;
+    B.cnt[2] = 0;
+    B.cnt[3] = 0;
   }
+  __syncthreads();
 
   const uint64_t t_split = now_ticks();
-  // ---- write and release (s items). Large trades open this phase to idle
-  // wavefronts of the whole kernel through their write job.
+  // ---- write and release (s items). Own-row entries fill the two rows from
+  // their back (own_cur), so later trades released here may emit into them
+  // from the front at once. Large trades open this phase to idle workgroups
+  // through their write job.
   WriteCounts W{0, 0, 0};
   const int w = tid >> 6;
   ItemSrc S{E, D, k, u, v, s, nD, a, du, dv, bu, bv};
@@ -1252,8 +1209,9 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
   }
   __syncthreads();
   if (tid == 0) {
-    if ((B.cnt[1] != B.own_cp[0] || B.cnt[2] != B.own_cp[1]) && !load_agent(&A.ctrl[cw(kCwAbort)]))
-      raise_error(A, kErrOut, k, -1);
+    // the back parts of the own rows, for the row check after the kernel
+    if (B.cnt[1]) atomic_add(&A.own_cur[u], B.cnt[1]);
+    if (B.cnt[2]) atomic_add(&A.own_cur[v], B.cnt[2]);
     counters[0] += (unsigned long long)s;
     counters[4] += t_gathered - t_begin;
     counters[5] += t_split - t_gathered;
@@ -1271,7 +1229,7 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
       T[12] = nD;
       T[13] = a;
       T[14] = B.tick[0] ? (int64_t)B.tick[0] : -1;
-      T[15] = B.tick[1] ? (int64_t)B.tick[1] : -1;
+      T[15] = -1;
     }
   }
   counters[1] += W.fwd;
