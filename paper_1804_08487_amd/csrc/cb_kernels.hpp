@@ -82,6 +82,7 @@ struct HelpJob {
                                  // phase 1: output list there
     int32_t k, u, v, s, nD, a, du, dv;
     int32_t phase, gi, side, d;  // phase 1: giant id, side and size of the list
+    int32_t gu, gv;              // phase 2: giant ids of u and v (-1: none)
   } f;
 };
 constexpr int kMatchCap = 2048;       // bucket size sorted in LDS by k_match_sort

@@ -262,6 +262,7 @@ struct ItemSrc {
   const int32_t* D;
   int32_t k, u, v, s, nD, a, du, dv;
   int64_t bu, bv;
+  int32_t gu, gv;   // giant ids of u and v (-1: none); their bitmaps are cleared here
 };
 
 struct WriteCounts {   // per lane
@@ -308,11 +309,20 @@ __device__ __forceinline__ void write_range(const TradeArgs& A, const ItemSrc& S
         towner[r] = ent_side(e) ? S.v : S.u;
       }
     }
-    // members of a giant node's list learn their tag here, one gather each
+    // members of a giant node's list learn their tag here, one gather each,
+    // and their bitmap words are cleared for the next round (every member of
+    // a giant's set is an item of this trade; nothing reads the set again
+    // this round)
     int32_t tinf[kBatch];
 #pragma unroll
-    for (int r = 0; r < kBatch; ++r)
-      tinf[r] = (tx[r] >= 0 && ttag[r] == kTagUnknown) ? A.tinfo[tx[r]] : 0;
+    for (int r = 0; r < kBatch; ++r) {
+      const bool unk = tx[r] >= 0 && ttag[r] == kTagUnknown;
+      tinf[r] = unk ? A.tinfo[tx[r]] : 0;
+      if (unk) {
+        if (S.gu >= 0) A.gs.bm[(int64_t)S.gu * A.gs.gwords + (tx[r] >> 6)] = 0ull;
+        if (S.gv >= 0) A.gs.bm[(int64_t)S.gv * A.gs.gwords + (tx[r] >> 6)] = 0ull;
+      }
+    }
 #pragma unroll
     for (int r = 0; r < kBatch; ++r) {
       if (tx[r] >= 0 && ttag[r] == kTagUnknown) ttag[r] = tag_of(tinf[r], S.k);
@@ -476,7 +486,6 @@ __device__ __forceinline__ void extract_chunk(const TradeArgs& A, int32_t k, int
       const int32_t at = lo[t] + wave_incl_scan(pc) - pc;
       if (wave_sum(pc) != hi[t] - lo[t]) bad = true;
       const int64_t wi = (int64_t)jj * kWave + l;
-      if (bits) bm[wi] = 0ull;
       int32_t idx = 0;
       while (bits) {
         const int bit = __builtin_ctzll(bits);
@@ -606,6 +615,8 @@ __device__ __forceinline__ bool try_help(const TradeArgs& A, int32_t b, WriteCou
   S.dv = load_agent(&J->f.dv);
   S.bu = load_agent64(&J->f.bu);
   S.bv = load_agent64(&J->f.bv);
+  S.gu = load_agent(&J->f.gu);
+  S.gv = load_agent(&J->f.gv);
   const int32_t first = c * kHelpChunk;
   const int32_t end = first + kHelpChunk < S.s ? first + kHelpChunk : S.s;
   write_range<true>(A, S, first, end, kWave * kBatch, J->c.own, W);
@@ -895,7 +906,8 @@ __device__ __forceinline__ bool gather_list(const TradeArgs& A, int32_t k, int64
 }
 
 // Write giant gi's neighbour set, ascending, as entries of `side` of trade k
-// into out[0..d), and clear the bitmap and its counts for the next round.
+// into out[0..d), and clear its counts for the next round (the write phase
+// clears its words).
 // Workgroup-wide; false (error raised) if the set does not hold d members.
 // Wave w takes 64 superblocks of each block of superblocks, 32 loaded at a
 // time, a lane covering 8 words. The members' tags are left unknown: the
@@ -958,7 +970,6 @@ __device__ __forceinline__ bool extract_giant(const TradeArgs& A, int32_t k, int
           unsigned long long bits = word[g][i];
           if (!bits) continue;
           const int64_t wi = jj * kWave + part * 8 + i;
-          bm[wi] = 0ull;
           while (bits) {
             const int bit = __builtin_ctzll(bits);
             bits &= bits - 1;
@@ -1150,7 +1161,7 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
   // through their write job.
   WriteCounts W{0, 0, 0};
   const int w = tid >> 6;
-  ItemSrc S{E, D, k, u, v, s, nD, a, du, dv, bu, bv};
+  ItemSrc S{E, D, k, u, v, s, nD, a, du, dv, bu, bv, gu, gv};
   if (A.help_min == 0 || s < A.help_min || (int)blockIdx.x >= kMaxJobs) {
     write_range<false>(A, S, w * kWave * kBatch, s, kWavesPerBlock * kWave * kBatch, B.cnt + 1, W);
   } else {
@@ -1175,6 +1186,8 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
       store_agent(&J->f.a, a);
       store_agent(&J->f.du, du);
       store_agent(&J->f.dv, dv);
+      store_agent(&J->f.gu, gu);
+      store_agent(&J->f.gv, gv);
       store_agent(&J->f.phase, 2);
       open_job(A, J, nchunks);
     }
