@@ -558,9 +558,14 @@ cb_status graph_upload(int64_t n, const int64_t* row_ptr, const int32_t* col, vo
     delete g;
     return fail(CB_ENOTSIMPLE, "upload validation: " + error_bits_text(err));
   }
-  // giant nodes: the default threshold keeps every other pair within one
-  // workgroup's LDS; it rises if the bitmaps would take too much memory
+  // giant nodes: the default threshold is max(6144, n / 1024). Reading a
+  // giant's set back costs n / 8 bytes of bitmap whatever its degree, sorting
+  // a list costs in proportion to the degree; measured on MI355X the two meet
+  // near degree n / 1024 (16384 at n = 2^24), and 6144 keeps every pair below
+  // it within one workgroup's LDS. It rises further if the bitmaps would take
+  // too much memory.
   {
+    const int64_t min_deg = std::max<int64_t>(kGiantMinDeg, n / 1024);
     size_t free_b = 0, total_b = 0;
     (void)hipMemGetInfo(&free_b, &total_b);
     const double budget = std::min(64.0 * (1ull << 30), 0.4 * (double)free_b);
@@ -569,11 +574,11 @@ cb_status graph_upload(int64_t n, const int64_t* row_ptr, const int32_t* col, vo
     std::vector<int64_t> degs;
     for (int64_t x = 0; x < n; ++x) {
       const int64_t d = row_ptr[x + 1] - row_ptr[x];
-      if (d >= kGiantMinDeg) degs.push_back(d);
+      if (d >= min_deg) degs.push_back(d);
     }
     std::sort(degs.begin(), degs.end(), std::greater<int64_t>());
     const int64_t fit = (int64_t)(budget / per_giant);
-    int64_t thr = kGiantMinDeg;
+    int64_t thr = min_deg;
     if ((int64_t)degs.size() > fit) thr = fit > 0 ? degs[(size_t)fit - 1] + 1 : INT64_MAX;
     if (thr == INT64_MAX || degs.empty()) thr = 0;
     cb_status gs = setup_giants(g, thr, row_ptr);
