@@ -999,7 +999,118 @@ __device__ __forceinline__ bool extract_giant(const TradeArgs& A, int32_t k, int
 }
 
    // items per thread whose atomics are in flight together
+
 constexpr int kPer = 8;     // consecutive entries per thread in the classification scan
+
+constexpr int32_t kFastOther = 2048;   // other-side sizes of the one-pass giant classification
+
+// One giant side G (ascending, d_g entries of side sh, node h) and a small
+// other side O (ascending in LDS, d_o <= kFastOther entries, node o): write
+// the merged list E and the disjoint / kept index array D in one pass.
+// An entry's merged position is its index plus the other list's entries
+// below it; its index among the disjoint entries is that position minus the
+// kept entries below it (kept ones go from the back by the same count). The
+// kept entries follow from O alone: a shared neighbour x gives the keys
+// (x, 0) and (x, 1), the partner edge gives O's entry for h and G's entry
+// for o. Workgroup-wide; sets *nD and *a in every thread.
+__device__ __forceinline__ void giant_fast_classify(const uint64_t* G, int32_t d_g, int sh, int32_t h,
+                                                    int32_t o, int32_t d_o, BigLds& B, uint64_t* E,
+                                                    int32_t* D, int32_t s, int32_t* nD_out, int32_t* a_out) {
+  const int tid = threadIdx.x;
+  const int nt = blockDim.x;
+  const int so = 1 - sh;
+  const uint64_t* O = B.u.tile.E;
+  int32_t* posO = B.u.tile.D;                  // merged position of O[j]
+  int32_t* kc = B.u.tile.D + kFastOther;       // kept entries O[j] stands for (0, 1 or 2)
+  uint64_t* Kk = reinterpret_cast<uint64_t*>(B.u.tile.D + 2 * kFastOther);   // kept keys from O
+  if (tid == 0) { B.cnt[0] = 0; B.cnt[1] = 0; }
+  __syncthreads();
+  for (int32_t j = tid; j < d_o; j += nt) {
+    const int32_t x = ent_node(O[j]);
+    const uint64_t kx0 = (uint64_t)x << 1;
+    int32_t lo = 0, hi = d_g;
+    while (lo < hi) {
+      const int32_t mid = (lo + hi) >> 1;
+      if ((G[mid] >> 32) < kx0) lo = mid + 1; else hi = mid;
+    }
+    const bool common = lo < d_g && ent_node(G[lo]) == x;
+    const bool partner = x == h;
+    posO[j] = j + lo + ((common && sh < so) ? 1 : 0);
+    kc[j] = common ? 2 : (partner ? 1 : 0);
+    if (common) atomicAdd(&B.cnt[0], 1);
+    if (partner) B.cnt[1] = 1;
+  }
+  __syncthreads();
+  int32_t nK1 = 0;
+  for (int32_t j0 = 0; j0 < d_o; j0 += nt) {
+    const int32_t j = j0 + tid;
+    const int32_t c = j < d_o ? kc[j] : 0;
+    int32_t tot;
+    const int32_t p = nK1 + block_excl_scan(c, B.scan, &tot);
+    if (c == 2) {
+      const uint64_t kx0 = (uint64_t)ent_node(O[j]) << 1;
+      Kk[p] = kx0;
+      Kk[p + 1] = kx0 | 1ull;
+    } else if (c == 1) {
+      Kk[p] = O[j] >> 32;
+    }
+    nK1 += tot;
+  }
+  __syncthreads();
+  const int32_t n_common = B.cnt[0];
+  const bool edge = B.cnt[1] != 0;
+  const uint64_t kgp = ((uint64_t)o << 1) | (uint64_t)sh;   // key of G's partner entry
+  // giant side: a thread takes kPer consecutive entries; both ranks only grow
+  for (int32_t i0 = tid * kPer; i0 < d_g; i0 += nt * kPer) {
+    int32_t ro = -1, rk = 0;
+    for (int r = 0; r < kPer && i0 + r < d_g; ++r) {
+      const int32_t i = i0 + r;
+      const uint64_t e = G[i];
+      const uint64_t key = e >> 32;
+      if (ro < 0) {
+        int32_t lo = 0, hi = d_o;
+        while (lo < hi) {
+          const int32_t mid = (lo + hi) >> 1;
+          if ((O[mid] >> 32) < key) lo = mid + 1; else hi = mid;
+        }
+        ro = lo;
+        lo = 0;
+        hi = nK1;
+        while (lo < hi) {
+          const int32_t mid = (lo + hi) >> 1;
+          if (Kk[mid] < key) lo = mid + 1; else hi = mid;
+        }
+        rk = lo;
+      } else {
+        while (ro < d_o && (O[ro] >> 32) < key) ++ro;
+        while (rk < nK1 && Kk[rk] < key) ++rk;
+      }
+      const int32_t x = ent_node(e);
+      const bool common = sh < so ? (ro < d_o && ent_node(O[ro]) == x) : (ro > 0 && ent_node(O[ro - 1]) == x);
+      const int32_t pe = i + ro;
+      const int32_t rkt = rk + ((edge && kgp < key) ? 1 : 0);
+      E[pe] = e;
+      if (common || x == o) D[s - 1 - rkt] = pe; else D[pe - rkt] = pe;
+    }
+  }
+  // other side
+  for (int32_t j = tid; j < d_o; j += nt) {
+    const uint64_t e = O[j];
+    const uint64_t key = e >> 32;
+    int32_t lo = 0, hi = nK1;
+    while (lo < hi) {
+      const int32_t mid = (lo + hi) >> 1;
+      if (Kk[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    const int32_t rkt = lo + ((edge && kgp < key) ? 1 : 0);
+    const int32_t pe = posO[j];
+    E[pe] = e;
+    if (kc[j]) D[s - 1 - rkt] = pe; else D[pe - rkt] = pe;
+  }
+  __syncthreads();
+  *nD_out = s - nK1 - (edge ? 1 : 0);
+  *a_out = (sh == 0 ? d_g : d_o) - n_common - (edge ? 1 : 0);
+}
 
 __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds& B, uint64_t* slot,
                           unsigned long long* counters) {
@@ -1022,6 +1133,8 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
   const int32_t niu = load_agent(&A.inbox_cur[u]);
   const int32_t niv = load_agent(&A.inbox_cur[v]);
   uint64_t t_lists = 0;
+  int32_t nD = 0, a = 0;
+  bool classified = false;   // E and D already built by the one-pass giant path
   if (tid == 0) B.tick[0] = 0;
 
   if (giant) {
@@ -1060,13 +1173,19 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
       __syncthreads();
     }
     t_lists = now_ticks();
+    const int gside = gu >= 0 ? 0 : 1;
+    if ((gu >= 0) != (gv >= 0) && xside < 0 && lds_side == 1 - gside && (gside ? du : dv) <= kFastOther) {
+      giant_fast_classify(L2 + (gside ? du : 0), gside ? dv : du, gside, gside ? v : u, gside ? u : v,
+                          gside ? du : dv, B, E, D, s, &nD, &a);
+      classified = true;
+    }
     auto list_at = [&](int sd, int32_t i) -> uint64_t {
       if (sd == lds_side) return B.u.tile.E[i];
       if (sd == xside) return load_agent_u64(&X[i]);
       return L2[(sd ? du : 0) + i];
     };
     // position in the merged list = own index + members of the other list below
-    for (int32_t i = tid; i < s; i += nt) {
+    for (int32_t i = tid; i < (classified ? 0 : s); i += nt) {
       const int sd = i < du ? 0 : 1;
       const int32_t idx = sd ? i - du : i;
       const uint64_t e = list_at(sd, idx);
@@ -1096,8 +1215,7 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
   // ones (shared neighbours, partner) to D[nD..s) from the back; a = entries
   // of u among the disjoint ones. Each thread takes kPer consecutive
   // entries, so one workgroup scan covers kPer * blockDim entries.
-  int32_t nD = 0, a = 0;
-  for (int32_t c = 0; c < s; c += nt * kPer) {
+  for (int32_t c = 0; c < (classified ? 0 : s); c += nt * kPer) {
     const int32_t i0 = c + tid * kPer;
     int32_t nodes[kPer + 2];
     uint32_t meta[kPer];   // bit 0: the partner, bit 1: side
