@@ -175,4 +175,74 @@ __device__ __forceinline__ T* block_radix_sort(T* a, T* b, int64_t s, int keybit
   return src;
 }
 
+// Stable LSD radix sort (8-bit digits) of a[0..s) by the low `keybits` bits
+// of (e >> 32), through b[0..s) (each in LDS or global memory; the passes
+// alternate between them). Wavefront w ranks the fixed
+// segment [w * seg, (w + 1) * seg) in order, so a pass needs three barriers:
+// per-wavefront digit counts, offsets in (digit, wavefront) order, scatter.
+// cnt: (blockDim / 64) * 256 ints of LDS; scan: blockDim / 64 + 1 ints.
+// Returns the buffer that holds the sorted sequence. Workgroup-wide.
+__device__ __forceinline__ uint64_t* seg_radix_sort(uint64_t* a, uint64_t* b, int32_t s, int keybits,
+                                                    int32_t* cnt, int32_t* scan) {
+  const int tid = threadIdx.x;
+  const int w = tid >> 6;
+  const int l = lane_id();
+  const int nw = blockDim.x >> 6;
+  const uint64_t lt = (1ull << l) - 1ull;
+  const int32_t seg = ((s + nw - 1) / nw + kWave - 1) / kWave * kWave;
+  const int32_t lo = w * seg < s ? w * seg : s;
+  const int32_t hi = lo + seg < s ? lo + seg : s;
+  int32_t* c = cnt + w * 256;
+  uint64_t* src = a;
+  uint64_t* dst = b;
+  for (int shift = 0; shift < keybits; shift += 8) {
+    for (int d = l; d < 256; d += kWave) c[d] = 0;
+    wave_sync();
+    for (int32_t i = lo + l; i < hi; i += kWave) atomicAdd(&c[(uint32_t)(src[i] >> (32 + shift)) & 255u], 1);
+    __syncthreads();
+    int32_t tot = 0;
+    if (tid < 256)
+      for (int q = 0; q < nw; ++q) tot += cnt[q * 256 + tid];
+    int32_t all;
+    const int32_t base = block_excl_scan(tid < 256 ? tot : 0, scan, &all);
+    if (tid < 256) {
+      int32_t run = base;
+      for (int q = 0; q < nw; ++q) {
+        const int32_t t = cnt[q * 256 + tid];
+        cnt[q * 256 + tid] = run;
+        run += t;
+      }
+    }
+    __syncthreads();
+    for (int32_t i0 = lo; i0 < hi; i0 += kWave) {
+      const int32_t i = i0 + l;
+      const bool valid = i < hi;
+      uint64_t e = 0;
+      uint32_t dg = 256;
+      if (valid) {
+        e = src[i];
+        dg = (uint32_t)(e >> (32 + shift)) & 255u;
+      }
+      uint64_t peers = ballot(valid);
+      if (!valid) peers = ~peers;
+#pragma unroll
+      for (int bit = 0; bit < 8; ++bit) {
+        const bool on = (dg >> bit) & 1u;
+        const uint64_t bb = ballot(on);
+        peers &= on ? bb : ~bb;
+      }
+      const int rank = popc64(peers & lt);
+      if (valid) dst[c[dg] + rank] = e;
+      wave_sync();
+      if (valid && rank == 0) c[dg] += popc64(peers);
+      wave_sync();
+    }
+    __syncthreads();
+    uint64_t* t = src;
+    src = dst;
+    dst = t;
+  }
+  return src;
+}
+
 }  // namespace cbx

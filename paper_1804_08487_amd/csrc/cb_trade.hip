@@ -1205,8 +1205,14 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
     }
     __syncthreads();
     t_lists = now_ticks();
-    if (in_lds) block_bitonic_sort(E, (uint32_t)s);
-    else E = block_radix_sort<uint64_t>(E, slot + A.smax, s, A.keybits, B.u.R);
+    // LDS ping-pong when both halves fit, else through the slot; the digit
+    // counters live in the (not yet used) LDS index array
+    if (in_lds && s <= kBigCap / 2)
+      E = seg_radix_sort(E, E + kBigCap / 2, s, A.keybits, B.u.tile.D, B.scan);
+    else if (in_lds)
+      E = seg_radix_sort(E, slot, s, A.keybits, B.u.tile.D, B.scan);
+    else
+      E = seg_radix_sort(E, slot + A.smax, s, A.keybits, B.u.tile.D, B.scan);
     __syncthreads();
   }
 
