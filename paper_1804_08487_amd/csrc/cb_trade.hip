@@ -1013,9 +1013,13 @@ constexpr int32_t kFastOther = 2048;   // other-side sizes of the one-pass giant
 // kept entries follow from O alone: a shared neighbour x gives the keys
 // (x, 0) and (x, 1), the partner edge gives O's entry for h and G's entry
 // for o. Workgroup-wide; sets *nD and *a in every thread.
+// If I is not null, the items of a shared write phase are published too
+// (entry with the side of its owner, as if the split moved nothing; the
+// positions the split touches are rewritten after it).
 __device__ __forceinline__ void giant_fast_classify(const uint64_t* G, int32_t d_g, int sh, int32_t h,
                                                     int32_t o, int32_t d_o, BigLds& B, uint64_t* E,
-                                                    int32_t* D, int32_t s, int32_t* nD_out, int32_t* a_out) {
+                                                    int32_t* D, int32_t s, int32_t* nD_out, int32_t* a_out,
+                                                    unsigned long long* I) {
   const int tid = threadIdx.x;
   const int nt = blockDim.x;
   const int so = 1 - sh;
@@ -1060,6 +1064,14 @@ __device__ __forceinline__ void giant_fast_classify(const uint64_t* G, int32_t d
   const int32_t n_common = B.cnt[0];
   const bool edge = B.cnt[1] != 0;
   const uint64_t kgp = ((uint64_t)o << 1) | (uint64_t)sh;   // key of G's partner entry
+  const int32_t nD = s - nK1 - (edge ? 1 : 0);
+  const int32_t a = (sh == 0 ? d_g : d_o) - n_common - (edge ? 1 : 0);
+  // item at disjoint position p (owner by position) or kept position p (owner by side)
+  auto put = [&](int32_t p, uint64_t e) {
+    if (!I) return;
+    const uint64_t own = p < nD ? (p < a ? 0ull : 1ull) : (uint64_t)ent_side(e);
+    store_agent_u64(&I[p], (e & ~(1ull << 32)) | (own << 32));
+  };
   // giant side: a thread takes kPer consecutive entries; both ranks only grow
   for (int32_t i0 = tid * kPer; i0 < d_g; i0 += nt * kPer) {
     int32_t ro = -1, rk = 0;
@@ -1090,7 +1102,9 @@ __device__ __forceinline__ void giant_fast_classify(const uint64_t* G, int32_t d
       const int32_t pe = i + ro;
       const int32_t rkt = rk + ((edge && kgp < key) ? 1 : 0);
       E[pe] = e;
-      if (common || x == o) D[s - 1 - rkt] = pe; else D[pe - rkt] = pe;
+      const int32_t pd = (common || x == o) ? s - 1 - rkt : pe - rkt;
+      D[pd] = pe;
+      put(pd, e);
     }
   }
   // other side
@@ -1105,11 +1119,32 @@ __device__ __forceinline__ void giant_fast_classify(const uint64_t* G, int32_t d
     const int32_t rkt = lo + ((edge && kgp < key) ? 1 : 0);
     const int32_t pe = posO[j];
     E[pe] = e;
-    if (kc[j]) D[s - 1 - rkt] = pe; else D[pe - rkt] = pe;
+    const int32_t pd = kc[j] ? s - 1 - rkt : pe - rkt;
+    D[pd] = pe;
+    put(pd, e);
   }
   __syncthreads();
-  *nD_out = s - nK1 - (edge ? 1 : 0);
-  *a_out = (sh == 0 ? d_g : d_o) - n_common - (edge ? 1 : 0);
+  *nD_out = nD;
+  *a_out = a;
+}
+
+// Items at the positions the split touched (its windows and its partners),
+// rewritten from the split disjoint array. Workgroup-wide.
+__device__ __forceinline__ void split_fix_items(const uint64_t* E, const int32_t* D, int32_t nD, int32_t a,
+                                                uint64_t seed, uint32_t round, int32_t k,
+                                                unsigned long long* I) {
+  const int32_t T = split_steps(nD, a);
+  const bool fwd = a <= nD - a;
+  for (int32_t t = threadIdx.x; t < T; t += blockDim.x) {
+    const int32_t j = fwd ? t : nD - 1 - t;
+    const int32_t r = split_partner(nD, a, t, seed, round, k);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int32_t p = q ? r : j;
+      const uint64_t e = E[D[p]];
+      store_agent_u64(&I[p], (e & ~(1ull << 32)) | ((p < a ? 0ull : 1ull) << 32));
+    }
+  }
 }
 
 __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds& B, uint64_t* slot,
@@ -1135,6 +1170,9 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
   uint64_t t_lists = 0;
   int32_t nD = 0, a = 0;
   bool classified = false;   // E and D already built by the one-pass giant path
+  bool items_ready = false;  // ... and the shared write phase's items too
+  const bool share = A.help_min > 0 && s >= A.help_min && (int)blockIdx.x < kMaxJobs;
+  unsigned long long* Ig = reinterpret_cast<unsigned long long*>(slot + shared_list_off(A));
   if (tid == 0) B.tick[0] = 0;
 
   if (giant) {
@@ -1176,8 +1214,9 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
     const int gside = gu >= 0 ? 0 : 1;
     if ((gu >= 0) != (gv >= 0) && xside < 0 && lds_side == 1 - gside && (gside ? du : dv) <= kFastOther) {
       giant_fast_classify(L2 + (gside ? du : 0), gside ? dv : du, gside, gside ? v : u, gside ? u : v,
-                          gside ? du : dv, B, E, D, s, &nD, &a);
+                          gside ? du : dv, B, E, D, s, &nD, &a, share ? Ig : nullptr);
       classified = true;
+      items_ready = share;
     }
     auto list_at = [&](int sd, int32_t i) -> uint64_t {
       if (sd == lds_side) return B.u.tile.E[i];
@@ -1271,6 +1310,7 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
   __syncthreads();
   const uint64_t t_classified = now_ticks();
   block_split(D, nD, a, A.seed, A.round, k, B.sboff, 2 * kTradeBlock);
+  if (items_ready) split_fix_items(E, D, nD, a, A.seed, A.round, k, Ig);
   if (tid == 0) {
     B.cnt[1] = 0;
     B.cnt[2] = 0;
@@ -1286,13 +1326,13 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
   WriteCounts W{0, 0, 0};
   const int w = tid >> 6;
   ItemSrc S{E, D, k, u, v, s, nD, a, du, dv, bu, bv, gu, gv};
-  if (A.help_min == 0 || s < A.help_min || (int)blockIdx.x >= kMaxJobs) {
+  if (!share) {
     write_range<false>(A, S, w * kWave * kBatch, s, kWavesPerBlock * kWave * kBatch, B.cnt + 1, W);
   } else {
     // publish the items where other workgroups can read them, in the slot
     // region that is only ever written with agent-scope stores
-    unsigned long long* Ig = reinterpret_cast<unsigned long long*>(slot + shared_list_off(A));
-    for (int32_t o = tid; o < s; o += nt) store_agent_u64(&Ig[o], item_entry<false>(S, o));
+    if (!items_ready)
+      for (int32_t o = tid; o < s; o += nt) store_agent_u64(&Ig[o], item_entry<false>(S, o));
     publish_wait();
     __syncthreads();
     if (A.trace && tid == 0) A.trace[kTraceFields * (int64_t)k + 16] = (int64_t)now_ticks();
