@@ -1003,43 +1003,80 @@ __device__ __forceinline__ bool extract_giant(const TradeArgs& A, int32_t k, int
 constexpr int kPer = 8;     // consecutive entries per thread in the classification scan
 
 constexpr int32_t kFastOther = 2048;   // other-side sizes of the one-pass giant classification
+constexpr int kRing = 256;             // nonzero bitmap words buffered per wavefront
+constexpr int kChunkBatch = 4;         // 1 KiB bitmap chunks loaded together per wavefront
 
-// One giant side G (ascending, d_g entries of side sh, node h) and a small
-// other side O (ascending in LDS, d_o <= kFastOther entries, node o): write
-// the merged list E and the disjoint / kept index array D in one pass.
-// An entry's merged position is its index plus the other list's entries
-// below it; its index among the disjoint entries is that position minus the
-// kept entries below it (kept ones go from the back by the same count). The
-// kept entries follow from O alone: a shared neighbour x gives the keys
-// (x, 0) and (x, 1), the partner edge gives O's entry for h and G's entry
-// for o. Workgroup-wide; sets *nD and *a in every thread.
-// If I is not null, the items of a shared write phase are published too
-// (entry with the side of its owner, as if the split moved nothing; the
-// positions the split touches are rewritten after it).
-__device__ __forceinline__ void giant_fast_classify(const uint64_t* G, int32_t d_g, int sh, int32_t h,
-                                                    int32_t o, int32_t d_o, BigLds& B, uint64_t* E,
-                                                    int32_t* D, int32_t s, int32_t* nD_out, int32_t* a_out,
-                                                    unsigned long long* I) {
+// Item of the shared write phase for the entry at D position p: the entry
+// with the side of its owner (by position among the disjoint ones, by its own
+// side among the kept ones).
+__device__ __forceinline__ void put_item(unsigned long long* I, int32_t p, uint64_t e, int32_t nD, int32_t a) {
+  const uint64_t own = p < nD ? (p < a ? 0ull : 1ull) : (uint64_t)ent_side(e);
+  store_agent_u64(&I[p], (e & ~(1ull << 32)) | (own << 32));
+}
+
+// Bits of the two words w0 (ids b .. b + 63) and w1 (ids b + 64 ..) below id x.
+__device__ __forceinline__ int32_t bits_below(uint64_t w0, uint64_t w1, int32_t b, int32_t x) {
+  int32_t c = 0;
+  if (x >= b + 64) c += popc64(w0);
+  else if (x > b) c += popc64(w0 & ((1ull << (x - b)) - 1ull));
+  if (x >= b + 128) c += popc64(w1);
+  else if (x > b + 64) c += popc64(w1 & ((1ull << (x - b - 64)) - 1ull));
+  return c;
+}
+
+// One giant side (node h, side sh, d_g members in giant gi's bitmap) and a
+// small other side O (ascending in LDS, d_o <= kFastOther entries, node o):
+// the merged list E and the disjoint / kept index array D in one pass over
+// the bitmap, without materialising the giant's sorted list.
+//
+// A member's merged position is its rank among the giant's members plus the
+// O entries below it; its disjoint position is that minus the kept entries
+// below it (kept ones fill D from the back by the same count). The kept
+// entries follow from O alone: a shared neighbour x gives the keys (x, 0) and
+// (x, 1), the partner edge gives O's entry for h and the giant's for o. The
+// bitmap is cut into chunks of 128 words (8192 ids); in a chunk that holds no
+// node of O and not o, both counts are constant, so its members need no
+// search. Each wavefront takes a contiguous range of superblocks, starting at
+// the prefix of the superblock counts before it; within a range the nonzero
+// words (about a fifth of all at the densities here) are compacted into an
+// LDS ring and expanded one word per lane, which keeps the lanes busy and the
+// loads coalesced. If I is not null, the items of a shared write phase are
+// published too (as if the split moved nothing; the positions the split
+// touches are rewritten after it). Clears the superblock counts of the
+// bitmap; its words are cleared when the edges are written. Workgroup-wide;
+// sets *nD and *a in every thread. False (error raised) if the bitmap does
+// not hold d_g members.
+__device__ __forceinline__ bool giant_fused(const TradeArgs& A, int32_t k, int32_t gi, int sh, int32_t d_g,
+                                            int32_t h, int32_t o, int32_t d_o, BigLds& B, uint64_t* E,
+                                            int32_t* D, int32_t s, int32_t* nD_out, int32_t* a_out,
+                                            unsigned long long* I) {
   const int tid = threadIdx.x;
   const int nt = blockDim.x;
+  const int w = tid >> 6;
+  const int l = lane_id();
+  const int nw = nt >> 6;
   const int so = 1 - sh;
   const uint64_t* O = B.u.tile.E;
   int32_t* posO = B.u.tile.D;                  // merged position of O[j]
   int32_t* kc = B.u.tile.D + kFastOther;       // kept entries O[j] stands for (0, 1 or 2)
   uint64_t* Kk = reinterpret_cast<uint64_t*>(B.u.tile.D + 2 * kFastOther);   // kept keys from O
-  if (tid == 0) { B.cnt[0] = 0; B.cnt[1] = 0; }
+  uint64_t* ringW = B.u.tile.E + kFastOther + w * kRing;
+  int4* ringM = reinterpret_cast<int4*>(B.u.tile.E + kFastOther + kWavesPerBlock * kRing) + w * kRing;
+  const int64_t gwords = A.gs.gwords;
+  const int64_t nsb = gwords >> 6;
+  const unsigned long long* bm = A.gs.bm + (int64_t)gi * gwords;
+  int32_t* sc = A.gs.sc + (int64_t)gi * nsb;
+  // The set was filled by other workgroups' atomics before this trade became
+  // ready; drop whatever this compute unit's cache holds, then read it with
+  // plain (wide) loads.
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  if (tid == 0) { B.cnt[0] = 0; B.cnt[1] = 0; B.cnt[2] = 0; }
   __syncthreads();
+  // O entries: shared neighbour (bit set in the giant's set) or partner
   for (int32_t j = tid; j < d_o; j += nt) {
     const int32_t x = ent_node(O[j]);
-    const uint64_t kx0 = (uint64_t)x << 1;
-    int32_t lo = 0, hi = d_g;
-    while (lo < hi) {
-      const int32_t mid = (lo + hi) >> 1;
-      if ((G[mid] >> 32) < kx0) lo = mid + 1; else hi = mid;
-    }
-    const bool common = lo < d_g && ent_node(G[lo]) == x;
+    const bool common = (bm[x >> 6] >> (x & 63)) & 1ull;
     const bool partner = x == h;
-    posO[j] = j + lo + ((common && sh < so) ? 1 : 0);
     kc[j] = common ? 2 : (partner ? 1 : 0);
     if (common) atomicAdd(&B.cnt[0], 1);
     if (partner) B.cnt[1] = 1;
@@ -1060,52 +1097,199 @@ __device__ __forceinline__ void giant_fast_classify(const uint64_t* G, int32_t d
     }
     nK1 += tot;
   }
+  // superblock range of this wavefront (an even number: whole chunks)
+  const int64_t R = (((nsb + nw - 1) / nw) + 1) & ~(int64_t)1;
+  const int64_t sb_lo = (int64_t)w * R < nsb ? (int64_t)w * R : nsb;
+  const int64_t sb_hi = sb_lo + R < nsb ? sb_lo + R : nsb;
+  int32_t my = 0;
+  for (int64_t j = sb_lo + l; j < sb_hi; j += kWave) my += sc[j];
+  my = wave_sum(my);
+  if (l == 0) B.sboff[w] = my;
   __syncthreads();
+  int32_t run = 0, total = 0;
+  for (int q = 0; q < nw; ++q) {
+    const int32_t c = B.sboff[q];
+    if (q < w) run += c;
+    total += c;
+  }
   const int32_t n_common = B.cnt[0];
   const bool edge = B.cnt[1] != 0;
-  const uint64_t kgp = ((uint64_t)o << 1) | (uint64_t)sh;   // key of G's partner entry
+  const uint64_t kgp = ((uint64_t)o << 1) | (uint64_t)sh;   // key of the giant's partner entry
   const int32_t nD = s - nK1 - (edge ? 1 : 0);
   const int32_t a = (sh == 0 ? d_g : d_o) - n_common - (edge ? 1 : 0);
-  // item at disjoint position p (owner by position) or kept position p (owner by side)
-  auto put = [&](int32_t p, uint64_t e) {
-    if (!I) return;
-    const uint64_t own = p < nD ? (p < a ? 0ull : 1ull) : (uint64_t)ent_side(e);
-    store_agent_u64(&I[p], (e & ~(1ull << 32)) | (own << 32));
-  };
-  // giant side: a thread takes kPer consecutive entries; both ranks only grow
-  for (int32_t i0 = tid * kPer; i0 < d_g; i0 += nt * kPer) {
-    int32_t ro = -1, rk = 0;
-    for (int r = 0; r < kPer && i0 + r < d_g; ++r) {
-      const int32_t i = i0 + r;
-      const uint64_t e = G[i];
-      const uint64_t key = e >> 32;
-      if (ro < 0) {
+  if (total != d_g) {
+    __syncthreads();
+    if (tid == 0) raise_error(A, kErrGather, k, 2000000 + total - d_g);
+    return false;
+  }
+  const int32_t run0 = run;
+
+  // members of one ring word: rank r of its lowest bit, word index wi; fast
+  // chunks carry the O and kept counts below them (ro >= 0), slow ones ro < 0
+  auto expand = [&](uint64_t bits, int4 m) {
+    int32_t r = m.x;
+    while (bits) {
+      const int bit = __builtin_ctzll(bits);
+      bits &= bits - 1ull;
+      const int32_t x = m.y * 64 + bit;
+      const int32_t i = r++;
+      if (i >= d_g) continue;
+      const uint64_t e = make_entry(x, sh, kTagUnknown);
+      int32_t pe, pd;
+      if (m.z >= 0) {
+        pe = i + m.z;
+        pd = pe - m.w;
+      } else {
+        const uint64_t key = e >> 32;
         int32_t lo = 0, hi = d_o;
         while (lo < hi) {
           const int32_t mid = (lo + hi) >> 1;
           if ((O[mid] >> 32) < key) lo = mid + 1; else hi = mid;
         }
-        ro = lo;
+        const int32_t ro = lo;
         lo = 0;
         hi = nK1;
         while (lo < hi) {
           const int32_t mid = (lo + hi) >> 1;
           if (Kk[mid] < key) lo = mid + 1; else hi = mid;
         }
-        rk = lo;
-      } else {
-        while (ro < d_o && (O[ro] >> 32) < key) ++ro;
-        while (rk < nK1 && Kk[rk] < key) ++rk;
+        const bool common = sh < so ? (ro < d_o && ent_node(O[ro]) == x) : (ro > 0 && ent_node(O[ro - 1]) == x);
+        pe = i + ro;
+        const int32_t rkt = lo + ((edge && kgp < key) ? 1 : 0);
+        pd = (common || x == o) ? s - 1 - rkt : pe - rkt;
       }
-      const int32_t x = ent_node(e);
-      const bool common = sh < so ? (ro < d_o && ent_node(O[ro]) == x) : (ro > 0 && ent_node(O[ro - 1]) == x);
-      const int32_t pe = i + ro;
-      const int32_t rkt = rk + ((edge && kgp < key) ? 1 : 0);
       E[pe] = e;
-      const int32_t pd = (common || x == o) ? s - 1 - rkt : pe - rkt;
       D[pd] = pe;
-      put(pd, e);
+      if (I) put_item(I, pd, e, nD, a);
     }
+  };
+
+  // O and kept entries below the current chunk, next node of O or o at or
+  // after it (all uniform across the wavefront)
+  const int32_t id_lo = (int32_t)(sb_lo * 4096);
+  int32_t ro = 0, rk = 0;
+  {
+    int32_t lo = 0, hi = d_o;
+    while (lo < hi) {
+      const int32_t mid = (lo + hi) >> 1;
+      if (ent_node(O[mid]) < id_lo) lo = mid + 1; else hi = mid;
+    }
+    ro = lo;
+    lo = 0;
+    hi = nK1;
+    while (lo < hi) {
+      const int32_t mid = (lo + hi) >> 1;
+      if (Kk[mid] < ((uint64_t)id_lo << 1)) lo = mid + 1; else hi = mid;
+    }
+    rk = lo;
+  }
+  auto next_special = [&](int64_t from) -> int64_t {
+    int64_t sp = ro < d_o ? (int64_t)ent_node(O[ro]) : INT64_MAX;
+    if (o >= from && o < sp) sp = o;
+    return sp;
+  };
+  int64_t sp = next_special(id_lo);
+  int32_t head = 0, fill = 0;   // ring counters (positions mod kRing)
+  int32_t scsum = 0;
+  for (int64_t p0 = sb_lo; p0 < sb_hi; p0 += 8 * kWave) {
+    // superblocks p0 + 8 l .. + 7 of this lane: pair q of them is chunk 4 l + q
+    int32_t c8[8];
+    int32_t mine = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int64_t j = p0 + 8 * l + i;
+      c8[i] = j < sb_hi ? sc[j] : 0;
+      mine += c8[i];
+      if (c8[i] != 0) sc[j] = 0;
+    }
+    scsum += mine;
+    uint64_t nz[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) nz[q] = ballot(c8[2 * q] + c8[2 * q + 1] != 0);
+    const int32_t nch = (int32_t)((((sb_hi - p0) < 8 * kWave ? (sb_hi - p0) : 8 * kWave) + 1) >> 1);
+    for (int32_t c0 = 0; c0 < nch; c0 += kChunkBatch) {
+      uint4 v[kChunkBatch];
+#pragma unroll
+      for (int b = 0; b < kChunkBatch; ++b) {
+        const int32_t ch = c0 + b;
+        const int64_t wb = (p0 + 2 * ch) * 64;
+        const bool ld = ch < nch && ((nz[b & 3] >> ((c0 >> 2) + (b >> 2))) & 1ull) && wb + 2 * l < gwords;
+        v[b] = ld ? reinterpret_cast<const uint4*>(bm + wb)[l] : make_uint4(0u, 0u, 0u, 0u);
+      }
+#pragma unroll
+      for (int b = 0; b < kChunkBatch; ++b) {
+        const int32_t ch = c0 + b;
+        if (ch >= nch) break;
+        const int64_t wb = (p0 + 2 * ch) * 64;
+        const int64_t id0 = wb * 64;
+        const int64_t id_end = id0 + 128 * 64;
+        const bool slow = sp < id_end;
+        const bool ne = (nz[b & 3] >> ((c0 >> 2) + (b >> 2))) & 1ull;
+        if (!ne && !slow) continue;
+        const uint64_t w0 = ((uint64_t)v[b].y << 32) | v[b].x;
+        const uint64_t w1 = ((uint64_t)v[b].w << 32) | v[b].z;
+        const int32_t pc = popc64(w0) + popc64(w1);
+        const int32_t nzc = (w0 != 0ull ? 1 : 0) + (w1 != 0ull ? 1 : 0);
+        const int32_t pk = pc | (nzc << 16);
+        const int32_t incl = wave_incl_scan(pk);
+        const int32_t tot = wave_bcast(incl, kWave - 1);
+        const int32_t ex = incl - pk;
+        int32_t mz = -1, mw = 0;
+        if (slow) {
+          // ranks of the O nodes in this chunk among the giant's members
+          const int32_t b0 = (int32_t)id0 + 128 * l;
+          while (ro < d_o && (int64_t)ent_node(O[ro]) < id_end) {
+            const int32_t x = ent_node(O[ro]);
+            const int32_t lo = run + wave_sum(bits_below(w0, w1, b0, x));
+            if (l == 0) posO[ro] = ro + lo + ((kc[ro] == 2 && sh < so) ? 1 : 0);
+            ++ro;
+          }
+        } else {
+          mz = ro;
+          mw = rk + ((edge && (int64_t)o < id0) ? 1 : 0);
+        }
+        int32_t at = fill + (ex >> 16);
+        const int32_t r0 = run + (ex & 0xFFFF);
+        if (w0) {
+          ringW[at & (kRing - 1)] = w0;
+          ringM[at & (kRing - 1)] = make_int4(r0, (int32_t)(wb + 2 * l), mz, mw);
+          ++at;
+        }
+        if (w1) {
+          ringW[at & (kRing - 1)] = w1;
+          ringM[at & (kRing - 1)] = make_int4(r0 + popc64(w0), (int32_t)(wb + 2 * l + 1), mz, mw);
+        }
+        fill += tot >> 16;
+        run += tot & 0xFFFF;
+        if (slow) {
+          while (rk < nK1 && Kk[rk] < ((uint64_t)id_end << 1)) ++rk;
+          sp = next_special(id_end);
+        }
+        if (fill - head >= kWave) {
+          wave_sync();
+          do {
+            const int32_t p = (head + l) & (kRing - 1);
+            expand(ringW[p], ringM[p]);
+            head += kWave;
+          } while (fill - head >= kWave);
+          wave_sync();
+        }
+      }
+    }
+  }
+  wave_sync();
+  if (l < fill - head) {
+    const int32_t p = (head + l) & (kRing - 1);
+    expand(ringW[p], ringM[p]);
+  }
+  // the members found must match the superblock counts of the range
+  const int32_t scw = wave_sum(scsum);
+  if (l == 0 && run - run0 != scw) B.cnt[2] = 1;
+  __syncthreads();
+  if (B.cnt[2] != 0) {
+    __syncthreads();
+    if (tid == 0) raise_error(A, kErrGather, k, 3000000 + run - run0 - scw);
+    return false;
   }
   // other side
   for (int32_t j = tid; j < d_o; j += nt) {
@@ -1121,11 +1305,13 @@ __device__ __forceinline__ void giant_fast_classify(const uint64_t* G, int32_t d
     E[pe] = e;
     const int32_t pd = kc[j] ? s - 1 - rkt : pe - rkt;
     D[pd] = pe;
-    put(pd, e);
+    if (I) put_item(I, pd, e, nD, a);
   }
+  if (tid == 0) B.tick[0] = now_ticks();
   __syncthreads();
   *nD_out = nD;
   *a_out = a;
+  return true;
 }
 
 // Items at the positions the split touched (its windows and its partners),
@@ -1188,10 +1374,14 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
       else if (gv >= 0) xside = 1;
       if (xside >= 0 && (xside ? dv : du) < A.help_min) xside = -1;
     }
+    // exactly one giant side and a small other side: one fused pass
+    const int gside = gu >= 0 ? 0 : 1;
+    const bool fused = (gu >= 0) != (gv >= 0) && xside < 0 && (gside ? du : dv) <= kFastOther;
     for (int side = 0; side < 2; ++side) {
       const int32_t gi = side ? gv : gu;
       const int32_t d = side ? dv : du;
       const int32_t off = side ? du : 0;
+      if (fused && side == gside) continue;
       if (side == xside) {
         if (!extract_giant_shared(A, k, gi, side, d, B)) return;
       } else if (gi >= 0) {
@@ -1211,10 +1401,10 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
       __syncthreads();
     }
     t_lists = now_ticks();
-    const int gside = gu >= 0 ? 0 : 1;
-    if ((gu >= 0) != (gv >= 0) && xside < 0 && lds_side == 1 - gside && (gside ? du : dv) <= kFastOther) {
-      giant_fast_classify(L2 + (gside ? du : 0), gside ? dv : du, gside, gside ? v : u, gside ? u : v,
-                          gside ? du : dv, B, E, D, s, &nD, &a, share ? Ig : nullptr);
+    if (fused) {
+      if (!giant_fused(A, k, gside ? gv : gu, gside, gside ? dv : du, gside ? v : u, gside ? u : v,
+                       gside ? du : dv, B, E, D, s, &nD, &a, share ? Ig : nullptr))
+        return;
       classified = true;
       items_ready = share;
     }
