@@ -125,8 +125,8 @@ cb_status global_trade_steps(cb_graph* g, uint64_t seed, uint32_t round, int32_t
                                 own rows from their back (with OUT_CUR the
                                 degree after a full round) */
 #define CB_STATE_INBOX_CUR 6 /* int32[n]: edges handed to each row this round */
-#define CB_STATE_TRACE    7  /* int64[20 * floor(n/2)] (CB_OPT_TRACE): per trade k
-                                at 20k + i: i=0 tick at which it became ready
+#define CB_STATE_TRACE    7  /* int64[24 * floor(n/2)] (CB_OPT_TRACE): per trade k
+                                at 24k + i: i=0 tick at which it became ready
                                 (-1: a source), 1 start and 2 end of its
                                 execution, 3 trade whose release made it ready
                                 (-1: a source); for trades run by a workgroup
@@ -136,10 +136,14 @@ cb_status global_trade_steps(cb_graph* g, uint64_t seed, uint32_t round, int32_t
                                 3 in global scratch), 10 deg u, 11 deg v,
                                 12 disjoint entries, 13 of which u's, 14 end of
                                 the bit pass of a giant node's list (the last
-                                one taken), 15 unused; for a
-                                write phase shared with helpers 16 arrays
-                                published, 17 own chunks done, 18 all chunks
-                                done, 19 chunks written by the owner. Ticks of
+                                one taken; with a small other side, the end of
+                                the one fused pass), 15 fused pass: counts
+                                and ranges set up; for a write phase shared
+                                with helpers 16 arrays published, 17 own
+                                chunks done, 18 all chunks done, 19 chunks
+                                written by the owner; fused pass: 20 last
+                                bitmap reader done, 21 last entry writer
+                                done; 22, 23 unused. Ticks of
                                 the device's constant 100 MHz clock; -1 where
                                 not recorded */
 
@@ -168,7 +172,7 @@ cb_status graph_download_state(cb_graph* g, int32_t which, void* host, int64_t c
                                    owners in their residue class modulo this
                                    (a divisor of 64; default 2) */
 #define CB_OPT_TRACE        10  /* 1: record per-trade times (CB_STATE_TRACE);
-                                   allocates 160 bytes per trade on first use */
+                                   allocates 192 bytes per trade on first use */
 #define CB_OPT_GIANT_DEG     8  /* nodes of at least this degree keep the edges
                                    handed to them in a bitmap over all node ids
                                    (n/8 bytes each) instead of a list; 0 = none.

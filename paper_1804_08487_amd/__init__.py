@@ -168,7 +168,7 @@ class Graph:
     def state(self, which: int):
         count = {STATE_PERM: self.n, STATE_TRADE_OF: self.n, STATE_DEP: self.n // 2,
                  STATE_COL: self.nnz, STATE_OUT_CUR: self.n, STATE_INBOX_CUR: self.n, STATE_OWN_CUR: self.n,
-                 STATE_TRACE: 20 * (self.n // 2)}[which]
+                 STATE_TRACE: 24 * (self.n // 2)}[which]
         out = np.empty(max(count, 1), np.int64 if which == STATE_TRACE else np.int32)
         _check(lib().graph_download_state(self._h, which, out.ctypes.data, count))
         return out[:count]

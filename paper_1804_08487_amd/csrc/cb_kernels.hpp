@@ -53,7 +53,7 @@ constexpr int kGiantMinDeg = kBigCap / 2;   // default giant degree: any other p
 constexpr int kTradeBlock = 512;      // threads per trade-kernel workgroup (one per CU: 256 VGPRs each)
 constexpr int kWavesPerBlock = kTradeBlock / 64;
 constexpr int kStackCap = 16;         // ready trades a wavefront may keep
-constexpr int kTraceFields = 20;      // int64 per trade of the optional trace
+constexpr int kTraceFields = 24;      // int64 per trade of the optional trace
 constexpr int kMaxJobs = 64;          // workgroups that can open their write phase to helpers
 constexpr int32_t kHelpChunk = 512;   // output items per claimed chunk
 constexpr int32_t kHelpMinItems = 8192;   // default: smaller trades work alone

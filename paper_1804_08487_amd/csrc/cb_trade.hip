@@ -1003,8 +1003,28 @@ __device__ __forceinline__ bool extract_giant(const TradeArgs& A, int32_t k, int
 constexpr int kPer = 8;     // consecutive entries per thread in the classification scan
 
 constexpr int32_t kFastOther = 2048;   // other-side sizes of the one-pass giant classification
-constexpr int kRing = 256;             // nonzero bitmap words buffered per wavefront
-constexpr int kChunkBatch = 4;         // 1 KiB bitmap chunks loaded together per wavefront
+constexpr int kRing = 512;             // nonzero bitmap words buffered per producer / consumer pair
+constexpr int kPairs = kWavesPerBlock / 2;
+constexpr int kChunkBatch = 8;         // 1 KiB bitmap chunks a producer keeps in flight (twice)
+static_assert(kFastOther + 3 * kPairs * kRing + 2 * kPairs <= kBigCap, "fused pass LDS fits the tile");
+constexpr int32_t kSlowWord = 0x40000000;   // ring word holding a node of the other side (or its node)
+constexpr int kBufDword3 = 0x00020000; // raw buffer resource: 32-bit format, bounds-checked by bytes
+constexpr int kCpolSc1 = 16;           // cache policy: agent-coherent load
+
+// LDS hand-over between two wavefronts of a workgroup: this wavefront's LDS
+// writes (and reads) complete before the counter changes; global memory
+// operations in flight are not waited for.
+__device__ __forceinline__ void lds_publish(int32_t* p, int32_t v) {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0) only
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ int32_t lds_observe(const int32_t* p) {
+  const int32_t v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  return v;
+}
 
 // Item of the shared write phase for the entry at D position p: the entry
 // with the side of its owner (by position among the disjoint ones, by its own
@@ -1033,19 +1053,25 @@ __device__ __forceinline__ int32_t bits_below(uint64_t w0, uint64_t w1, int32_t 
 // O entries below it; its disjoint position is that minus the kept entries
 // below it (kept ones fill D from the back by the same count). The kept
 // entries follow from O alone: a shared neighbour x gives the keys (x, 0) and
-// (x, 1), the partner edge gives O's entry for h and the giant's for o. The
-// bitmap is cut into chunks of 128 words (8192 ids); in a chunk that holds no
-// node of O and not o, both counts are constant, so its members need no
-// search. Each wavefront takes a contiguous range of superblocks, starting at
-// the prefix of the superblock counts before it; within a range the nonzero
-// words (about a fifth of all at the densities here) are compacted into an
-// LDS ring and expanded one word per lane, which keeps the lanes busy and the
-// loads coalesced. If I is not null, the items of a shared write phase are
-// published too (as if the split moved nothing; the positions the split
-// touches are rewritten after it). Clears the superblock counts of the
-// bitmap; its words are cleared when the edges are written. Workgroup-wide;
-// sets *nD and *a in every thread. False (error raised) if the bitmap does
-// not hold d_g members.
+// (x, 1), the partner edge gives O's entry for h and the giant's for o. So
+// within a bitmap word that holds no node of O and not o both counts are
+// constant; the producer works them out per word (per chunk of 128 words
+// (8192 ids) when the chunk holds none of those nodes), and only the members
+// of the few words that do hold one scan on from the word's counts.
+//
+// Half of the wavefronts produce, half consume, in pairs. A producer streams
+// a contiguous range of superblocks (starting at the prefix of the
+// superblock counts before it) with wide loads kept in flight a batch ahead,
+// and compacts the nonzero words into its pair's LDS ring; it never stores to
+// global memory, so its waits for loads never wait for stores. Its consumer
+// expands the ring one word per lane and writes the entries. The two
+// synchronise through LDS counters only.
+//
+// If I is not null, the items of a shared write phase are published too (as
+// if the split moved nothing; the positions the split touches are rewritten
+// after it). Clears the superblock counts of the bitmap; its words are
+// cleared when the edges are written. Workgroup-wide; sets *nD and *a in
+// every thread. False (error raised) if the bitmap does not hold d_g members.
 __device__ __forceinline__ bool giant_fused(const TradeArgs& A, int32_t k, int32_t gi, int sh, int32_t d_g,
                                             int32_t h, int32_t o, int32_t d_o, BigLds& B, uint64_t* E,
                                             int32_t* D, int32_t s, int32_t* nD_out, int32_t* a_out,
@@ -1054,28 +1080,30 @@ __device__ __forceinline__ bool giant_fused(const TradeArgs& A, int32_t k, int32
   const int nt = blockDim.x;
   const int w = tid >> 6;
   const int l = lane_id();
-  const int nw = nt >> 6;
+  const int np = (nt >> 6) >> 1;               // producer wavefronts; as many consume
   const int so = 1 - sh;
   const uint64_t* O = B.u.tile.E;
   int32_t* posO = B.u.tile.D;                  // merged position of O[j]
   int32_t* kc = B.u.tile.D + kFastOther;       // kept entries O[j] stands for (0, 1 or 2)
   uint64_t* Kk = reinterpret_cast<uint64_t*>(B.u.tile.D + 2 * kFastOther);   // kept keys from O
-  uint64_t* ringW = B.u.tile.E + kFastOther + w * kRing;
-  int4* ringM = reinterpret_cast<int4*>(B.u.tile.E + kFastOther + kWavesPerBlock * kRing) + w * kRing;
+  const int pair = w < np ? w : w - np;
+  uint64_t* ringW = B.u.tile.E + kFastOther + pair * kRing;
+  int4* ringM = reinterpret_cast<int4*>(B.u.tile.E + kFastOther + kPairs * kRing) + pair * kRing;
+  auto ring_ctr = [&](int q) {
+    return reinterpret_cast<int32_t*>(B.u.tile.E + kFastOther + 3 * kPairs * kRing) + 4 * q;
+  };
+  int32_t* rc = ring_ctr(pair);
   const int64_t gwords = A.gs.gwords;
   const int64_t nsb = gwords >> 6;
   const unsigned long long* bm = A.gs.bm + (int64_t)gi * gwords;
   int32_t* sc = A.gs.sc + (int64_t)gi * nsb;
-  // The set was filled by other workgroups' atomics before this trade became
-  // ready; drop whatever this compute unit's cache holds, then read it with
-  // plain (wide) loads.
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   if (tid == 0) { B.cnt[0] = 0; B.cnt[1] = 0; B.cnt[2] = 0; }
+  if (w < np && l < 4) rc[l] = 0;   // fill, head, done, finished wavefronts (trace)
   __syncthreads();
   // O entries: shared neighbour (bit set in the giant's set) or partner
   for (int32_t j = tid; j < d_o; j += nt) {
     const int32_t x = ent_node(O[j]);
-    const bool common = (bm[x >> 6] >> (x & 63)) & 1ull;
+    const bool common = (load_agent_u64(&bm[x >> 6]) >> (x & 63)) & 1ull;
     const bool partner = x == h;
     kc[j] = common ? 2 : (partner ? 1 : 0);
     if (common) atomicAdd(&B.cnt[0], 1);
@@ -1097,19 +1125,26 @@ __device__ __forceinline__ bool giant_fused(const TradeArgs& A, int32_t k, int32
     }
     nK1 += tot;
   }
-  // superblock range of this wavefront (an even number: whole chunks)
-  const int64_t R = (((nsb + nw - 1) / nw) + 1) & ~(int64_t)1;
-  const int64_t sb_lo = (int64_t)w * R < nsb ? (int64_t)w * R : nsb;
+  // superblock range of each producer (an even number: whole chunks); its
+  // members counted from the superblock counts, which are cleared
+  const int64_t R = (((nsb + np - 1) / np) + 1) & ~(int64_t)1;
+  const int64_t sb_lo = (int64_t)pair * R < nsb ? (int64_t)pair * R : nsb;
   const int64_t sb_hi = sb_lo + R < nsb ? sb_lo + R : nsb;
-  int32_t my = 0;
-  for (int64_t j = sb_lo + l; j < sb_hi; j += kWave) my += sc[j];
-  my = wave_sum(my);
-  if (l == 0) B.sboff[w] = my;
+  if (w < np) {
+    int32_t my = 0;
+    for (int64_t j = sb_lo + l; j < sb_hi; j += kWave) {
+      const int32_t c = load_agent(&sc[j]);
+      my += c;
+      if (c != 0) sc[j] = 0;
+    }
+    my = wave_sum(my);
+    if (l == 0) B.sboff[w] = my;
+  }
   __syncthreads();
   int32_t run = 0, total = 0;
-  for (int q = 0; q < nw; ++q) {
+  for (int q = 0; q < np; ++q) {
     const int32_t c = B.sboff[q];
-    if (q < w) run += c;
+    if (q < pair) run += c;
     total += c;
   }
   const int32_t n_common = B.cnt[0];
@@ -1122,110 +1157,67 @@ __device__ __forceinline__ bool giant_fused(const TradeArgs& A, int32_t k, int32
     if (tid == 0) raise_error(A, kErrGather, k, 2000000 + total - d_g);
     return false;
   }
-  const int32_t run0 = run;
+  if (A.trace && tid == 0) A.trace[kTraceFields * (int64_t)k + 15] = (int64_t)now_ticks();
+  // trace: the last producer and the last consumer to finish record the time
+  auto trace_finish = [&](int q, int field) {
+    int32_t* f = ring_ctr(q) + 3;
+    if (A.trace && l == 0 && atomicAdd(f, 1) == np - 1)
+      A.trace[kTraceFields * (int64_t)k + field] = (int64_t)now_ticks();
+  };
 
-  // members of one ring word: rank r of its lowest bit, word index wi; fast
-  // chunks carry the O and kept counts below them (ro >= 0), slow ones ro < 0
-  auto expand = [&](uint64_t bits, int4 m) {
-    int32_t r = m.x;
-    while (bits) {
-      const int bit = __builtin_ctzll(bits);
-      bits &= bits - 1ull;
-      const int32_t x = m.y * 64 + bit;
-      const int32_t i = r++;
-      if (i >= d_g) continue;
-      const uint64_t e = make_entry(x, sh, kTagUnknown);
-      int32_t pe, pd;
-      if (m.z >= 0) {
-        pe = i + m.z;
-        pd = pe - m.w;
-      } else {
-        const uint64_t key = e >> 32;
-        int32_t lo = 0, hi = d_o;
-        while (lo < hi) {
-          const int32_t mid = (lo + hi) >> 1;
-          if ((O[mid] >> 32) < key) lo = mid + 1; else hi = mid;
-        }
-        const int32_t ro = lo;
-        lo = 0;
-        hi = nK1;
-        while (lo < hi) {
-          const int32_t mid = (lo + hi) >> 1;
-          if (Kk[mid] < key) lo = mid + 1; else hi = mid;
-        }
-        const bool common = sh < so ? (ro < d_o && ent_node(O[ro]) == x) : (ro > 0 && ent_node(O[ro - 1]) == x);
-        pe = i + ro;
-        const int32_t rkt = lo + ((edge && kgp < key) ? 1 : 0);
-        pd = (common || x == o) ? s - 1 - rkt : pe - rkt;
+  if (w < np) {
+    // ---- producer
+    const int32_t run0 = run;
+    const int32_t nchunks = (int32_t)((sb_hi - sb_lo + 1) >> 1);
+    const int32_t wbase = (int32_t)(sb_lo * 64);   // first word of the range
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void*)bm, (short)0, (int)(gwords * 8), kBufDword3);
+    // O and kept entries below the current chunk, next node of O or o at or
+    // after it (all uniform across the wavefront)
+    const uint32_t id_lo = (uint32_t)wbase * 64u;
+    int32_t ro = 0, rk = 0;
+    {
+      int32_t lo = 0, hi = d_o;
+      while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if ((uint32_t)ent_node(O[mid]) < id_lo) lo = mid + 1; else hi = mid;
       }
-      E[pe] = e;
-      D[pd] = pe;
-      if (I) put_item(I, pd, e, nD, a);
+      ro = lo;
+      lo = 0;
+      hi = nK1;
+      while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (Kk[mid] < ((uint64_t)id_lo << 1)) lo = mid + 1; else hi = mid;
+      }
+      rk = lo;
     }
-  };
-
-  // O and kept entries below the current chunk, next node of O or o at or
-  // after it (all uniform across the wavefront)
-  const int32_t id_lo = (int32_t)(sb_lo * 4096);
-  int32_t ro = 0, rk = 0;
-  {
-    int32_t lo = 0, hi = d_o;
-    while (lo < hi) {
-      const int32_t mid = (lo + hi) >> 1;
-      if (ent_node(O[mid]) < id_lo) lo = mid + 1; else hi = mid;
-    }
-    ro = lo;
-    lo = 0;
-    hi = nK1;
-    while (lo < hi) {
-      const int32_t mid = (lo + hi) >> 1;
-      if (Kk[mid] < ((uint64_t)id_lo << 1)) lo = mid + 1; else hi = mid;
-    }
-    rk = lo;
-  }
-  auto next_special = [&](int64_t from) -> int64_t {
-    int64_t sp = ro < d_o ? (int64_t)ent_node(O[ro]) : INT64_MAX;
-    if (o >= from && o < sp) sp = o;
-    return sp;
-  };
-  int64_t sp = next_special(id_lo);
-  int32_t head = 0, fill = 0;   // ring counters (positions mod kRing)
-  int32_t scsum = 0;
-  for (int64_t p0 = sb_lo; p0 < sb_hi; p0 += 8 * kWave) {
-    // superblocks p0 + 8 l .. + 7 of this lane: pair q of them is chunk 4 l + q
-    int32_t c8[8];
-    int32_t mine = 0;
+    auto next_special = [&](uint32_t from) -> uint32_t {
+      uint32_t sp = ro < d_o ? (uint32_t)ent_node(O[ro]) : 0xFFFFFFFFu;
+      if ((uint32_t)o >= from && (uint32_t)o < sp) sp = (uint32_t)o;
+      return sp;
+    };
+    uint32_t sp = next_special(id_lo);
+    int32_t fill = 0, head_seen = 0;
+    int32_t spins = 0;   // trace: waits for ring space
+    // lane l holds words 2 l and 2 l + 1 of a chunk (sc1 loads: the words
+    // were set by other workgroups' atomics; past the bitmap they read 0)
+    auto load_batch = [&](uint4* v, int32_t c0) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int64_t j = p0 + 8 * l + i;
-      c8[i] = j < sb_hi ? sc[j] : 0;
-      mine += c8[i];
-      if (c8[i] != 0) sc[j] = 0;
-    }
-    scsum += mine;
-    uint64_t nz[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) nz[q] = ballot(c8[2 * q] + c8[2 * q + 1] != 0);
-    const int32_t nch = (int32_t)((((sb_hi - p0) < 8 * kWave ? (sb_hi - p0) : 8 * kWave) + 1) >> 1);
-    for (int32_t c0 = 0; c0 < nch; c0 += kChunkBatch) {
-      uint4 v[kChunkBatch];
+      for (int b = 0; b < kChunkBatch; ++b)
+        v[b] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(
+                                             rs, (wbase + 128 * (c0 + b) + 2 * l) * 8, 0, kCpolSc1));
+    };
+    // two register sets in turn, each batch loaded a batch ahead; the loads
+    // are unconditional (one batch past the range is read and dropped)
+    auto process = [&](const uint4* v, int32_t c0) {
 #pragma unroll
       for (int b = 0; b < kChunkBatch; ++b) {
         const int32_t ch = c0 + b;
-        const int64_t wb = (p0 + 2 * ch) * 64;
-        const bool ld = ch < nch && ((nz[b & 3] >> ((c0 >> 2) + (b >> 2))) & 1ull) && wb + 2 * l < gwords;
-        v[b] = ld ? reinterpret_cast<const uint4*>(bm + wb)[l] : make_uint4(0u, 0u, 0u, 0u);
-      }
-#pragma unroll
-      for (int b = 0; b < kChunkBatch; ++b) {
-        const int32_t ch = c0 + b;
-        if (ch >= nch) break;
-        const int64_t wb = (p0 + 2 * ch) * 64;
-        const int64_t id0 = wb * 64;
-        const int64_t id_end = id0 + 128 * 64;
+        if (ch >= nchunks) break;
+        const int32_t wb = wbase + 128 * ch;
+        const uint32_t id0 = (uint32_t)wb * 64u;
+        const uint32_t id_end = id0 + 128u * 64u;
         const bool slow = sp < id_end;
-        const bool ne = (nz[b & 3] >> ((c0 >> 2) + (b >> 2))) & 1ull;
-        if (!ne && !slow) continue;
         const uint64_t w0 = ((uint64_t)v[b].y << 32) | v[b].x;
         const uint64_t w1 = ((uint64_t)v[b].w << 32) | v[b].z;
         const int32_t pc = popc64(w0) + popc64(w1);
@@ -1234,61 +1226,148 @@ __device__ __forceinline__ bool giant_fused(const TradeArgs& A, int32_t k, int32
         const int32_t incl = wave_incl_scan(pk);
         const int32_t tot = wave_bcast(incl, kWave - 1);
         const int32_t ex = incl - pk;
-        int32_t mz = -1, mw = 0;
+        // per word: O entries and kept keys below its first id; a word that
+        // holds a node of O or o itself is expanded with a short scan
+        const uint32_t b0 = id0 + 128u * (uint32_t)l, b1 = b0 + 64u;
+        const int32_t e0 = (edge && (uint32_t)o < b0) ? 1 : 0;
+        const int32_t e1 = (edge && (uint32_t)o < b1) ? 1 : 0;
+        int32_t ro0 = ro, ro1 = ro, rk0 = rk, rk1 = rk;
+        bool s0 = false, s1 = false;
         if (slow) {
           // ranks of the O nodes in this chunk among the giant's members
-          const int32_t b0 = (int32_t)id0 + 128 * l;
-          while (ro < d_o && (int64_t)ent_node(O[ro]) < id_end) {
+          while (ro < d_o && (uint32_t)ent_node(O[ro]) < id_end) {
             const int32_t x = ent_node(O[ro]);
-            const int32_t lo = run + wave_sum(bits_below(w0, w1, b0, x));
-            if (l == 0) posO[ro] = ro + lo + ((kc[ro] == 2 && sh < so) ? 1 : 0);
+            const int32_t kx = kc[ro];
+            const int32_t lo = run + wave_sum(bits_below(w0, w1, (int32_t)b0, x));
+            if (l == 0) posO[ro] = ro + lo + ((kx == 2 && sh < so) ? 1 : 0);
+            if ((uint32_t)x < b0) { ++ro0; rk0 += kx; }
+            if ((uint32_t)x < b1) { ++ro1; rk1 += kx; }
+            s0 |= (uint32_t)x >= b0 && (uint32_t)x < b1;
+            s1 |= (uint32_t)x >= b1 && (uint32_t)x < b1 + 64u;
             ++ro;
           }
-        } else {
-          mz = ro;
-          mw = rk + ((edge && (int64_t)o < id0) ? 1 : 0);
+          s0 |= (uint32_t)o >= b0 && (uint32_t)o < b1;
+          s1 |= (uint32_t)o >= b1 && (uint32_t)o < b1 + 64u;
         }
-        int32_t at = fill + (ex >> 16);
-        const int32_t r0 = run + (ex & 0xFFFF);
-        if (w0) {
-          ringW[at & (kRing - 1)] = w0;
-          ringM[at & (kRing - 1)] = make_int4(r0, (int32_t)(wb + 2 * l), mz, mw);
-          ++at;
+        const int32_t add = tot >> 16;
+        if (add != 0) {
+          if (fill + add - head_seen > kRing) {
+            lds_publish(&rc[0], fill);   // all written entries visible before waiting
+            while (true) {
+              head_seen = lds_observe(&rc[1]);
+              if (fill + add - head_seen <= kRing) break;
+              __builtin_amdgcn_s_sleep(1);
+              ++spins;
+            }
+          }
+          int32_t at = fill + (ex >> 16);
+          const int32_t r0 = run + (ex & 0xFFFF);
+          if (w0) {
+            ringW[at & (kRing - 1)] = w0;
+            ringM[at & (kRing - 1)] =
+                make_int4(r0, wb + 2 * l, s0 ? (ro0 | kSlowWord) : ro0, s0 ? rk0 : rk0 + e0);
+            ++at;
+          }
+          if (w1) {
+            ringW[at & (kRing - 1)] = w1;
+            ringM[at & (kRing - 1)] = make_int4(r0 + popc64(w0), wb + 2 * l + 1,
+                                                s1 ? (ro1 | kSlowWord) : ro1, s1 ? rk1 : rk1 + e1);
+          }
+          fill += add;
         }
-        if (w1) {
-          ringW[at & (kRing - 1)] = w1;
-          ringM[at & (kRing - 1)] = make_int4(r0 + popc64(w0), (int32_t)(wb + 2 * l + 1), mz, mw);
-        }
-        fill += tot >> 16;
         run += tot & 0xFFFF;
         if (slow) {
           while (rk < nK1 && Kk[rk] < ((uint64_t)id_end << 1)) ++rk;
           sp = next_special(id_end);
         }
-        if (fill - head >= kWave) {
-          wave_sync();
-          do {
-            const int32_t p = (head + l) & (kRing - 1);
-            expand(ringW[p], ringM[p]);
-            head += kWave;
-          } while (fill - head >= kWave);
-          wave_sync();
+      }
+      lds_publish(&rc[0], fill);
+    };
+    uint4 va[kChunkBatch], vb[kChunkBatch];
+    load_batch(va, 0);
+    for (int32_t c0 = 0;;) {
+      load_batch(vb, c0 + kChunkBatch);
+      process(va, c0);
+      c0 += kChunkBatch;
+      if (c0 >= nchunks) break;
+      load_batch(va, c0 + kChunkBatch);
+      process(vb, c0);
+      c0 += kChunkBatch;
+      if (c0 >= nchunks) break;
+    }
+    lds_publish(&rc[0], fill);
+    lds_publish(&rc[2], 1);
+    // the members found must match the superblock counts of the range
+    if (l == 0 && run - run0 != B.sboff[w]) B.cnt[2] = 1;
+    trace_finish(0, 20);
+    if (A.trace && l == 0) atomicAdd(ring_ctr(2) + 3, spins);
+  } else {
+    // ---- consumer: members of one ring word: rank of its lowest bit, word
+    // index, O entries below the word (with kSlowWord: the word holds one of
+    // the special nodes), kept entries below it
+    int32_t head = 0, fill_seen = 0;
+    int32_t spins = 0;   // trace: waits for ring entries
+    while (true) {
+      if (fill_seen - head < kWave) {
+        const int32_t dn = lds_observe(&rc[2]);
+        fill_seen = lds_observe(&rc[0]);
+        if (fill_seen - head < kWave && dn == 0) {
+          __builtin_amdgcn_s_sleep(1);
+          ++spins;
+          continue;
         }
       }
+      int32_t cnt = fill_seen - head;
+      if (cnt == 0) break;
+      if (cnt > kWave) cnt = kWave;
+      if (l < cnt) {
+        const int32_t p = (head + l) & (kRing - 1);
+        uint64_t bits = ringW[p];
+        const int4 m = ringM[p];
+        int32_t r = m.x;
+        while (bits) {
+          const int bit = __builtin_ctzll(bits);
+          bits &= bits - 1ull;
+          const int32_t x = m.y * 64 + bit;
+          const int32_t i = r++;
+          if (i >= d_g) continue;
+          const uint64_t e = make_entry(x, sh, kTagUnknown);
+          int32_t pe, pd;
+          if (!(m.z & kSlowWord)) {
+            pe = i + m.z;
+            pd = pe - m.w;
+          } else {
+            // from the word's counts past the few O entries and kept keys below this member
+            const uint64_t key = e >> 32;
+            int32_t rO = m.z & ~kSlowWord;
+            while (rO < d_o && (O[rO] >> 32) < key) ++rO;
+            int32_t rK = m.w;
+            while (rK < nK1 && Kk[rK] < key) ++rK;
+            const bool common =
+                sh < so ? (rO < d_o && ent_node(O[rO]) == x) : (rO > 0 && ent_node(O[rO - 1]) == x);
+            pe = i + rO;
+            const int32_t rkt = rK + ((edge && kgp < key) ? 1 : 0);
+            pd = (common || x == o) ? s - 1 - rkt : pe - rkt;
+          }
+          E[pe] = e;
+          D[pd] = pe;
+          if (I) put_item(I, pd, e, nD, a);
+        }
+      }
+      head += cnt;
+      lds_publish(&rc[1], head);
     }
+    trace_finish(1, 21);
+    if (A.trace && l == 0) atomicAdd(ring_ctr(3) + 3, spins);
   }
-  wave_sync();
-  if (l < fill - head) {
-    const int32_t p = (head + l) & (kRing - 1);
-    expand(ringW[p], ringM[p]);
-  }
-  // the members found must match the superblock counts of the range
-  const int32_t scw = wave_sum(scsum);
-  if (l == 0 && run - run0 != scw) B.cnt[2] = 1;
   __syncthreads();
+  if (A.trace && tid == 0) {
+    A.trace[kTraceFields * (int64_t)k + 22] = *(ring_ctr(2) + 3);
+    A.trace[kTraceFields * (int64_t)k + 23] = *(ring_ctr(3) + 3);
+  }
   if (B.cnt[2] != 0) {
     __syncthreads();
-    if (tid == 0) raise_error(A, kErrGather, k, 3000000 + run - run0 - scw);
+    if (tid == 0) raise_error(A, kErrGather, k, 3000000);
     return false;
   }
   // other side
@@ -1596,7 +1675,6 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
       T[12] = nD;
       T[13] = a;
       T[14] = B.tick[0] ? (int64_t)B.tick[0] : -1;
-      T[15] = -1;
     }
   }
   counters[1] += W.fwd;
