@@ -174,9 +174,9 @@ __device__ __forceinline__ void block_split(int32_t* D, int32_t N, int32_t a, ui
 // reserves a slot with its shard's tail counter and fills it; a popper takes
 // a slot with a compare-and-swap on the head, waits for the fill, and
 // resets the slot to -1 so the queues are clean for the next round.
-__device__ __forceinline__ int32_t queue_pop(const TradeArgs& A, int32_t* q, int shards, int head0, int tail0,
-                             int start) {
-  for (int i = 0; i < shards; ++i) {
+__device__ __forceinline__ int32_t queue_pop(const TradeArgs& A, int32_t* q, int nscan, int head0, int tail0,
+                             int start, int shards) {
+  for (int i = 0; i < nscan; ++i) {
     const int sh = (start + i) % shards;
     int32_t* head = &A.ctrl[cw(head0 + sh)];
     const int32_t h = load_agent(head);
@@ -805,6 +805,12 @@ __device__ void wave_flush(const TradeArgs& A, WaveState& S) {
 }
 
 constexpr int32_t kFlushEvery = 32;   // trades between progress flushes
+// An idle wavefront worker scans this many ready-queue shards per poll
+// (rotating; the many idle wavefronts cover every shard between them) and
+// sleeps up to kSmallMaxBackoff * 32 * 64 cycles between polls, which keeps
+// the polls of the shared control words from crowding the memory side.
+constexpr int kQsScan = 4;
+constexpr int32_t kSmallMaxBackoff = 32;
 
 __device__ __forceinline__ void small_worker(const TradeArgs& A, WaveLds& W) {
   const int l = lane_id();
@@ -813,6 +819,8 @@ __device__ __forceinline__ void small_worker(const TradeArgs& A, WaveLds& W) {
   S.shard = wid % kQsShards;
   Watchdog wd{0, 0};
   int32_t backoff = 1;
+  bool sources_left = true;   // no trade becomes a source during the kernel
+  int32_t scan = S.shard;
   for (;;) {
     int32_t k = -1;
     if (S.top > 0) {
@@ -820,8 +828,14 @@ __device__ __forceinline__ void small_worker(const TradeArgs& A, WaveLds& W) {
       k = W.stack[S.top];
     } else {
       if (l == 0) {
-        k = source_pop(A);
-        if (k < 0) k = queue_pop(A, A.qs, kQsShards, kCwQsHead0, kCwQsTail0, S.shard);
+        if (sources_left) {
+          k = source_pop(A);
+          sources_left = k >= 0;
+        }
+        if (k < 0) {
+          k = queue_pop(A, A.qs, kQsScan, kCwQsHead0, kCwQsTail0, scan, kQsShards);
+          scan = (scan + kQsScan) % kQsShards;
+        }
       }
       k = wave_bcast(k, 0);
     }
@@ -835,7 +849,7 @@ __device__ __forceinline__ void small_worker(const TradeArgs& A, WaveLds& W) {
       }
       if (wave_bcast(stop, 0)) break;
       idle_backoff(backoff);
-      backoff = backoff < 16 ? backoff * 2 : 16;
+      backoff = backoff < kSmallMaxBackoff ? backoff * 2 : kSmallMaxBackoff;
       continue;
     }
     backoff = 1;
@@ -1699,7 +1713,7 @@ __device__ __forceinline__ void big_worker(const TradeArgs& A, BigLds& B) {
       if (load_agent(&A.ctrl[cw(kCwAbort)])) {
         k = -2;
       } else {
-        k = queue_pop(A, A.qb, kQbShards, kCwQbHead0, kCwQbTail0, (int)(blockIdx.x % kQbShards));
+        k = queue_pop(A, A.qb, kQbShards, kCwQbHead0, kCwQbTail0, (int)(blockIdx.x % kQbShards), kQbShards);
         if (k < 0) {
           const int32_t done = load_agent(&A.ctrl[cw(kCwDone)]);
           if (done >= A.L) k = -2;
