@@ -807,10 +807,11 @@ __device__ void wave_flush(const TradeArgs& A, WaveState& S) {
 constexpr int32_t kFlushEvery = 32;   // trades between progress flushes
 // An idle wavefront worker scans this many ready-queue shards per poll
 // (rotating; the many idle wavefronts cover every shard between them) and
-// sleeps up to kSmallMaxBackoff * 32 * 64 cycles between polls, which keeps
-// the polls of the shared control words from crowding the memory side.
-constexpr int kQsScan = 4;
-constexpr int32_t kSmallMaxBackoff = 32;
+// sleeps up to kSmallMaxBackoff * 32 * 64 cycles (about 110 us) between
+// polls, which keeps the polls of the shared control words from crowding the
+// memory side.
+constexpr int kQsScan = 1;
+constexpr int32_t kSmallMaxBackoff = 128;
 
 __device__ __forceinline__ void small_worker(const TradeArgs& A, WaveLds& W) {
   const int l = lane_id();
