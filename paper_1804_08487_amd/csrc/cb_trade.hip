@@ -849,6 +849,15 @@ __device__ __forceinline__ void small_worker(const TradeArgs& A, WaveLds& W) {
         if (!stop && wd.stalled(A, done)) { raise_error(A, kErrWatchdog); stop = 1; }
       }
       if (wave_bcast(stop, 0)) break;
+      // an idle wavefront also writes chunks of the large trades' write jobs
+      WriteCounts H{0, 0, 0};
+      if (try_help(A, (int32_t)blockIdx.x, H)) {
+        S.fwd += (unsigned long long)wave_sum((int32_t)H.fwd);
+        S.emit += (unsigned long long)wave_sum((int32_t)H.emit);
+        S.n_push += (unsigned long long)wave_sum((int32_t)H.push);
+        backoff = 1;
+        continue;
+      }
       idle_backoff(backoff);
       backoff = backoff < kSmallMaxBackoff ? backoff * 2 : kSmallMaxBackoff;
       continue;
