@@ -170,6 +170,83 @@ __device__ __forceinline__ void block_split(int32_t* D, int32_t N, int32_t a, ui
   }
 }
 
+// The same split for a D in global memory, through LDS: the positions its
+// steps touch go into a hash table (with the number of steps touching each),
+// their entries are gathered, swapped there and written back. A step whose two
+// positions no other step touches commutes with all others, so those steps
+// swap in parallel; the others keep their order on one lane (each wavefront
+// lists its own in order, and the wavefronts' lists are taken in turn).
+// Workgroup-wide; needs 4 * T <= nslots (a power of two). key: position + 1
+// (0 = empty), cnt: steps touching it, val: its entry; ST: 2 T slots.
+__device__ __forceinline__ void lds_split(int32_t* D, int32_t N, int32_t a, uint64_t seed, uint32_t round,
+                                          int32_t k, int32_t* key, int32_t* cnt, int32_t* val, int32_t nslots,
+                                          int32_t* ST, int32_t* late, int32_t* nlate) {
+  const int tid = threadIdx.x;
+  const int nt = blockDim.x;
+  const int w = tid >> 6;
+  const int nw = nt >> 6;
+  const int32_t T = split_steps(N, a);
+  const bool fwd = a <= N - a;
+  const int sh = 31 - __clz(nslots);
+  for (int32_t i = tid; i < nslots; i += nt) { key[i] = 0; cnt[i] = 0; }
+  __syncthreads();
+  for (int32_t i = tid; i < 2 * T; i += nt) {
+    const int32_t t = i >> 1;
+    const int32_t x = (i & 1) ? split_partner(N, a, t, seed, round, k) : (fwd ? t : N - 1 - t);
+    int32_t q = (int32_t)(((uint32_t)x * 2654435761u) >> (32 - sh));
+    while (true) {
+      const int32_t old = atomicCAS(&key[q], 0, x + 1);
+      if (old == 0 || old == x + 1) break;
+      q = (q + 1) & (nslots - 1);
+    }
+    ST[i] = q;
+    atomicAdd(&cnt[q], 1);
+  }
+  __syncthreads();
+  for (int32_t i = tid; i < nslots; i += nt)
+    if (key[i] != 0) val[i] = D[key[i] - 1];
+  // steps of wavefront w: [w * per, (w + 1) * per)
+  const int32_t per = (T + nw - 1) / nw;
+  const int32_t t_lo = w * per < T ? w * per : T, t_hi = t_lo + per < T ? t_lo + per : T;
+  __syncthreads();
+  int32_t nl = 0;
+  for (int32_t t0 = t_lo; t0 < t_hi; t0 += kWave) {
+    const int32_t t = t0 + lane_id();
+    bool lt = false;
+    if (t < t_hi) {
+      const int32_t p = ST[2 * t], q = ST[2 * t + 1];
+      if (cnt[p] == 1 && cnt[q] == 1) {
+        const int32_t vp = val[p];
+        val[p] = val[q];
+        val[q] = vp;
+      } else {
+        lt = p != q;
+      }
+    }
+    const uint64_t lm = ballot(lt);
+    if (lt) late[t_lo + nl + rank_below(lm)] = t;
+    nl += popc64(lm);
+  }
+  if (lane_id() == 0) nlate[w] = nl;
+  __syncthreads();
+  if (tid == 0) {
+    for (int v = 0; v < nw; ++v) {
+      const int32_t lo = v * per < T ? v * per : T;
+      for (int32_t z = 0; z < nlate[v]; ++z) {
+        const int32_t t = late[lo + z];
+        const int32_t p = ST[2 * t], q = ST[2 * t + 1];
+        const int32_t vp = val[p];
+        val[p] = val[q];
+        val[q] = vp;
+      }
+    }
+  }
+  __syncthreads();
+  for (int32_t i = tid; i < nslots; i += nt)
+    if (key[i] != 0) D[key[i] - 1] = val[i];
+  __syncthreads();
+}
+
 // Ready queues: `shards` queues of L slots each; q[shard * L + pos]. A pusher
 // reserves a slot with its shard's tail counter and fills it; a popper takes
 // a slot with a compare-and-swap on the head, waits for the fill, and
@@ -1025,6 +1102,10 @@ __device__ __forceinline__ bool extract_giant(const TradeArgs& A, int32_t k, int
    // items per thread whose atomics are in flight together
 
 constexpr int kPer = 8;     // consecutive entries per thread in the classification scan
+// hash slots of the split through LDS (key, count, value, then 2 T + T step
+// slots): 3 * 8192 + 6144 ints of the tile's 36864
+constexpr int32_t kSplitSlots = 8192;
+static_assert(3 * kSplitSlots + 3 * (kSplitSlots / 4) <= kBigCap * 3, "split slots fit the tile");
 
 constexpr int32_t kFastOther = 2048;   // other-side sizes of the one-pass giant classification
 constexpr int kRing = 512;             // nonzero bitmap words buffered per producer / consumer pair
@@ -1602,7 +1683,18 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
   }
   __syncthreads();
   const uint64_t t_classified = now_ticks();
-  block_split(D, nD, a, A.seed, A.round, k, B.sboff, 2 * kTradeBlock);
+  {
+    // D in global memory: the touched positions through LDS (the tile is
+    // free by now); D in LDS, or a long split: in place, in order
+    const int32_t T = split_steps(nD, a);
+    int32_t* Lt = reinterpret_cast<int32_t*>(B.u.tile.E);
+    if (!in_lds && T > 0 && 4 * T <= kSplitSlots) {
+      lds_split(D, nD, a, A.seed, A.round, k, Lt, Lt + kSplitSlots, Lt + 2 * kSplitSlots, kSplitSlots,
+                Lt + 3 * kSplitSlots, Lt + 3 * kSplitSlots + 2 * (kSplitSlots / 4), B.sboff);
+    } else {
+      block_split(D, nD, a, A.seed, A.round, k, B.sboff, 2 * kTradeBlock);
+    }
+  }
   if (items_ready) split_fix_items(E, D, nD, a, A.seed, A.round, k, Ig);
   if (tid == 0) {
     B.cnt[1] = 0;
