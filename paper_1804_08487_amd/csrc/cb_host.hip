@@ -517,7 +517,7 @@ cb_status graph_upload(int64_t n, const int64_t* row_ptr, const int32_t* col, vo
             alloc_into(g, &g->giant_id, n) && alloc_into(g, &g->mtmp, n) &&
             alloc_into(g, &g->mkey, n) && alloc_into(g, &g->dep, g->L) &&
             alloc_into(g, &g->src_list, g->L) && alloc_into(g, &g->tsz, g->L) &&
-            alloc_into(g, &g->jobs, kMaxJobs) && alloc_into(g, &g->qs, (int64_t)kQsShards * std::max<int64_t>(g->L, 1)) &&
+            alloc_into(g, &g->jobs, 2 * kMaxJobs) && alloc_into(g, &g->qs, (int64_t)kQsShards * std::max<int64_t>(g->L, 1)) &&
             alloc_into(g, &g->qb, (int64_t)kQbShards * std::max<int64_t>(g->L, 1)) && alloc_into(g, &g->bcount, g->nb) &&
             alloc_into(g, &g->bstart, g->nb + 1) && alloc_into(g, &g->bcur, g->nb) &&
             alloc_into(g, &g->ctrl, kCtrlInts) && alloc_into(g, &g->stats, kStatCount) &&
@@ -537,7 +537,7 @@ cb_status graph_upload(int64_t n, const int64_t* row_ptr, const int32_t* col, vo
        (rm.empty() || hip_ok(hipMemcpyAsync(g->rows_mid, rm.data(), rm.size() * sizeof(int32_t), hipMemcpyHostToDevice, st), &msg, "copy rows")) &&
        (rb.empty() || hip_ok(hipMemcpyAsync(g->rows_big, rb.data(), rb.size() * sizeof(int32_t), hipMemcpyHostToDevice, st), &msg, "copy rows")) &&
        hip_ok(hipMemsetAsync(g->ctrl, 0, kCtrlInts * sizeof(int32_t), st), &msg, "clear ctrl") &&
-       hip_ok(hipMemsetAsync(g->jobs, 0, kMaxJobs * sizeof(HelpJob), st), &msg, "clear jobs") &&
+       hip_ok(hipMemsetAsync(g->jobs, 0, 2 * kMaxJobs * sizeof(HelpJob), st), &msg, "clear jobs") &&
        hip_ok(hipMemsetAsync(g->qs, 0xFF, (size_t)kQsShards * std::max<int64_t>(g->L, 1) * sizeof(int32_t), st), &msg, "clear queues") &&
        hip_ok(hipMemsetAsync(g->qb, 0xFF, (size_t)kQbShards * std::max<int64_t>(g->L, 1) * sizeof(int32_t), st), &msg, "clear queues");
   if (ok && (flags & CB_VALIDATE) && nnz > 0) {

@@ -29,6 +29,8 @@ enum CtrlWord : int {
   kCwQbTail0 = kCwQbHead0 + kQbShards,
   kCwJobMask0 = kCwQbTail0 + kQbShards,   // write jobs open to helpers: workgroups 0..31
   kCwJobMask1,                            // ... and 32..63
+  kCwJobMask2,                            // giant bitmap passes open to a helper workgroup: 0..31
+  kCwJobMask3,                            // ... and 32..63
   kCwCount
 };
 __host__ __device__ constexpr int cw(int word) { return word * kCtrlStride; }
@@ -55,6 +57,7 @@ constexpr int kWavesPerBlock = kTradeBlock / 64;
 constexpr int kStackCap = 16;         // ready trades a wavefront may keep
 constexpr int kTraceFields = 24;      // int64 per trade of the optional trace
 constexpr int kMaxJobs = 64;          // workgroups that can open their write phase to helpers
+                                      // (and, in a second set of jobs, part of a giant's bitmap pass)
 constexpr int32_t kHelpChunk = 512;   // output items per claimed chunk
 constexpr int32_t kHelpMinItems = 8192;   // default: smaller trades work alone
 constexpr int32_t kSbChunk = 16;      // bitmap superblocks per claimed extraction chunk
@@ -83,6 +86,8 @@ struct HelpJob {
     int32_t k, u, v, s, nD, a, du, dv;
     int32_t phase, gi, side, d;  // phase 1: giant id, side and size of the list
     int32_t gu, gv;              // phase 2: giant ids of u and v (-1: none)
+    int32_t d_o, nK1, o, edge;   // phase 3 (part of a giant's bitmap pass): the other side
+    int64_t sb_from, sb_to;      // phase 3: the helper's superblocks
   } f;
 };
 constexpr int kMatchCap = 2048;       // bucket size sorted in LDS by k_match_sort

@@ -247,6 +247,87 @@ __device__ __forceinline__ void lds_split(int32_t* D, int32_t N, int32_t a, uint
   __syncthreads();
 }
 
+// The split applied to a trade's published items at disjoint positions
+// 0..N-1 (agent-scope array), as lds_split does it to D: the touched
+// positions' items are gathered into an LDS hash table, swapped there, and
+// written back, each with the side of its new owner (position below a: u). A
+// flag bit on a key marks a position that several steps touch. Workgroup-wide;
+// needs 4 * T <= nslots (a power of two).
+constexpr int32_t kMultiTouch = 0x40000000;
+__device__ __forceinline__ void item_split(unsigned long long* I, int32_t N, int32_t a, uint64_t seed,
+                                           uint32_t round, int32_t k, int32_t* key, uint64_t* val,
+                                           int32_t nslots, int32_t* ST, int32_t* late, int32_t* nlate) {
+  const int tid = threadIdx.x;
+  const int nt = blockDim.x;
+  const int w = tid >> 6;
+  const int nw = nt >> 6;
+  const int32_t T = split_steps(N, a);
+  const bool fwd = a <= N - a;
+  const int sh = 31 - __clz(nslots);
+  for (int32_t i = tid; i < nslots; i += nt) key[i] = 0;
+  __syncthreads();
+  for (int32_t i = tid; i < 2 * T; i += nt) {
+    const int32_t t = i >> 1;
+    const int32_t x = (i & 1) ? split_partner(N, a, t, seed, round, k) : (fwd ? t : N - 1 - t);
+    int32_t q = (int32_t)(((uint32_t)x * 2654435761u) >> (32 - sh));
+    while (true) {
+      const int32_t old = atomicCAS(&key[q], 0, x + 1);
+      if (old == 0) break;
+      if ((old & ~kMultiTouch) == x + 1) {
+        atomicOr(&key[q], kMultiTouch);
+        break;
+      }
+      q = (q + 1) & (nslots - 1);
+    }
+    ST[i] = q;
+  }
+  __syncthreads();
+  for (int32_t i = tid; i < nslots; i += nt)
+    if (key[i] != 0) val[i] = load_agent_u64(&I[(key[i] & ~kMultiTouch) - 1]);
+  const int32_t per = (T + nw - 1) / nw;
+  const int32_t t_lo = w * per < T ? w * per : T, t_hi = t_lo + per < T ? t_lo + per : T;
+  __syncthreads();
+  int32_t nl = 0;
+  for (int32_t t0 = t_lo; t0 < t_hi; t0 += kWave) {
+    const int32_t t = t0 + lane_id();
+    bool lt = false;
+    if (t < t_hi) {
+      const int32_t p = ST[2 * t], q = ST[2 * t + 1];
+      if (!(key[p] & kMultiTouch) && !(key[q] & kMultiTouch)) {
+        const uint64_t vp = val[p];
+        val[p] = val[q];
+        val[q] = vp;
+      } else {
+        lt = p != q;
+      }
+    }
+    const uint64_t lm = ballot(lt);
+    if (lt) late[t_lo + nl + rank_below(lm)] = t;
+    nl += popc64(lm);
+  }
+  if (lane_id() == 0) nlate[w] = nl;
+  __syncthreads();
+  if (tid == 0) {
+    for (int v = 0; v < nw; ++v) {
+      const int32_t lo = v * per < T ? v * per : T;
+      for (int32_t z = 0; z < nlate[v]; ++z) {
+        const int32_t t = late[lo + z];
+        const int32_t p = ST[2 * t], q = ST[2 * t + 1];
+        const uint64_t vp = val[p];
+        val[p] = val[q];
+        val[q] = vp;
+      }
+    }
+  }
+  __syncthreads();
+  for (int32_t i = tid; i < nslots; i += nt) {
+    if (key[i] == 0) continue;
+    const int32_t pos = (key[i] & ~kMultiTouch) - 1;
+    store_agent_u64(&I[pos], (val[i] & ~(1ull << 32)) | ((pos < a ? 0ull : 1ull) << 32));
+  }
+  __syncthreads();
+}
+
 // Ready queues: `shards` queues of L slots each; q[shard * L + pos]. A pusher
 // reserves a slot with its shard's tail counter and fills it; a popper takes
 // a slot with a compare-and-swap on the head, waits for the fill, and
@@ -494,8 +575,10 @@ __device__ __forceinline__ int32_t claim_chunk(HelpJob* J) {
   return ticket_next(t) < ticket_chunks(t) ? ticket_next(t) : -1;
 }
 
-__device__ __forceinline__ int32_t* job_mask(const TradeArgs& A, int owner) {
-  return &A.ctrl[cw(owner < 32 ? kCwJobMask0 : kCwJobMask1)];
+// Mask word of owner's jobs: kCwJobMask0/1 (write phases, taken by single
+// wavefronts) or kCwJobMask2/3 (parts of a bitmap pass, taken by workgroups).
+__device__ __forceinline__ int32_t* job_mask(const TradeArgs& A, int owner, int base = kCwJobMask0) {
+  return &A.ctrl[cw(base + (owner < 32 ? 0 : 1))];
 }
 
 // Extraction of a giant's neighbour set shared with helper wavefronts is
@@ -509,7 +592,8 @@ __device__ __forceinline__ int64_t shared_list_off(const TradeArgs& A) { return 
 
 // Open the calling workgroup's job, of nchunks chunks, with its fields
 // already stored (thread 0).
-__device__ __forceinline__ void open_job(const TradeArgs& A, HelpJob* J, int32_t nchunks) {
+__device__ __forceinline__ void open_job(const TradeArgs& A, HelpJob* J, int32_t nchunks,
+                                         int mask = kCwJobMask0) {
   store_agent(&J->c.done, 0);
   store_agent(&J->c.own[0], 0);
   store_agent(&J->c.own[1], 0);
@@ -518,12 +602,13 @@ __device__ __forceinline__ void open_job(const TradeArgs& A, HelpJob* J, int32_t
   store_agent_u64(&J->t.ticket, (gen << (2 * kTicketCountBits)) |
                                     ((unsigned long long)nchunks << kTicketCountBits));
   publish_wait();
-  atomic_or(job_mask(A, blockIdx.x), (int32_t)(1u << (blockIdx.x & 31)));
+  atomic_or(job_mask(A, blockIdx.x, mask), (int32_t)(1u << (blockIdx.x & 31)));
 }
 
 // Every chunk is claimed: close the job and wait for the helpers (thread 0).
-__device__ __forceinline__ void close_job(const TradeArgs& A, HelpJob* J, int32_t nchunks) {
-  atomic_and(job_mask(A, blockIdx.x), (int32_t)~(1u << (blockIdx.x & 31)));
+__device__ __forceinline__ void close_job(const TradeArgs& A, HelpJob* J, int32_t nchunks,
+                                          int mask = kCwJobMask0) {
+  atomic_and(job_mask(A, blockIdx.x, mask), (int32_t)~(1u << (blockIdx.x & 31)));
   while (load_agent(&J->c.done) < nchunks) {
     if (load_agent(&A.ctrl[cw(kCwAbort)])) break;
     __builtin_amdgcn_s_sleep(2);
@@ -1112,7 +1197,8 @@ constexpr int kRing = 512;             // nonzero bitmap words buffered per prod
 constexpr int kPairs = kWavesPerBlock / 2;
 constexpr int kChunkBatch = 8;         // 1 KiB bitmap chunks a producer keeps in flight (twice)
 static_assert(kFastOther + 3 * kPairs * kRing + 2 * kPairs <= kBigCap, "fused pass LDS fits the tile");
-constexpr int32_t kSlowWord = 0x40000000;   // ring word holding a node of the other side (or its node)
+constexpr int32_t kSlowWord = 0x40000000;
+constexpr int32_t kFusedShareMin = 16384;   // giant sides whose bitmap pass is offered in halves   // ring word holding a node of the other side (or its node)
 constexpr int kBufDword3 = 0x00020000; // raw buffer resource: 32-bit format, bounds-checked by bytes
 constexpr int kCpolSc1 = 16;           // cache policy: agent-coherent load
 
@@ -1149,48 +1235,44 @@ __device__ __forceinline__ int32_t bits_below(uint64_t w0, uint64_t w1, int32_t 
   return c;
 }
 
-// One giant side (node h, side sh, d_g members in giant gi's bitmap) and a
-// small other side O (ascending in LDS, d_o <= kFastOther entries, node o):
-// the merged list E and the disjoint / kept index array D in one pass over
-// the bitmap, without materialising the giant's sorted list.
-//
-// A member's merged position is its rank among the giant's members plus the
-// O entries below it; its disjoint position is that minus the kept entries
-// below it (kept ones fill D from the back by the same count). The kept
-// entries follow from O alone: a shared neighbour x gives the keys (x, 0) and
-// (x, 1), the partner edge gives O's entry for h and the giant's for o. So
-// within a bitmap word that holds no node of O and not o both counts are
-// constant; the producer works them out per word (per chunk of 128 words
-// (8192 ids) when the chunk holds none of those nodes), and only the members
-// of the few words that do hold one scan on from the word's counts.
-//
-// Half of the wavefronts produce, half consume, in pairs. A producer streams
-// a contiguous range of superblocks (starting at the prefix of the
-// superblock counts before it) with wide loads kept in flight a batch ahead,
-// and compacts the nonzero words into its pair's LDS ring; it never stores to
-// global memory, so its waits for loads never wait for stores. Its consumer
-// expands the ring one word per lane and writes the entries. The two
-// synchronise through LDS counters only.
-//
-// If I is not null, the items of a shared write phase are published too (as
-// if the split moved nothing; the positions the split touches are rewritten
-// after it). Clears the superblock counts of the bitmap; its words are
-// cleared when the edges are written. Workgroup-wide; sets *nD and *a in
-// every thread. False (error raised) if the bitmap does not hold d_g members.
-__device__ __forceinline__ bool giant_fused(const TradeArgs& A, int32_t k, int32_t gi, int sh, int32_t d_g,
-                                            int32_t h, int32_t o, int32_t d_o, BigLds& B, uint64_t* E,
-                                            int32_t* D, int32_t s, int32_t* nD_out, int32_t* a_out,
-                                            unsigned long long* I) {
+// Parameters of the producer / consumer phase of a fused giant pass, the
+// same for the owner and for a helper workgroup that takes part of the
+// bitmap; O, kc and Kk are in the workgroup's LDS at the fixed places.
+struct FusedCtx {
+  const unsigned long long* bm;   // the giant's bitmap
+  const int32_t* pre;             // prefix of its superblock counts (agent-scope)
+  unsigned long long* I;          // items, or null: E and D
+  uint64_t* E;
+  int32_t* D;
+  int64_t gwords;
+  int32_t k, sh, d_g, d_o, nK1, s, nD, a, o;
+  bool edge;
+  bool trace;                     // record trade k's trace fields of the phase
+};
+
+// The producer / consumer phase of a fused giant pass over the superblocks
+// [sb_from, sb_to) (sb_from even). Workgroup-wide; false if the members
+// found do not match the superblock counts.
+__device__ __forceinline__ bool fused_roles(const TradeArgs& A, BigLds& B, const FusedCtx& C, int64_t sb_from,
+                                            int64_t sb_to) {
   const int tid = threadIdx.x;
   const int nt = blockDim.x;
   const int w = tid >> 6;
   const int l = lane_id();
   const int np = (nt >> 6) >> 1;               // producer wavefronts; as many consume
-  const int so = 1 - sh;
+  const int32_t k = C.k, sh = C.sh, so = 1 - C.sh, d_g = C.d_g, d_o = C.d_o, nK1 = C.nK1, s = C.s;
+  const int32_t nD = C.nD, a = C.a, o = C.o;
+  const bool edge = C.edge;
+  const uint64_t kgp = ((uint64_t)o << 1) | (uint64_t)sh;   // key of the giant's partner entry
+  const unsigned long long* bm = C.bm;
+  const int64_t gwords = C.gwords;
+  unsigned long long* I = C.I;
+  uint64_t* E = C.E;
+  int32_t* D = C.D;
+  const bool items_only = I != nullptr;
   const uint64_t* O = B.u.tile.E;
-  int32_t* posO = B.u.tile.D;                  // merged position of O[j]
-  int32_t* kc = B.u.tile.D + kFastOther;       // kept entries O[j] stands for (0, 1 or 2)
-  uint64_t* Kk = reinterpret_cast<uint64_t*>(B.u.tile.D + 2 * kFastOther);   // kept keys from O
+  const int32_t* kc = B.u.tile.D + kFastOther;
+  const uint64_t* Kk = reinterpret_cast<const uint64_t*>(B.u.tile.D + 2 * kFastOther);
   const int pair = w < np ? w : w - np;
   uint64_t* ringW = B.u.tile.E + kFastOther + pair * kRing;
   int4* ringM = reinterpret_cast<int4*>(B.u.tile.E + kFastOther + kPairs * kRing) + pair * kRing;
@@ -1198,78 +1280,20 @@ __device__ __forceinline__ bool giant_fused(const TradeArgs& A, int32_t k, int32
     return reinterpret_cast<int32_t*>(B.u.tile.E + kFastOther + 3 * kPairs * kRing) + 4 * q;
   };
   int32_t* rc = ring_ctr(pair);
-  const int64_t gwords = A.gs.gwords;
-  const int64_t nsb = gwords >> 6;
-  const unsigned long long* bm = A.gs.bm + (int64_t)gi * gwords;
-  int32_t* sc = A.gs.sc + (int64_t)gi * nsb;
-  if (tid == 0) { B.cnt[0] = 0; B.cnt[1] = 0; B.cnt[2] = 0; }
+  if (tid == 0) B.cnt[2] = 0;
   if (w < np && l < 4) rc[l] = 0;   // fill, head, done, finished wavefronts (trace)
   __syncthreads();
-  // O entries: shared neighbour (bit set in the giant's set) or partner
-  for (int32_t j = tid; j < d_o; j += nt) {
-    const int32_t x = ent_node(O[j]);
-    const bool common = (load_agent_u64(&bm[x >> 6]) >> (x & 63)) & 1ull;
-    const bool partner = x == h;
-    kc[j] = common ? 2 : (partner ? 1 : 0);
-    if (common) atomicAdd(&B.cnt[0], 1);
-    if (partner) B.cnt[1] = 1;
-  }
-  __syncthreads();
-  int32_t nK1 = 0;
-  for (int32_t j0 = 0; j0 < d_o; j0 += nt) {
-    const int32_t j = j0 + tid;
-    const int32_t c = j < d_o ? kc[j] : 0;
-    int32_t tot;
-    const int32_t p = nK1 + block_excl_scan(c, B.scan, &tot);
-    if (c == 2) {
-      const uint64_t kx0 = (uint64_t)ent_node(O[j]) << 1;
-      Kk[p] = kx0;
-      Kk[p + 1] = kx0 | 1ull;
-    } else if (c == 1) {
-      Kk[p] = O[j] >> 32;
-    }
-    nK1 += tot;
-  }
-  // superblock range of each producer (an even number: whole chunks); its
-  // members counted from the superblock counts, which are cleared
-  const int64_t R = (((nsb + np - 1) / np) + 1) & ~(int64_t)1;
-  const int64_t sb_lo = (int64_t)pair * R < nsb ? (int64_t)pair * R : nsb;
-  const int64_t sb_hi = sb_lo + R < nsb ? sb_lo + R : nsb;
-  if (w < np) {
-    int32_t my = 0;
-    for (int64_t j = sb_lo + l; j < sb_hi; j += kWave) {
-      const int32_t c = load_agent(&sc[j]);
-      my += c;
-      if (c != 0) sc[j] = 0;
-    }
-    my = wave_sum(my);
-    if (l == 0) B.sboff[w] = my;
-  }
-  __syncthreads();
-  int32_t run = 0, total = 0;
-  for (int q = 0; q < np; ++q) {
-    const int32_t c = B.sboff[q];
-    if (q < pair) run += c;
-    total += c;
-  }
-  const int32_t n_common = B.cnt[0];
-  const bool edge = B.cnt[1] != 0;
-  const uint64_t kgp = ((uint64_t)o << 1) | (uint64_t)sh;   // key of the giant's partner entry
-  const int32_t nD = s - nK1 - (edge ? 1 : 0);
-  const int32_t a = (sh == 0 ? d_g : d_o) - n_common - (edge ? 1 : 0);
-  if (total != d_g) {
-    __syncthreads();
-    if (tid == 0) raise_error(A, kErrGather, k, 2000000 + total - d_g);
-    return false;
-  }
-  if (A.trace && tid == 0) A.trace[kTraceFields * (int64_t)k + 15] = (int64_t)now_ticks();
+  const int64_t span = sb_to - sb_from;
+  const int64_t R = (((span + np - 1) / np) + 1) & ~(int64_t)1;
+  const int64_t sb_lo = sb_from + ((int64_t)pair * R < span ? (int64_t)pair * R : span);
+  const int64_t sb_hi = sb_lo + R < sb_to ? sb_lo + R : sb_to;
+  int32_t run = load_agent(&C.pre[sb_lo]);
   // trace: the last producer and the last consumer to finish record the time
   auto trace_finish = [&](int q, int field) {
     int32_t* f = ring_ctr(q) + 3;
-    if (A.trace && l == 0 && atomicAdd(f, 1) == np - 1)
+    if (C.trace && A.trace && l == 0 && atomicAdd(f, 1) == np - 1)
       A.trace[kTraceFields * (int64_t)k + field] = (int64_t)now_ticks();
   };
-
   if (w < np) {
     // ---- producer
     const int32_t run0 = run;
@@ -1343,8 +1367,6 @@ __device__ __forceinline__ bool giant_fused(const TradeArgs& A, int32_t k, int32
           while (ro < d_o && (uint32_t)ent_node(O[ro]) < id_end) {
             const int32_t x = ent_node(O[ro]);
             const int32_t kx = kc[ro];
-            const int32_t lo = run + wave_sum(bits_below(w0, w1, (int32_t)b0, x));
-            if (l == 0) posO[ro] = ro + lo + ((kx == 2 && sh < so) ? 1 : 0);
             if ((uint32_t)x < b0) { ++ro0; rk0 += kx; }
             if ((uint32_t)x < b1) { ++ro1; rk1 += kx; }
             s0 |= (uint32_t)x >= b0 && (uint32_t)x < b1;
@@ -1403,7 +1425,7 @@ __device__ __forceinline__ bool giant_fused(const TradeArgs& A, int32_t k, int32
     lds_publish(&rc[0], fill);
     lds_publish(&rc[2], 1);
     // the members found must match the superblock counts of the range
-    if (l == 0 && run - run0 != B.sboff[w]) B.cnt[2] = 1;
+    if (l == 0 && run - run0 != load_agent(&C.pre[sb_hi]) - load_agent(&C.pre[sb_lo])) B.cnt[2] = 1;
     trace_finish(0, 20);
     if (A.trace && l == 0) atomicAdd(ring_ctr(2) + 3, spins);
   } else {
@@ -1454,9 +1476,12 @@ __device__ __forceinline__ bool giant_fused(const TradeArgs& A, int32_t k, int32
             const int32_t rkt = rK + ((edge && kgp < key) ? 1 : 0);
             pd = (common || x == o) ? s - 1 - rkt : pe - rkt;
           }
-          E[pe] = e;
-          D[pd] = pe;
-          if (I) put_item(I, pd, e, nD, a);
+          if (items_only) {
+            put_item(I, pd, e, nD, a);
+          } else {
+            E[pe] = e;
+            D[pd] = pe;
+          }
         }
       }
       head += cnt;
@@ -1466,16 +1491,149 @@ __device__ __forceinline__ bool giant_fused(const TradeArgs& A, int32_t k, int32
     if (A.trace && l == 0) atomicAdd(ring_ctr(3) + 3, spins);
   }
   __syncthreads();
-  if (A.trace && tid == 0) {
+  if (C.trace && A.trace && tid == 0) {
     A.trace[kTraceFields * (int64_t)k + 22] = *(ring_ctr(2) + 3);
     A.trace[kTraceFields * (int64_t)k + 23] = *(ring_ctr(3) + 3);
   }
-  if (B.cnt[2] != 0) {
+  const bool ok = B.cnt[2] == 0;
+  __syncthreads();
+  return ok;
+}
+
+// One giant side (node h, side sh, d_g members in giant gi's bitmap) and a
+// small other side O (ascending in LDS, d_o <= kFastOther entries, node o):
+// the merged list E and the disjoint / kept index array D in one pass over
+// the bitmap, without materialising the giant's sorted list.
+//
+// A member's merged position is its rank among the giant's members plus the
+// O entries below it; its disjoint position is that minus the kept entries
+// below it (kept ones fill D from the back by the same count). The kept
+// entries follow from O alone: a shared neighbour x gives the keys (x, 0) and
+// (x, 1), the partner edge gives O's entry for h and the giant's for o. So
+// within a bitmap word that holds no node of O and not o both counts are
+// constant; the producer works them out per word (per chunk of 128 words
+// (8192 ids) when the chunk holds none of those nodes), and only the members
+// of the few words that do hold one scan on from the word's counts.
+//
+// Half of the wavefronts produce, half consume, in pairs. A producer streams
+// a contiguous range of superblocks (starting at the prefix of the
+// superblock counts before it) with wide loads kept in flight a batch ahead,
+// and compacts the nonzero words into its pair's LDS ring; it never stores to
+// global memory, so its waits for loads never wait for stores. Its consumer
+// expands the ring one word per lane and writes the entries. The two
+// synchronise through LDS counters only.
+//
+// If I is not null, the items of a shared write phase are published too (as
+// if the split moved nothing; the positions the split touches are rewritten
+// after it). Clears the superblock counts of the bitmap; its words are
+// cleared when the edges are written. Workgroup-wide; sets *nD and *a in
+// every thread. False (error raised) if the bitmap does not hold d_g members.
+__device__ __forceinline__ bool giant_fused(const TradeArgs& A, int32_t k, int32_t gi, int sh, int32_t d_g,
+                                            int32_t h, int32_t o, int32_t d_o, BigLds& B, uint64_t* E,
+                                            int32_t* D, int32_t s, int32_t* nD_out, int32_t* a_out,
+                                            unsigned long long* I, bool* split_done) {
+  const int tid = threadIdx.x;
+  const int nt = blockDim.x;
+  const int w = tid >> 6;
+  const int l = lane_id();
+  const int np = (nt >> 6) >> 1;               // producer wavefronts; as many consume
+  const int so = 1 - sh;
+  const uint64_t* O = B.u.tile.E;
+  int32_t* posO = B.u.tile.D;                  // merged position of O[j]
+  int32_t* kc = B.u.tile.D + kFastOther;       // kept entries O[j] stands for (0, 1 or 2)
+  uint64_t* Kk = reinterpret_cast<uint64_t*>(B.u.tile.D + 2 * kFastOther);   // kept keys from O
+  const int64_t gwords = A.gs.gwords;
+  const int64_t nsb = gwords >> 6;
+  const unsigned long long* bm = A.gs.bm + (int64_t)gi * gwords;
+  int32_t* sc = A.gs.sc + (int64_t)gi * nsb;
+  if (tid == 0) { B.cnt[0] = 0; B.cnt[1] = 0; B.cnt[2] = 0; }
+  __syncthreads();
+  // O entries: shared neighbour (bit set in the giant's set) or partner
+  for (int32_t j = tid; j < d_o; j += nt) {
+    const int32_t x = ent_node(O[j]);
+    const bool common = (load_agent_u64(&bm[x >> 6]) >> (x & 63)) & 1ull;
+    const bool partner = x == h;
+    kc[j] = common ? 2 : (partner ? 1 : 0);
+    if (common) atomicAdd(&B.cnt[0], 1);
+    if (partner) B.cnt[1] = 1;
+  }
+  __syncthreads();
+  int32_t nK1 = 0;
+  for (int32_t j0 = 0; j0 < d_o; j0 += nt) {
+    const int32_t j = j0 + tid;
+    const int32_t c = j < d_o ? kc[j] : 0;
+    int32_t tot;
+    const int32_t p = nK1 + block_excl_scan(c, B.scan, &tot);
+    if (c == 2) {
+      const uint64_t kx0 = (uint64_t)ent_node(O[j]) << 1;
+      Kk[p] = kx0;
+      Kk[p + 1] = kx0 | 1ull;
+    } else if (c == 1) {
+      Kk[p] = O[j] >> 32;
+    }
+    nK1 += tot;
+  }
+  // prefix of the superblock counts (cleared as they are read); each
+  // producer takes an even number of superblocks (whole chunks)
+  int32_t* pre = A.sbpre + (int64_t)blockIdx.x * A.sbpre_stride;
+  {
+    // a contiguous run of superblocks per thread, loaded together
+    const int64_t per = (nsb + nt - 1) / nt;
+    const int64_t j0 = (int64_t)tid * per;
+    const int64_t j1 = j0 + per < nsb ? j0 + per : nsb;
+    int32_t sum = 0;
+    for (int64_t j = j0; j < j1; ++j) sum += load_agent(&sc[j]);
+    int32_t tot;
+    int32_t at = block_excl_scan(sum, B.scan, &tot);
+    for (int64_t j = j0; j < j1; ++j) {
+      const int32_t c = load_agent(&sc[j]);
+      store_agent(&pre[j], at);
+      at += c;
+      if (c != 0) sc[j] = 0;
+    }
+    if (tid == 0) store_agent(&pre[nsb], tot);
+  }
+  __syncthreads();
+  const int32_t total = load_agent(&pre[nsb]);
+  // ranks of O's nodes among the giant's members: the prefix of their
+  // superblock plus the members below them in it (8 lanes, 8 words each)
+  for (int32_t j0 = w * 8; j0 < d_o; j0 += (nt >> 6) * 8) {
+    const int32_t j = j0 + (l >> 3);
+    int32_t c = 0;
+    int32_t x = 0;
+    if (j < d_o) {
+      x = ent_node(O[j]);
+      const int64_t wb = (int64_t)(x >> 12) * 64 + (l & 7) * 8;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int64_t wi = wb + i;
+        const int32_t below = x - (int32_t)(wi * 64);   // bits of word wi below x
+        if (below > 0) {
+          const uint64_t word = load_agent_u64(&bm[wi]);
+          c += below >= 64 ? popc64(word) : popc64(word & ((1ull << below) - 1ull));
+        }
+      }
+    }
+    c += __shfl_xor(c, 1, kWave);
+    c += __shfl_xor(c, 2, kWave);
+    c += __shfl_xor(c, 4, kWave);
+    if (j < d_o && (l & 7) == 0)
+      posO[j] = j + load_agent(&pre[x >> 12]) + c + ((kc[j] == 2 && sh < so) ? 1 : 0);
+  }
+  __syncthreads();   // posO is read by other wavefronts below
+  const int32_t n_common = B.cnt[0];
+  const bool edge = B.cnt[1] != 0;
+  const uint64_t kgp = ((uint64_t)o << 1) | (uint64_t)sh;   // key of the giant's partner entry
+  const int32_t nD = s - nK1 - (edge ? 1 : 0);
+  const int32_t a = (sh == 0 ? d_g : d_o) - n_common - (edge ? 1 : 0);
+  if (total != d_g) {
     __syncthreads();
-    if (tid == 0) raise_error(A, kErrGather, k, 3000000);
+    if (tid == 0) raise_error(A, kErrGather, k, 2000000 + total - d_g);
     return false;
   }
-  // other side
+  // with items (a shared write phase), only the items are written: the
+  // split is applied to them afterwards; the other side's entries first
+  const bool items_only = I != nullptr;
   for (int32_t j = tid; j < d_o; j += nt) {
     const uint64_t e = O[j];
     const uint64_t key = e >> 32;
@@ -1486,16 +1644,114 @@ __device__ __forceinline__ bool giant_fused(const TradeArgs& A, int32_t k, int32
     }
     const int32_t rkt = lo + ((edge && kgp < key) ? 1 : 0);
     const int32_t pe = posO[j];
-    E[pe] = e;
     const int32_t pd = kc[j] ? s - 1 - rkt : pe - rkt;
-    D[pd] = pe;
-    if (I) put_item(I, pd, e, nD, a);
+    if (items_only) {
+      put_item(I, pd, e, nD, a);
+    } else {
+      E[pe] = e;
+      D[pd] = pe;
+    }
+  }
+  if (A.trace && tid == 0) A.trace[kTraceFields * (int64_t)k + 15] = (int64_t)now_ticks();
+  FusedCtx C{bm, pre, I, E, D, gwords, k, sh, d_g, d_o, nK1, s, nD, a, o, edge, true};
+  // a large giant with a shared write phase offers the upper half of its
+  // superblocks to an idle workgroup: the other side's entries, flags and
+  // kept keys go to the (otherwise unused) entry region of the slot
+  const bool offer = items_only && d_g >= kFusedShareMin && nsb >= 4 && (int)blockIdx.x < kMaxJobs;
+  const int64_t mid = offer ? (((nsb >> 1) + 1) & ~(int64_t)1) : nsb;
+  HelpJob* Jf = A.jobs + kMaxJobs + blockIdx.x;
+  if (offer) {
+    unsigned long long* Pub = reinterpret_cast<unsigned long long*>(E);
+    for (int32_t j = tid; j < d_o; j += nt) {
+      store_agent_u64(&Pub[j], O[j]);
+      store_agent(reinterpret_cast<int32_t*>(Pub + d_o + nK1) + j, kc[j]);
+    }
+    for (int32_t j = tid; j < nK1; j += nt) store_agent_u64(&Pub[d_o + j], Kk[j]);
+    if (tid == 0) {
+      store_agent(&Jf->f.k, k);
+      store_agent(&Jf->f.gi, gi);
+      store_agent(&Jf->f.side, sh);
+      store_agent(&Jf->f.d, d_g);
+      store_agent(&Jf->f.d_o, d_o);
+      store_agent(&Jf->f.nK1, nK1);
+      store_agent(&Jf->f.s, s);
+      store_agent(&Jf->f.nD, nD);
+      store_agent(&Jf->f.a, a);
+      store_agent(&Jf->f.o, o);
+      store_agent(&Jf->f.edge, edge ? 1 : 0);
+      store_agent64(&Jf->f.sb_from, mid);
+      store_agent64(&Jf->f.sb_to, nsb);
+      store_agent(&Jf->f.phase, 3);
+    }
+    publish_wait();
+    __syncthreads();
+    if (tid == 0) open_job(A, Jf, 1, kCwJobMask2);
+  }
+  bool ok = fused_roles(A, B, C, 0, mid);
+  if (offer) {
+    // nobody took the upper half yet: do it here
+    if (tid == 0) B.next = claim_chunk(Jf);
+    __syncthreads();
+    const bool mine = B.next >= 0;
+    __syncthreads();
+    if (mine) {
+      C.trace = false;
+      ok = fused_roles(A, B, C, mid, nsb) && ok;
+      publish_wait();
+      __syncthreads();
+      if (tid == 0) atomic_add(&Jf->c.done, 1);
+    }
+    if (tid == 0) close_job(A, Jf, 1, kCwJobMask2);
+    __syncthreads();
+  }
+  if (!ok) {
+    if (tid == 0) raise_error(A, kErrGather, k, 3000000);
+    return false;
   }
   if (tid == 0) B.tick[0] = now_ticks();
+  if (items_only) publish_wait();   // the items are gathered by other wavefronts next
   __syncthreads();
   *nD_out = nD;
   *a_out = a;
+  *split_done = items_only;
   return true;
+}
+
+// An idle workgroup's part of owner j's giant bitmap pass (phase 3 of the
+// second set of jobs, its one chunk claimed): the other side, its flags and
+// kept keys from j's slot into this workgroup's LDS, then the producer /
+// consumer phase over the offered superblocks, writing into j's items.
+__device__ __forceinline__ void fused_help(const TradeArgs& A, BigLds& B, int32_t j) {
+  const int tid = threadIdx.x;
+  const int nt = blockDim.x;
+  HelpJob* J = A.jobs + kMaxJobs + j;
+  consume_order();
+  const int32_t k = load_agent(&J->f.k), gi = load_agent(&J->f.gi), sh = load_agent(&J->f.side);
+  const int32_t d_g = load_agent(&J->f.d), d_o = load_agent(&J->f.d_o), nK1 = load_agent(&J->f.nK1);
+  const int32_t s = load_agent(&J->f.s), nD = load_agent(&J->f.nD), a = load_agent(&J->f.a);
+  const int32_t o = load_agent(&J->f.o), edge = load_agent(&J->f.edge);
+  const int64_t sb_from = load_agent64(&J->f.sb_from), sb_to = load_agent64(&J->f.sb_to);
+  uint64_t* slot = A.slots + (int64_t)j * A.slot_elems;
+  const unsigned long long* Pub = reinterpret_cast<const unsigned long long*>(slot);
+  int32_t* kc = B.u.tile.D + kFastOther;
+  uint64_t* Kk = reinterpret_cast<uint64_t*>(B.u.tile.D + 2 * kFastOther);
+  for (int32_t i = tid; i < d_o; i += nt) {
+    B.u.tile.E[i] = load_agent_u64(&Pub[i]);
+    kc[i] = load_agent(reinterpret_cast<const int32_t*>(Pub + d_o + nK1) + i);
+  }
+  for (int32_t i = tid; i < nK1; i += nt) Kk[i] = load_agent_u64(&Pub[d_o + i]);
+  __syncthreads();
+  const int64_t gwords = A.gs.gwords;
+  FusedCtx C{A.gs.bm + (int64_t)gi * gwords, A.sbpre + (int64_t)j * A.sbpre_stride,
+             reinterpret_cast<unsigned long long*>(slot + shared_list_off(A)), nullptr, nullptr, gwords,
+             k, sh, d_g, d_o, nK1, s, nD, a, o, edge != 0, false};
+  const bool ok = fused_roles(A, B, C, sb_from, sb_to);
+  publish_wait();   // the items are complete before the owner hears of it
+  __syncthreads();
+  if (tid == 0) {
+    if (!ok) raise_error(A, kErrGather, k, 5000000);
+    atomic_add(&J->c.done, 1);
+  }
 }
 
 // Items at the positions the split touched (its windows and its partners),
@@ -1541,6 +1797,7 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
   int32_t nD = 0, a = 0;
   bool classified = false;   // E and D already built by the one-pass giant path
   bool items_ready = false;  // ... and the shared write phase's items too
+  bool items_only = false;   // ... only those (the split is applied to them)
   const bool share = A.help_min > 0 && s >= A.help_min && (int)blockIdx.x < kMaxJobs;
   unsigned long long* Ig = reinterpret_cast<unsigned long long*>(slot + shared_list_off(A));
   if (tid == 0) B.tick[0] = 0;
@@ -1587,7 +1844,7 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
     t_lists = now_ticks();
     if (fused) {
       if (!giant_fused(A, k, gside ? gv : gu, gside, gside ? dv : du, gside ? v : u, gside ? u : v,
-                       gside ? du : dv, B, E, D, s, &nD, &a, share ? Ig : nullptr))
+                       gside ? du : dv, B, E, D, s, &nD, &a, share ? Ig : nullptr, &items_only))
         return;
       classified = true;
       items_ready = share;
@@ -1688,14 +1945,18 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
     // free by now); D in LDS, or a long split: in place, in order
     const int32_t T = split_steps(nD, a);
     int32_t* Lt = reinterpret_cast<int32_t*>(B.u.tile.E);
-    if (!in_lds && T > 0 && 4 * T <= kSplitSlots) {
+    if (items_only) {
+      if (T > 0)
+        item_split(Ig, nD, a, A.seed, A.round, k, Lt, B.u.tile.E + kSplitSlots / 2, kSplitSlots,
+                   Lt + 3 * kSplitSlots, Lt + 3 * kSplitSlots + 2 * (kSplitSlots / 4), B.sboff);
+    } else if (!in_lds && T > 0 && 4 * T <= kSplitSlots) {
       lds_split(D, nD, a, A.seed, A.round, k, Lt, Lt + kSplitSlots, Lt + 2 * kSplitSlots, kSplitSlots,
                 Lt + 3 * kSplitSlots, Lt + 3 * kSplitSlots + 2 * (kSplitSlots / 4), B.sboff);
     } else {
       block_split(D, nD, a, A.seed, A.round, k, B.sboff, 2 * kTradeBlock);
     }
   }
-  if (items_ready) split_fix_items(E, D, nD, a, A.seed, A.round, k, Ig);
+  if (items_ready && !items_only) split_fix_items(E, D, nD, a, A.seed, A.round, k, Ig);
   if (tid == 0) {
     B.cnt[1] = 0;
     B.cnt[2] = 0;
@@ -1829,6 +2090,27 @@ __device__ __forceinline__ void big_worker(const TradeArgs& A, BigLds& B) {
     __syncthreads();
     if (k == -2) break;
     if (k < 0) {
+      // the whole workgroup may take part of a giant's bitmap pass
+      if (tid == 0) {
+        int32_t jj = -1;
+        const uint64_t m = (uint64_t)(uint32_t)load_agent(&A.ctrl[cw(kCwJobMask2)]) |
+                           ((uint64_t)(uint32_t)load_agent(&A.ctrl[cw(kCwJobMask3)]) << 32);
+        if (m) {
+          const int rot = (int)(blockIdx.x & 63);
+          const uint64_t rm = rot ? ((m >> rot) | (m << (64 - rot))) : m;
+          const int32_t j = (int32_t)((__builtin_ctzll(rm) + rot) & 63);
+          if (claim_chunk(A.jobs + kMaxJobs + j) >= 0) jj = j;
+        }
+        B.next = jj;
+      }
+      __syncthreads();
+      const int32_t fj = B.next;
+      __syncthreads();
+      if (fj >= 0) {
+        fused_help(A, B, fj);
+        backoff = 1;
+        continue;
+      }
       WriteCounts H{0, 0, 0};
       const bool helped = try_help(A, (int32_t)blockIdx.x, H);
       counters[1] += H.fwd;
