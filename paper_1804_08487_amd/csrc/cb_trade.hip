@@ -1197,8 +1197,9 @@ constexpr int kRing = 512;             // nonzero bitmap words buffered per prod
 constexpr int kPairs = kWavesPerBlock / 2;
 constexpr int kChunkBatch = 8;         // 1 KiB bitmap chunks a producer keeps in flight (twice)
 static_assert(kFastOther + 3 * kPairs * kRing + 2 * kPairs <= kBigCap, "fused pass LDS fits the tile");
-constexpr int32_t kSlowWord = 0x40000000;
-constexpr int32_t kFusedShareMin = 16384;   // giant sides whose bitmap pass is offered in halves   // ring word holding a node of the other side (or its node)
+constexpr int32_t kSlowWord = 0x40000000;   // ring word holding a node of the other side (or its node)
+constexpr int32_t kFusedShareMin = 2048;    // members per offered part of a giant's bitmap pass
+constexpr int32_t kFusedParts = 16;         // at most this many parts
 constexpr int kBufDword3 = 0x00020000; // raw buffer resource: 32-bit format, bounds-checked by bytes
 constexpr int kCpolSc1 = 16;           // cache policy: agent-coherent load
 
@@ -1654,11 +1655,14 @@ __device__ __forceinline__ bool giant_fused(const TradeArgs& A, int32_t k, int32
   }
   if (A.trace && tid == 0) A.trace[kTraceFields * (int64_t)k + 15] = (int64_t)now_ticks();
   FusedCtx C{bm, pre, I, E, D, gwords, k, sh, d_g, d_o, nK1, s, nD, a, o, edge, true};
-  // a large giant with a shared write phase offers the upper half of its
-  // superblocks to an idle workgroup: the other side's entries, flags and
-  // kept keys go to the (otherwise unused) entry region of the slot
-  const bool offer = items_only && d_g >= kFusedShareMin && nsb >= 4 && (int)blockIdx.x < kMaxJobs;
-  const int64_t mid = offer ? (((nsb >> 1) + 1) & ~(int64_t)1) : nsb;
+  // a large giant with a shared write phase offers all but the first of
+  // its parts (one per kFusedShareMin members, at most kFusedParts) to idle
+  // workgroups: the other side's entries, flags and kept keys go to the
+  // (otherwise unused) entry region of the slot
+  const int32_t parts = d_g / kFusedShareMin < kFusedParts ? d_g / kFusedShareMin : kFusedParts;
+  const bool offer = items_only && parts >= 2 && nsb >= 2 * parts && (int)blockIdx.x < kMaxJobs;
+  const int64_t step = offer ? (((nsb / parts) + 1) & ~(int64_t)1) : nsb;   // superblocks per part
+  const int32_t noff = offer ? (int32_t)((nsb + step - 1) / step) - 1 : 0;   // parts offered
   HelpJob* Jf = A.jobs + kMaxJobs + blockIdx.x;
   if (offer) {
     unsigned long long* Pub = reinterpret_cast<unsigned long long*>(E);
@@ -1679,29 +1683,31 @@ __device__ __forceinline__ bool giant_fused(const TradeArgs& A, int32_t k, int32
       store_agent(&Jf->f.a, a);
       store_agent(&Jf->f.o, o);
       store_agent(&Jf->f.edge, edge ? 1 : 0);
-      store_agent64(&Jf->f.sb_from, mid);
+      store_agent64(&Jf->f.sb_from, step);
       store_agent64(&Jf->f.sb_to, nsb);
       store_agent(&Jf->f.phase, 3);
     }
     publish_wait();
     __syncthreads();
-    if (tid == 0) open_job(A, Jf, 1, kCwJobMask2);
+    if (tid == 0) open_job(A, Jf, noff, kCwJobMask2);
   }
-  bool ok = fused_roles(A, B, C, 0, mid);
+  bool ok = fused_roles(A, B, C, 0, step < nsb ? step : nsb);
   if (offer) {
-    // nobody took the upper half yet: do it here
-    if (tid == 0) B.next = claim_chunk(Jf);
-    __syncthreads();
-    const bool mine = B.next >= 0;
-    __syncthreads();
-    if (mine) {
-      C.trace = false;
-      ok = fused_roles(A, B, C, mid, nsb) && ok;
+    // parts nobody took yet are done here
+    C.trace = false;
+    while (true) {
+      if (tid == 0) B.next = claim_chunk(Jf);
+      __syncthreads();
+      const int32_t c = B.next;
+      __syncthreads();
+      if (c < 0) break;
+      const int64_t from = (c + 1) * step;
+      ok = fused_roles(A, B, C, from, from + step < nsb ? from + step : nsb) && ok;
       publish_wait();
       __syncthreads();
       if (tid == 0) atomic_add(&Jf->c.done, 1);
     }
-    if (tid == 0) close_job(A, Jf, 1, kCwJobMask2);
+    if (tid == 0) close_job(A, Jf, noff, kCwJobMask2);
     __syncthreads();
   }
   if (!ok) {
@@ -1718,10 +1724,10 @@ __device__ __forceinline__ bool giant_fused(const TradeArgs& A, int32_t k, int32
 }
 
 // An idle workgroup's part of owner j's giant bitmap pass (phase 3 of the
-// second set of jobs, its one chunk claimed): the other side, its flags and
+// second set of jobs, chunk c claimed: part c + 1): the other side, its flags and
 // kept keys from j's slot into this workgroup's LDS, then the producer /
 // consumer phase over the offered superblocks, writing into j's items.
-__device__ __forceinline__ void fused_help(const TradeArgs& A, BigLds& B, int32_t j) {
+__device__ __forceinline__ void fused_help(const TradeArgs& A, BigLds& B, int32_t j, int32_t c) {
   const int tid = threadIdx.x;
   const int nt = blockDim.x;
   HelpJob* J = A.jobs + kMaxJobs + j;
@@ -1730,7 +1736,8 @@ __device__ __forceinline__ void fused_help(const TradeArgs& A, BigLds& B, int32_
   const int32_t d_g = load_agent(&J->f.d), d_o = load_agent(&J->f.d_o), nK1 = load_agent(&J->f.nK1);
   const int32_t s = load_agent(&J->f.s), nD = load_agent(&J->f.nD), a = load_agent(&J->f.a);
   const int32_t o = load_agent(&J->f.o), edge = load_agent(&J->f.edge);
-  const int64_t sb_from = load_agent64(&J->f.sb_from), sb_to = load_agent64(&J->f.sb_to);
+  const int64_t step = load_agent64(&J->f.sb_from), nsb = load_agent64(&J->f.sb_to);
+  const int64_t sb_from = (c + 1) * step, sb_to = sb_from + step < nsb ? sb_from + step : nsb;
   uint64_t* slot = A.slots + (int64_t)j * A.slot_elems;
   const unsigned long long* Pub = reinterpret_cast<const unsigned long long*>(slot);
   int32_t* kc = B.u.tile.D + kFastOther;
@@ -2099,7 +2106,8 @@ __device__ __forceinline__ void big_worker(const TradeArgs& A, BigLds& B) {
           const int rot = (int)(blockIdx.x & 63);
           const uint64_t rm = rot ? ((m >> rot) | (m << (64 - rot))) : m;
           const int32_t j = (int32_t)((__builtin_ctzll(rm) + rot) & 63);
-          if (claim_chunk(A.jobs + kMaxJobs + j) >= 0) jj = j;
+          const int32_t c = claim_chunk(A.jobs + kMaxJobs + j);
+          if (c >= 0) jj = j | (c << 8);
         }
         B.next = jj;
       }
@@ -2107,7 +2115,7 @@ __device__ __forceinline__ void big_worker(const TradeArgs& A, BigLds& B) {
       const int32_t fj = B.next;
       __syncthreads();
       if (fj >= 0) {
-        fused_help(A, B, fj);
+        fused_help(A, B, fj & 255, fj >> 8);
         backoff = 1;
         continue;
       }
