@@ -143,7 +143,9 @@ cb_status global_trade_steps(cb_graph* g, uint64_t seed, uint32_t round, int32_t
                                 chunks done, 18 all chunks done, 19 chunks
                                 written by the owner; fused pass: 20 last
                                 bitmap reader done, 21 last entry writer
-                                done; 22, 23 unused. Ticks of
+                                done, 22 waits of its bitmap readers for
+                                ring space, 23 waits of its entry writers
+                                for ring entries. Ticks of
                                 the device's constant 100 MHz clock; -1 where
                                 not recorded */
 
@@ -167,7 +169,7 @@ cb_status graph_download_state(cb_graph* g, int32_t which, void* host, int64_t c
 #define CB_OPT_DEBUG_CHECKS  9  /* 1: extra invariant checks between kernels */
 #define CB_OPT_HELP_MIN     11  /* workgroup trades with deg u + deg v >= this
                                    let idle wavefronts of the kernel share their
-                                   write phase (0 = never). Default 8192. */
+                                   write phase (0 = never). Default 4096. */
 #define CB_OPT_HELP_GROUPS  12  /* workgroup workers help the shared phases of
                                    owners in their residue class modulo this
                                    (a divisor of 64; default 2) */

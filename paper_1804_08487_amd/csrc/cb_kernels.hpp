@@ -58,8 +58,8 @@ constexpr int kStackCap = 16;         // ready trades a wavefront may keep
 constexpr int kTraceFields = 24;      // int64 per trade of the optional trace
 constexpr int kMaxJobs = 64;          // workgroups that can open their write phase to helpers
                                       // (and, in a second set of jobs, part of a giant's bitmap pass)
-constexpr int32_t kHelpChunk = 512;   // output items per claimed chunk
-constexpr int32_t kHelpMinItems = 8192;   // default: smaller trades work alone
+constexpr int32_t kHelpChunk = 128;   // output items per claimed chunk
+constexpr int32_t kHelpMinItems = 4096;   // default: smaller trades work alone
 constexpr int32_t kSbChunk = 16;      // bitmap superblocks per claimed extraction chunk
 
 // A phase of one large trade open to helper wavefronts (one job per

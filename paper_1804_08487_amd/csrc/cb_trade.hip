@@ -1516,19 +1516,24 @@ __device__ __forceinline__ bool fused_roles(const TradeArgs& A, BigLds& B, const
 // (8192 ids) when the chunk holds none of those nodes), and only the members
 // of the few words that do hold one scan on from the word's counts.
 //
-// Half of the wavefronts produce, half consume, in pairs. A producer streams
-// a contiguous range of superblocks (starting at the prefix of the
-// superblock counts before it) with wide loads kept in flight a batch ahead,
-// and compacts the nonzero words into its pair's LDS ring; it never stores to
-// global memory, so its waits for loads never wait for stores. Its consumer
-// expands the ring one word per lane and writes the entries. The two
-// synchronise through LDS counters only.
+// Half of the wavefronts produce, half consume, in pairs (fused_roles). A
+// producer streams a contiguous range of superblocks (starting at the prefix
+// of the superblock counts before it) with wide loads kept in flight a batch
+// ahead, and compacts the nonzero words into its pair's LDS ring; it never
+// stores to global memory, so its waits for loads never wait for stores. Its
+// consumer expands the ring one word per lane and writes the entries. The
+// two synchronise through LDS counters only. The ranks of O's nodes among
+// the members (the prefix of their superblock plus the members below them in
+// it) are worked out first, so O's entries are written before the members.
 //
-// If I is not null, the items of a shared write phase are published too (as
-// if the split moved nothing; the positions the split touches are rewritten
-// after it). Clears the superblock counts of the bitmap; its words are
-// cleared when the edges are written. Workgroup-wide; sets *nD and *a in
-// every thread. False (error raised) if the bitmap does not hold d_g members.
+// If I is not null (a shared write phase), only the items are written, at the
+// positions before the split (the caller applies the split to them), and a
+// large giant offers all but the first of its superblock parts to idle
+// workgroups (fused_help), taking back any part nobody claimed. Otherwise E
+// and D are written. Clears the superblock counts of the bitmap; its words
+// are cleared when the edges are written. Workgroup-wide; sets *nD and *a in
+// every thread, and *split_done when only the items were written. False
+// (error raised) if the bitmap does not hold d_g members.
 __device__ __forceinline__ bool giant_fused(const TradeArgs& A, int32_t k, int32_t gi, int sh, int32_t d_g,
                                             int32_t h, int32_t o, int32_t d_o, BigLds& B, uint64_t* E,
                                             int32_t* D, int32_t s, int32_t* nD_out, int32_t* a_out,
