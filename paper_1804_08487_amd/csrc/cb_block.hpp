@@ -97,6 +97,158 @@ __device__ void wave_bitonic_sort(T* a, uint32_t s) {
   }
 }
 
+// Largest bucket that bucket_sort ranks; a fuller one sends the caller to
+// another sort.
+constexpr int32_t kBucketMax = 256;
+
+// Bucket bits for s entries: at most 16 entries per bucket on average, no
+// more than maxbits bits and no more bits than the keys have.
+__device__ __forceinline__ int bucket_bits(int32_t s, int keybits, int maxbits) {
+  int lb = 0;
+  while (lb < maxbits && lb < keybits && (16 << lb) < s) ++lb;
+  return lb;
+}
+
+typedef __attribute__((address_space(3))) uint64_t lds_u64;
+typedef __attribute__((address_space(3))) int32_t lds_i32;
+
+// Bucket sort: ascending sort of a[0..s) by the whole 64-bit value into
+// out[0..s), where every key (e >> 32) is below 2^keybits. A counting scatter
+// by the top lb bits of the key moves the entries from a into buf (cnt: 2^lb
+// LDS counters), then an entry's place within its bucket is the number of
+// smaller entries in the bucket (equal ones, which distinct keys never give,
+// are ordered by their position in buf). a and out may be the same array;
+// buf overlaps neither. Workgroup-wide; barriers inside; *flag is LDS.
+constexpr int kBucketBatch = 8;   // loads in flight per thread
+
+struct Buckets {
+  int32_t nb;
+  int sh;
+  // the bucket of an entry (clamped, so a stray key cannot leave the arrays)
+  __device__ __forceinline__ uint32_t of(uint64_t e) const {
+    const uint32_t b = (uint32_t)(e >> 32) >> sh;
+    return b < (uint32_t)nb ? b : (uint32_t)nb - 1u;
+  }
+};
+
+// Counting and scatter passes. False, with a and out untouched, if a bucket
+// holds more than kBucketMax entries. Afterwards cnt[b] is the end of bucket
+// b in buf and the start of bucket b + 1.
+template <typename T, typename U>
+__device__ __forceinline__ bool bucket_scatter(const T* a, U* buf, int32_t s, const Buckets& K, lds_i32* cnt,
+                                               lds_i32* scan, lds_i32* flag) {
+  const int tid = threadIdx.x;
+  const int nt = blockDim.x;
+  for (int32_t b = tid; b < K.nb; b += nt) cnt[b] = 0;
+  if (tid == 0) *flag = 0;
+  __syncthreads();
+  for (int32_t i0 = tid; i0 < s; i0 += kBucketBatch * nt) {
+    uint64_t v[kBucketBatch];
+#pragma unroll
+    for (int r = 0; r < kBucketBatch; ++r) v[r] = i0 + r * nt < s ? a[i0 + r * nt] : 0;
+#pragma unroll
+    for (int r = 0; r < kBucketBatch; ++r)
+      if (i0 + r * nt < s) atomicAdd((int32_t*)&cnt[K.of(v[r])], 1);
+  }
+  __syncthreads();
+  // each thread scans a run of consecutive buckets
+  const int32_t per = (K.nb + nt - 1) / nt;
+  const int32_t b0 = tid * per < K.nb ? tid * per : K.nb;
+  const int32_t b1 = b0 + per < K.nb ? b0 + per : K.nb;
+  int32_t sum = 0;
+  bool full = false;
+  for (int32_t b = b0; b < b1; ++b) {
+    const int32_t c = cnt[b];
+    sum += c;
+    full |= c > kBucketMax;
+  }
+  if (full) *flag = 1;
+  int32_t tot;
+  int32_t run = block_excl_scan(sum, (int32_t*)scan, &tot);   // its barriers publish *flag
+  if (*flag) return false;                                    // uniform
+  for (int32_t b = b0; b < b1; ++b) {
+    const int32_t c = cnt[b];
+    cnt[b] = run;
+    run += c;
+  }
+  __syncthreads();
+  for (int32_t i0 = tid; i0 < s; i0 += kBucketBatch * nt) {
+    uint64_t v[kBucketBatch];
+#pragma unroll
+    for (int r = 0; r < kBucketBatch; ++r) v[r] = i0 + r * nt < s ? a[i0 + r * nt] : 0;
+#pragma unroll
+    for (int r = 0; r < kBucketBatch; ++r)
+      if (i0 + r * nt < s) buf[atomicAdd((int32_t*)&cnt[K.of(v[r])], 1)] = v[r];
+  }
+  __syncthreads();
+  return true;
+}
+
+// Place of the entry at position i of src (bucket-ordered, positions offset
+// by base) in the sorted order.
+template <typename U>
+__device__ __forceinline__ int32_t bucket_rank(const U* src, int32_t base, int32_t i, uint64_t e,
+                                               const Buckets& K, const lds_i32* cnt) {
+  const uint32_t b = K.of(e);
+  const int32_t lo = b ? cnt[b - 1] : 0;
+  const int32_t hi = cnt[b];
+  int32_t r = lo;
+  for (int32_t j = lo; j < hi; ++j) {
+    const uint64_t x = src[j - base];
+    r += (x < e || (x == e && j < i)) ? 1 : 0;
+  }
+  return r;
+}
+
+// All three arrays in LDS. Kept out of line, like the variant below: the
+// trade kernel has no registers to spare for them.
+// False, with a and out untouched, if a bucket holds more than kBucketMax
+// entries.
+__device__ __noinline__ bool bucket_sort_lds(lds_u64* a, lds_u64* buf, lds_u64* out, int32_t s, int keybits,
+                                             int lb, lds_i32* cnt, lds_i32* scan, lds_i32* flag) {
+  const Buckets K{1 << lb, keybits - lb};
+  if (!bucket_scatter(a, buf, s, K, cnt, scan, flag)) return false;
+  for (int32_t i = threadIdx.x; i < s; i += blockDim.x) {
+    const uint64_t e = buf[i];
+    out[bucket_rank(buf, 0, i, e, K, cnt)] = e;
+  }
+  __syncthreads();
+  return true;
+}
+
+// buf in global memory (a and out anywhere): the ranking reads buf through
+// windows staged in LDS (stage: cap entries), each window with a bucket's
+// worth of margin on both sides, so every bucket it ranks lies inside.
+__device__ __noinline__ bool bucket_sort_staged(uint64_t* a, uint64_t* buf, uint64_t* out, int32_t s,
+                                                int keybits, int lb, lds_i32* cnt, lds_i32* scan,
+                                                lds_i32* flag, lds_u64* stage, int32_t cap) {
+  const int tid = threadIdx.x;
+  const int nt = blockDim.x;
+  const Buckets K{1 << lb, keybits - lb};
+  if (!bucket_scatter(a, buf, s, K, cnt, scan, flag)) return false;
+  const int32_t W = cap - 2 * kBucketMax;
+  for (int32_t p0 = 0; p0 < s; p0 += W) {
+    const int32_t p1 = p0 + W < s ? p0 + W : s;
+    const int32_t q0 = p0 > kBucketMax ? p0 - kBucketMax : 0;
+    const int32_t q1 = p1 + kBucketMax < s ? p1 + kBucketMax : s;
+    for (int32_t i0 = q0 + tid; i0 < q1; i0 += kBucketBatch * nt) {
+      uint64_t v[kBucketBatch];
+#pragma unroll
+      for (int r = 0; r < kBucketBatch; ++r) v[r] = i0 + r * nt < q1 ? buf[i0 + r * nt] : 0;
+#pragma unroll
+      for (int r = 0; r < kBucketBatch; ++r)
+        if (i0 + r * nt < q1) stage[i0 + r * nt - q0] = v[r];
+    }
+    __syncthreads();
+    for (int32_t i = p0 + tid; i < p1; i += nt) {
+      const uint64_t e = stage[i - q0];
+      out[bucket_rank(stage, q0, i, e, K, cnt)] = e;
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
 // LDS needed by block_radix_sort.
 struct RadixLds {
   int32_t hist[256];

@@ -64,6 +64,8 @@ struct WaveLds {
   int32_t stack[kStackCap];
 };
 
+constexpr int kBucketLdsBits = 10;    // bucket sort of a trade in LDS: counters beside the tile
+constexpr int kBucketTileBits = 13;   // ... of a trade in the slot: counters in the (unused) LDS tile
 struct BigLds {
   union {
     struct {
@@ -79,6 +81,8 @@ struct BigLds {
   uint64_t tick[1];    // trace: end of a giant's bit pass
   int32_t base[2];
   int32_t ndone;
+  int32_t bflag;                   // bucket sort: a bucket is too full
+  int32_t bkt[1 << kBucketLdsBits];   // bucket sort counters of trades held in LDS
   // giant extraction: output offset and members per superblock; the split
   // reuses both as one buffer of 2 * kTradeBlock swap partners
   int32_t sboff[kTradeBlock];
@@ -1061,6 +1065,7 @@ __device__ __forceinline__ void small_worker(const TradeArgs& A, WaveLds& W) {
 // later trades (plus partner and left-out node) from the CSR row, then the
 // arrivals from the inbox. Workgroup-wide; false (error raised) on a size
 // mismatch.
+constexpr int kGatherBatch = 4;   // loads in flight per thread while collecting a list
 __device__ __forceinline__ bool gather_list(const TradeArgs& A, int32_t k, int64_t b, int32_t d, int32_t ni,
                             int side, uint64_t* out, BigLds& B) {
   const int tid = threadIdx.x;
@@ -1068,15 +1073,28 @@ __device__ __forceinline__ bool gather_list(const TradeArgs& A, int32_t k, int64
   __syncthreads();
   // one LDS counter update per wavefront and chunk (trip count is uniform
   // across a wavefront: the bound is rounded up to whole wavefronts)
+  // kGatherBatch strides of loads are issued before the first is used.
   const int32_t dr = (d + kWave - 1) / kWave * kWave;
-  for (int32_t e = tid; e < dr; e += blockDim.x) {
-    const int32_t t = e < d ? A.col_t[b + e] : 0;
-    const bool fresh = e < d && tinfo_trade(t) >= k;
-    const uint64_t m = ballot(fresh);
-    int32_t base = 0;
-    if (lane_id() == 0 && m) base = atomicAdd(&B.cnt[0], popc64(m));
-    base = wave_bcast(base, 0);
-    if (fresh) out[base + rank_below(m)] = make_entry(A.col[b + e], side, tag_of(t, k));
+  const int32_t nt = blockDim.x;
+  for (int32_t e0 = tid; e0 < dr; e0 += kGatherBatch * nt) {
+    int32_t t[kGatherBatch], x[kGatherBatch];
+#pragma unroll
+    for (int r = 0; r < kGatherBatch; ++r) {
+      const int32_t e = e0 + r * nt;
+      t[r] = e < d ? A.col_t[b + e] : 0;
+      x[r] = e < d ? A.col[b + e] : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < kGatherBatch; ++r) {
+      const int32_t e = e0 + r * nt;
+      if (e >= dr) break;   // uniform across a wavefront
+      const bool fresh = e < d && tinfo_trade(t[r]) >= k;
+      const uint64_t m = ballot(fresh);
+      int32_t base = 0;
+      if (lane_id() == 0 && m) base = atomicAdd(&B.cnt[0], popc64(m));
+      base = wave_bcast(base, 0);
+      if (fresh) out[base + rank_below(m)] = make_entry(x[r], side, tag_of(t[r], k));
+    }
   }
   __syncthreads();
   const int32_t nf = B.cnt[0];
@@ -1085,8 +1103,19 @@ __device__ __forceinline__ bool gather_list(const TradeArgs& A, int32_t k, int64
     if (tid == 0) raise_error(A, kErrGather, k, 1000000 + nf + ni - d);
     return false;
   }
-  for (int32_t j = tid; j < ni; j += blockDim.x)
-    out[nf + j] = make_entry(load_agent(&A.inbox[b + j]), side, kTagEmit);
+  for (int32_t j0 = tid; j0 < ni; j0 += kGatherBatch * nt) {
+    int32_t x[kGatherBatch];
+#pragma unroll
+    for (int r = 0; r < kGatherBatch; ++r) {
+      const int32_t j = j0 + r * nt;
+      x[r] = j < ni ? load_agent(&A.inbox[b + j]) : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < kGatherBatch; ++r) {
+      const int32_t j = j0 + r * nt;
+      if (j < ni) out[nf + j] = make_entry(x[r], side, kTagEmit);
+    }
+  }
   __syncthreads();
   return true;
 }
@@ -1887,9 +1916,31 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
     }
     __syncthreads();
     t_lists = now_ticks();
+    // Bucket sort: its buffer follows the entries in LDS while both fit in
+    // the tile (the index array is not used yet), else it is in the slot and
+    // read back through LDS windows.
+    // If a bucket is too full (node ids bunched together), LSD radix sort:
     // LDS ping-pong when both halves fit, else through the slot; the digit
-    // counters live in the (not yet used) LDS index array
-    if (in_lds && s <= kBigCap / 2)
+    // counters live in the (not yet used) LDS index array.
+    const int lb = bucket_bits(s, A.keybits, in_lds ? kBucketLdsBits : kBucketTileBits);
+    lds_i32* bscan = (lds_i32*)B.scan;
+    lds_i32* bflag = (lds_i32*)&B.bflag;
+    bool bsorted;
+    if (in_lds && 2 * s <= kBigCap + kBigCap / 2) {
+      lds_u64* le = (lds_u64*)B.u.tile.E;
+      bsorted = bucket_sort_lds(le, le + s, le, s, A.keybits, lb, (lds_i32*)B.bkt, bscan, bflag);
+    } else if (in_lds) {
+      // staged through the index array (kBigCap / 2 entries)
+      bsorted = bucket_sort_staged(E, slot, E, s, A.keybits, lb, (lds_i32*)B.bkt, bscan, bflag,
+                                   (lds_u64*)B.u.tile.D, kBigCap / 2);
+    } else {
+      // counters in the index array, staged through the entry array
+      bsorted = bucket_sort_staged(E, slot + A.smax, E, s, A.keybits, lb, (lds_i32*)B.u.tile.D, bscan,
+                                   bflag, (lds_u64*)B.u.tile.E, kBigCap);
+    }
+    if (bsorted) {
+      // sorted in place
+    } else if (in_lds && s <= kBigCap / 2)
       E = seg_radix_sort(E, E + kBigCap / 2, s, A.keybits, B.u.tile.D, B.scan);
     else if (in_lds)
       E = seg_radix_sort(E, slot, s, A.keybits, B.u.tile.D, B.scan);

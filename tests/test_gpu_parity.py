@@ -117,6 +117,29 @@ def test_hub_above_2_15_entries(orc, tier):
     _run_and_compare(orc, rp, col, seed=3, rounds=2, options=opts)
 
 
+def _bunched_graph():
+    """Two nodes whose neighbours are runs of consecutive ids (2000 and 1500
+    of them) among 60000 nodes, plus a sparse random graph: their trades have
+    lists whose keys crowd a few top-bit buckets."""
+    rng = np.random.default_rng(91)
+    n = 60000
+    edges = {(0, i) for i in range(2, 2002)} | {(1, i) for i in range(3000, 4500)}
+    for _ in range(90000):
+        x, y = sorted(int(t) for t in rng.integers(2, n, 2))
+        if x != y:
+            edges.add((x, y))
+    return graphgen.edge_list_to_csr(n, sorted(edges))
+
+
+@pytest.mark.parametrize("tier", ["default", "all_global", "no_help"])
+def test_bunched_neighbour_ids(orc, tier):
+    """Workgroup trades whose neighbour ids are bunched together (a bucket of
+    the first sort pass too full for ranking) and spread out, alike."""
+    _say(f"bunched graph tier {tier}")
+    rp, col = _bunched_graph()
+    _run_and_compare(orc, rp, col, seed=5, rounds=3, options=TIERS[tier])
+
+
 def test_partial_round_then_full_round(orc):
     """A step-wise round that stops early must not leak state into the next."""
     rp, col = graphgen.pld_graph(3000, 2, 300, 2.0, 11)
