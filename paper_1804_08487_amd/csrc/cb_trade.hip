@@ -1120,6 +1120,70 @@ __device__ __forceinline__ bool gather_list(const TradeArgs& A, int32_t k, int64
   return true;
 }
 
+// Both lists of trade k into out[0..du + dv) in no particular order (the
+// caller sorts them): u's and v's row entries whose other end has not traded
+// yet, then the arrivals in their inboxes, each as an entry of its side.
+// Workgroup-wide; false (error raised) if a row's count does not match.
+__device__ __forceinline__ bool gather_both(const TradeArgs& A, int32_t k, int64_t bu, int32_t du, int32_t niu,
+                                            int64_t bv, int32_t dv, int32_t niv, uint64_t* out, BigLds& B) {
+  const int tid = threadIdx.x;
+  const int32_t nt = blockDim.x;
+  if (tid == 0) { B.cnt[0] = 0; B.cnt[1] = 0; }
+  __syncthreads();
+  const int32_t s = du + dv;
+  const int32_t sr = (s + kWave - 1) / kWave * kWave;
+  for (int32_t e0 = tid; e0 < sr; e0 += kGatherBatch * nt) {
+    int32_t t[kGatherBatch], x[kGatherBatch];
+#pragma unroll
+    for (int r = 0; r < kGatherBatch; ++r) {
+      const int32_t e = e0 + r * nt;
+      const int64_t at = e < du ? bu + e : bv + (e - du);
+      t[r] = e < s ? A.col_t[at] : 0;
+      x[r] = e < s ? A.col[at] : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < kGatherBatch; ++r) {
+      const int32_t e = e0 + r * nt;
+      if (e >= sr) break;   // uniform across a wavefront
+      const int side = e < du ? 0 : 1;
+      const bool fresh = e < s && tinfo_trade(t[r]) >= k;
+      const uint64_t m = ballot(fresh);
+      const uint64_t mu = ballot(fresh && side == 0);
+      int32_t base = 0;
+      if (lane_id() == 0 && m) {
+        base = atomicAdd(&B.cnt[0], popc64(m));
+        if (mu) atomicAdd(&B.cnt[1], popc64(mu));
+      }
+      base = wave_bcast(base, 0);
+      if (fresh) out[base + rank_below(m)] = make_entry(x[r], side, tag_of(t[r], k));
+    }
+  }
+  __syncthreads();
+  const int32_t nf = B.cnt[0];
+  const int32_t nfu = B.cnt[1];
+  __syncthreads();
+  if (nfu + niu != du || nf - nfu + niv != dv) {
+    if (tid == 0) raise_error(A, kErrGather, k, 1000000 + nf + niu + niv - s);
+    return false;
+  }
+  const int32_t ni = niu + niv;
+  for (int32_t j0 = tid; j0 < ni; j0 += kGatherBatch * nt) {
+    int32_t x[kGatherBatch];
+#pragma unroll
+    for (int r = 0; r < kGatherBatch; ++r) {
+      const int32_t j = j0 + r * nt;
+      x[r] = j < ni ? load_agent(&A.inbox[j < niu ? bu + j : bv + (j - niu)]) : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < kGatherBatch; ++r) {
+      const int32_t j = j0 + r * nt;
+      if (j < ni) out[nf + j] = make_entry(x[r], j < niu ? 0 : 1, kTagEmit);
+    }
+  }
+  __syncthreads();
+  return true;
+}
+
 // Write giant gi's neighbour set, ascending, as entries of `side` of trade k
 // into out[0..d), and clear its counts for the next round (the write phase
 // clears its words).
@@ -1870,7 +1934,11 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
         if (!extract_giant(A, k, gi, side, d, L2 + off, B)) return;
       } else if (d <= kBigCap) {
         if (!gather_list(A, k, side ? bv : bu, d, side ? niv : niu, side, B.u.tile.E, B)) return;
-        block_bitonic_sort(B.u.tile.E, (uint32_t)d);
+        lds_u64* le = (lds_u64*)B.u.tile.E;
+        if (2 * d > kBigCap + kBigCap / 2 ||
+            !bucket_sort_lds(le, le + d, le, d, A.keybits, bucket_bits(d, A.keybits, kBucketLdsBits),
+                             (lds_i32*)B.bkt, (lds_i32*)B.scan, (lds_i32*)&B.bflag))
+          block_bitonic_sort(B.u.tile.E, (uint32_t)d);
         lds_side = side;
       } else {
         // the other node is too large for LDS (giant degree set above kBigCap)
@@ -1909,12 +1977,7 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
     }
     __syncthreads();
   } else {
-    for (int side = 0; side < 2; ++side) {
-      if (!gather_list(A, k, side ? bv : bu, side ? dv : du, side ? niv : niu, side,
-                       E + (side ? du : 0), B))
-        return;
-    }
-    __syncthreads();
+    if (!gather_both(A, k, bu, du, niu, bv, dv, niv, E, B)) return;
     t_lists = now_ticks();
     // Bucket sort: its buffer follows the entries in LDS while both fit in
     // the tile (the index array is not used yet), else it is in the slot and
