@@ -1291,6 +1291,7 @@ constexpr int kPairs = kWavesPerBlock / 2;
 constexpr int kChunkBatch = 8;         // 1 KiB bitmap chunks a producer keeps in flight (twice)
 static_assert(kFastOther + 3 * kPairs * kRing + 2 * kPairs <= kBigCap, "fused pass LDS fits the tile");
 constexpr int32_t kSlowWord = 0x40000000;   // ring word holding a node of the other side (or its node)
+constexpr int kSbRegs = 8;   // superblock counts per thread kept in registers by the fused pass
 constexpr int32_t kFusedShareMin = 2048;    // members per offered part of a giant's bitmap pass
 constexpr int32_t kFusedParts = 16;         // at most this many parts
 constexpr int kBufDword3 = 0x00020000; // raw buffer resource: 32-bit format, bounds-checked by bytes
@@ -1645,6 +1646,16 @@ __device__ __forceinline__ bool giant_fused(const TradeArgs& A, int32_t k, int32
   const int64_t nsb = gwords >> 6;
   const unsigned long long* bm = A.gs.bm + (int64_t)gi * gwords;
   int32_t* sc = A.gs.sc + (int64_t)gi * nsb;
+  // superblock counts: a contiguous run per thread, loaded now (their
+  // latency overlaps the probes of O below) and kept in registers when the
+  // run is short enough
+  const int64_t per = (nsb + nt - 1) / nt;
+  const int64_t j0s = (int64_t)tid * per < nsb ? (int64_t)tid * per : nsb;
+  const int64_t j1s = j0s + per < nsb ? j0s + per : nsb;
+  const bool inreg = per <= kSbRegs;   // uniform
+  int32_t cv[kSbRegs];
+#pragma unroll
+  for (int i = 0; i < kSbRegs; ++i) cv[i] = inreg && j0s + i < j1s ? load_agent(&sc[j0s + i]) : 0;
   if (tid == 0) { B.cnt[0] = 0; B.cnt[1] = 0; B.cnt[2] = 0; }
   __syncthreads();
   // O entries: shared neighbour (bit set in the giant's set) or partner
@@ -1675,25 +1686,36 @@ __device__ __forceinline__ bool giant_fused(const TradeArgs& A, int32_t k, int32
   // prefix of the superblock counts (cleared as they are read); each
   // producer takes an even number of superblocks (whole chunks)
   int32_t* pre = A.sbpre + (int64_t)blockIdx.x * A.sbpre_stride;
+  int32_t total;
   {
-    // a contiguous run of superblocks per thread, loaded together
-    const int64_t per = (nsb + nt - 1) / nt;
-    const int64_t j0 = (int64_t)tid * per;
-    const int64_t j1 = j0 + per < nsb ? j0 + per : nsb;
     int32_t sum = 0;
-    for (int64_t j = j0; j < j1; ++j) sum += load_agent(&sc[j]);
-    int32_t tot;
-    int32_t at = block_excl_scan(sum, B.scan, &tot);
-    for (int64_t j = j0; j < j1; ++j) {
-      const int32_t c = load_agent(&sc[j]);
-      store_agent(&pre[j], at);
-      at += c;
-      if (c != 0) sc[j] = 0;
+    if (inreg) {
+#pragma unroll
+      for (int i = 0; i < kSbRegs; ++i) sum += cv[i];
+    } else {
+      for (int64_t j = j0s; j < j1s; ++j) sum += load_agent(&sc[j]);
     }
-    if (tid == 0) store_agent(&pre[nsb], tot);
+    int32_t at = block_excl_scan(sum, B.scan, &total);
+    if (inreg) {
+#pragma unroll
+      for (int i = 0; i < kSbRegs; ++i) {
+        if (j0s + i < j1s) {
+          store_agent(&pre[j0s + i], at);
+          at += cv[i];
+          if (cv[i] != 0) sc[j0s + i] = 0;
+        }
+      }
+    } else {
+      for (int64_t j = j0s; j < j1s; ++j) {
+        const int32_t c = load_agent(&sc[j]);
+        store_agent(&pre[j], at);
+        at += c;
+        if (c != 0) sc[j] = 0;
+      }
+    }
+    if (tid == 0) store_agent(&pre[nsb], total);
   }
   __syncthreads();
-  const int32_t total = load_agent(&pre[nsb]);
   // ranks of O's nodes among the giant's members: the prefix of their
   // superblock plus the members below them in it (8 lanes, 8 words each)
   for (int32_t j0 = w * 8; j0 < d_o; j0 += (nt >> 6) * 8) {
