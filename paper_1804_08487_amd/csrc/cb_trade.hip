@@ -1686,6 +1686,10 @@ __device__ __forceinline__ bool giant_fused(const TradeArgs& A, int32_t k, int32
   // prefix of the superblock counts (cleared as they are read); each
   // producer takes an even number of superblocks (whole chunks)
   int32_t* pre = A.sbpre + (int64_t)blockIdx.x * A.sbpre_stride;
+  // a copy in LDS, for the ranks of O's nodes below, in the ring space (not
+  // in use until the roles start) when it fits
+  int32_t* preL = reinterpret_cast<int32_t*>(B.u.tile.E + kFastOther);
+  const bool pre_lds = nsb <= 2 * (int64_t)(kBigCap - kFastOther);
   int32_t total;
   {
     int32_t sum = 0;
@@ -1701,6 +1705,7 @@ __device__ __forceinline__ bool giant_fused(const TradeArgs& A, int32_t k, int32
       for (int i = 0; i < kSbRegs; ++i) {
         if (j0s + i < j1s) {
           store_agent(&pre[j0s + i], at);
+          if (pre_lds) preL[j0s + i] = at;
           at += cv[i];
           if (cv[i] != 0) sc[j0s + i] = 0;
         }
@@ -1709,6 +1714,7 @@ __device__ __forceinline__ bool giant_fused(const TradeArgs& A, int32_t k, int32
       for (int64_t j = j0s; j < j1s; ++j) {
         const int32_t c = load_agent(&sc[j]);
         store_agent(&pre[j], at);
+        if (pre_lds) preL[j] = at;
         at += c;
         if (c != 0) sc[j] = 0;
       }
@@ -1739,7 +1745,8 @@ __device__ __forceinline__ bool giant_fused(const TradeArgs& A, int32_t k, int32
     c += __shfl_xor(c, 2, kWave);
     c += __shfl_xor(c, 4, kWave);
     if (j < d_o && (l & 7) == 0)
-      posO[j] = j + load_agent(&pre[x >> 12]) + c + ((kc[j] == 2 && sh < so) ? 1 : 0);
+      posO[j] = j + (pre_lds ? preL[x >> 12] : load_agent(&pre[x >> 12])) + c +
+                ((kc[j] == 2 && sh < so) ? 1 : 0);
   }
   __syncthreads();   // posO is read by other wavefronts below
   const int32_t n_common = B.cnt[0];
