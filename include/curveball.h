@@ -178,7 +178,7 @@ cb_status graph_download_state(cb_graph* g, int32_t which, void* host, int64_t c
 #define CB_OPT_GIANT_DEG     8  /* nodes of at least this degree keep the edges
                                    handed to them in a bitmap over all node ids
                                    (n/8 bytes each) instead of a list; 0 = none.
-                                   Default max(6144, n/1024), raised while the
+                                   Default max(6144, n/2048), raised while the
                                    bitmaps would exceed min(64 GiB, 40% of free
                                    memory). */
 

@@ -558,14 +558,15 @@ cb_status graph_upload(int64_t n, const int64_t* row_ptr, const int32_t* col, vo
     delete g;
     return fail(CB_ENOTSIMPLE, "upload validation: " + error_bits_text(err));
   }
-  // giant nodes: the default threshold is max(6144, n / 1024). Reading a
+  // giant nodes: the default threshold is max(6144, n / 2048). Reading a
   // giant's set back costs n / 8 bytes of bitmap whatever its degree, sorting
-  // a list costs in proportion to the degree; measured on MI355X the two meet
-  // near degree n / 1024 (16384 at n = 2^24), and 6144 keeps every pair below
-  // it within one workgroup's LDS. It rises further if the bitmaps would take
-  // too much memory.
+  // a list costs in proportion to the degree; measured on MI355X a round at
+  // n = 2^24 is fastest near degree n / 2048 (8192; 2% faster than 16384,
+  // 12% faster than 24576), and 6144 keeps every pair below it within one
+  // workgroup's LDS (at n = 2^22, 4096 was 1% slower than 6144). It rises
+  // further if the bitmaps would take too much memory.
   {
-    const int64_t min_deg = std::max<int64_t>(kGiantMinDeg, n / 1024);
+    const int64_t min_deg = std::max<int64_t>(kGiantMinDeg, n / 2048);
     size_t free_b = 0, total_b = 0;
     (void)hipMemGetInfo(&free_b, &total_b);
     const double budget = std::min(64.0 * (1ull << 30), 0.4 * (double)free_b);
