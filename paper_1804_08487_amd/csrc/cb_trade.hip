@@ -1292,7 +1292,7 @@ constexpr int kChunkBatch = 8;         // 1 KiB bitmap chunks a producer keeps i
 static_assert(kFastOther + 3 * kPairs * kRing + 2 * kPairs <= kBigCap, "fused pass LDS fits the tile");
 constexpr int32_t kSlowWord = 0x40000000;   // ring word holding a node of the other side (or its node)
 constexpr int kSbRegs = 8;   // superblock counts per thread kept in registers by the fused pass
-constexpr int32_t kFusedShareMin = 2048;    // members per offered part of a giant's bitmap pass
+constexpr int32_t kFusedShareMin = 512;     // members per offered part of a giant's bitmap pass
 constexpr int32_t kFusedParts = 16;         // at most this many parts
 constexpr int kBufDword3 = 0x00020000; // raw buffer resource: 32-bit format, bounds-checked by bytes
 constexpr int kCpolSc1 = 16;           // cache policy: agent-coherent load
