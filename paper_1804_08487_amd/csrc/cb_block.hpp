@@ -1,5 +1,5 @@
-// Workgroup-level building blocks: prefix sums, in-LDS bitonic sort, and a
-// stable LSD radix sort of one segment in global memory.
+// Workgroup-level building blocks: prefix sums, in-LDS bitonic sort, a
+// bucket sort of entries with distinct keys, and stable LSD radix sorts.
 #pragma once
 
 #include "cb_device.hpp"

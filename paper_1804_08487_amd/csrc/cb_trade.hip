@@ -23,9 +23,10 @@
 // trade").
 //
 // Workers: workgroups [0, nbig) run large trades with the whole workgroup
-// (in LDS up to kBigCap entries, else in a global scratch slot with a radix
-// sort); every other workgroup holds sixteen wavefronts that each run small
-// trades (deg u + deg v <= small_max) in LDS.
+// (in LDS up to kBigCap entries, else in a global scratch slot; lists are
+// bucket-sorted, giant nodes' sets read from bitmaps); every other workgroup
+// holds eight wavefronts that each run small trades (deg u + deg v <=
+// small_max) in LDS.
 #include "cb_block.hpp"
 #include "cb_kernels.hpp"
 
@@ -1059,7 +1060,8 @@ __device__ __forceinline__ void small_worker(const TradeArgs& A, WaveLds& W) {
 
 // ============================================================ large trades
 // One workgroup per trade. Entries live in LDS when deg u + deg v <= kBigCap,
-// otherwise in this workgroup's global scratch slot (sorted by radix sort).
+// otherwise in this workgroup's global scratch slot (bucket sort, with LSD
+// radix sort for node ids bunched together).
 
 // Collect one list of trade k (in any order): the round-start neighbours of
 // later trades (plus partner and left-out node) from the CSR row, then the
