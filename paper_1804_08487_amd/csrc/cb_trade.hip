@@ -375,6 +375,7 @@ __device__ __forceinline__ int32_t source_pop(const TradeArgs& A) {
 
 // Idle wait that grows with the time spent idle (fewer polls of the shared
 // control words while there is nothing to do).
+constexpr int32_t kBigMaxBackoff = 1;    // idle workgroup workers: longest back-off level (about 1 us)
 __device__ __forceinline__ void idle_backoff(int32_t level) {
   for (int32_t i = 0; i < level; ++i) __builtin_amdgcn_s_sleep(32);
 }
@@ -2278,7 +2279,7 @@ __device__ __forceinline__ void big_worker(const TradeArgs& A, BigLds& B) {
         backoff = 1;
       } else {
         idle_backoff(backoff);
-        backoff = backoff < 16 ? backoff * 2 : 16;
+        backoff = backoff < kBigMaxBackoff ? backoff * 2 : kBigMaxBackoff;
       }
       continue;
     }
