@@ -97,8 +97,8 @@ __device__ void wave_bitonic_sort(T* a, uint32_t s) {
   }
 }
 
-// Largest bucket that bucket_sort ranks; a fuller one sends the caller to
-// another sort.
+// Largest bucket the bucket sorts below rank (a fuller one sends the caller
+// to another sort); also the margin of the staged sort's LDS windows.
 constexpr int32_t kBucketMax = 256;
 
 // Bucket bits for s entries: at most 16 entries per bucket on average, no
