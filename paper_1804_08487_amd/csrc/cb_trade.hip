@@ -1289,6 +1289,9 @@ constexpr int32_t kSplitSlots = 8192;
 static_assert(3 * kSplitSlots + 3 * (kSplitSlots / 4) <= kBigCap * 3, "split slots fit the tile");
 
 constexpr int32_t kFastOther = 2048;   // other-side sizes of the one-pass giant classification
+// the split of a fused giant pass's items has at most kFastOther steps (the
+// small side's disjoint entries), which its hash table must hold four times
+static_assert(4 * kFastOther <= kSplitSlots, "item split slots cover the fused pass");
 constexpr int kRing = 512;             // nonzero bitmap words buffered per producer / consumer pair
 constexpr int kPairs = kWavesPerBlock / 2;
 constexpr int kChunkBatch = 8;         // 1 KiB bitmap chunks a producer keeps in flight (twice)
@@ -2103,12 +2106,16 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
     // free by now); D in LDS, or a long split: in place, in order
     const int32_t T = split_steps(nD, a);
     int32_t* Lt = reinterpret_cast<int32_t*>(B.u.tile.E);
+    // hash slots in use: a power of two of at least 4 T (the arrays are laid
+    // out for kSplitSlots); fewer slots are fewer to clear and scan
+    int32_t nslots = 512;
+    while (nslots < 4 * T && nslots < kSplitSlots) nslots <<= 1;
     if (items_only) {
       if (T > 0)
-        item_split(Ig, nD, a, A.seed, A.round, k, Lt, B.u.tile.E + kSplitSlots / 2, kSplitSlots,
+        item_split(Ig, nD, a, A.seed, A.round, k, Lt, B.u.tile.E + kSplitSlots / 2, nslots,
                    Lt + 3 * kSplitSlots, Lt + 3 * kSplitSlots + 2 * (kSplitSlots / 4), B.sboff);
     } else if (!in_lds && T > 0 && 4 * T <= kSplitSlots) {
-      lds_split(D, nD, a, A.seed, A.round, k, Lt, Lt + kSplitSlots, Lt + 2 * kSplitSlots, kSplitSlots,
+      lds_split(D, nD, a, A.seed, A.round, k, Lt, Lt + kSplitSlots, Lt + 2 * kSplitSlots, nslots,
                 Lt + 3 * kSplitSlots, Lt + 3 * kSplitSlots + 2 * (kSplitSlots / 4), B.sboff);
     } else {
       block_split(D, nD, a, A.seed, A.round, k, B.sboff, 2 * kTradeBlock);
