@@ -411,7 +411,7 @@ cb_status enqueue_round(cb_graph* g, uint64_t seed, uint32_t round, int last_ste
                          g->rows_small, g->n_small, g->rp, g->col_out, g->col, g->ctrl);
     if (g->n_mid)
       hipLaunchKernelGGL(k_segsort_mid, dim3(grid_for(g->n_mid, 1, 65536)), dim3(256), 0, st,
-                         g->rows_mid, g->n_mid, g->rp, g->col_out, g->col, g->ctrl);
+                         g->rows_mid, g->n_mid, g->rp, g->col_out, g->col, g->keybits_node, g->ctrl);
     if (g->n_big)
       hipLaunchKernelGGL(k_segsort_big, dim3(grid_for(g->n_big, 1, 8192)), dim3(256), 0, st,
                          g->rows_big, g->n_big, g->rp, g->col_out, g->col, g->keybits_node, g->ctrl);

@@ -187,7 +187,7 @@ __global__ void k_check_rows(int64_t n, const int64_t* rp, const int32_t* out_cu
 __global__ void k_segsort_small(const int32_t* rows, int64_t nrows, const int64_t* rp,
                                 const int32_t* src, int32_t* dst, const int32_t* ctrl);
 __global__ void k_segsort_mid(const int32_t* rows, int64_t nrows, const int64_t* rp,
-                              const int32_t* src, int32_t* dst, const int32_t* ctrl);
+                              const int32_t* src, int32_t* dst, int keybits, const int32_t* ctrl);
 __global__ void k_segsort_big(const int32_t* rows, int64_t nrows, const int64_t* rp,
                               int32_t* src, int32_t* dst, int keybits, const int32_t* ctrl);
 __global__ void k_validate(int64_t n, int64_t nnz, const int64_t* rp, const int32_t* col,

@@ -316,19 +316,80 @@ k_segsort_small(const int32_t* rows, int64_t nrows, const int64_t* rp, const int
   }
 }
 
+// Rows of 65..4096 entries, one workgroup per row. The ids of a row are
+// distinct, so a bucket sort needs no stable pass: a counting scatter by the
+// top bits of the id into LDS (about 16 per bucket), then each id's place is
+// the number of smaller ids in its bucket. A row whose ids crowd one bucket
+// (more than kSegBucketMax) is sorted by the bitonic network instead.
+constexpr int kSegMidPer = kSegMidMax / 256;   // ids per thread
+constexpr int32_t kSegBucketMax = 256;
 __global__ void __launch_bounds__(256)
 k_segsort_mid(const int32_t* rows, int64_t nrows, const int64_t* rp, const int32_t* src,
-              int32_t* dst, const int32_t* ctrl) {
+              int32_t* dst, int keybits, const int32_t* ctrl) {
   __shared__ int32_t buf[kSegMidMax];
+  __shared__ int32_t cnt[kSegMidMax / 16];
+  __shared__ int32_t scan[256 / 64 + 1];
+  __shared__ int32_t full;
   if (ctrl[cw(kCwErr)]) return;
+  const int tid = threadIdx.x;
   for (int64_t r = blockIdx.x; r < nrows; r += gridDim.x) {
     const int32_t x = rows[r];
     const int64_t b = rp[x];
     const int32_t d = (int32_t)(rp[x + 1] - b);
-    for (int32_t i = threadIdx.x; i < d; i += blockDim.x) buf[i] = src[b + i];
+    int lb = 0;
+    while ((16 << lb) < d && lb < keybits) ++lb;   // at most 8: d <= 4096
+    const int32_t nb = 1 << lb;
+    const int sh = keybits - lb;
+    auto bucket = [&](int32_t v) -> int32_t {
+      const uint32_t q = (uint32_t)v >> sh;
+      return q < (uint32_t)nb ? (int32_t)q : nb - 1;
+    };
+    int32_t v[kSegMidPer];
+#pragma unroll
+    for (int q = 0; q < kSegMidPer; ++q) {
+      const int32_t i = tid + q * 256;
+      v[q] = i < d ? src[b + i] : 0;
+    }
+    for (int32_t q = tid; q < nb; q += 256) cnt[q] = 0;
+    if (tid == 0) full = 0;
     __syncthreads();
-    block_bitonic_sort(buf, (uint32_t)d);
-    for (int32_t i = threadIdx.x; i < d; i += blockDim.x) dst[b + i] = buf[i];
+#pragma unroll
+    for (int q = 0; q < kSegMidPer; ++q)
+      if (tid + q * 256 < d) atomicAdd(&cnt[bucket(v[q])], 1);
+    __syncthreads();
+    const int32_t c = tid < nb ? cnt[tid] : 0;   // nb <= 256: one bucket per thread
+    if (c > kSegBucketMax) full = 1;
+    int32_t tot;
+    const int32_t start = block_excl_scan(c, scan, &tot);   // its barriers publish `full`
+    if (full) {
+#pragma unroll
+      for (int q = 0; q < kSegMidPer; ++q)
+        if (tid + q * 256 < d) buf[tid + q * 256] = v[q];
+      __syncthreads();
+      block_bitonic_sort(buf, (uint32_t)d);
+      for (int32_t i = tid; i < d; i += blockDim.x) dst[b + i] = buf[i];
+      __syncthreads();
+      continue;
+    }
+    if (tid < nb) cnt[tid] = start;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kSegMidPer; ++q)
+      if (tid + q * 256 < d) buf[atomicAdd(&cnt[bucket(v[q])], 1)] = v[q];
+    __syncthreads();
+    // cnt[q] is now the end of bucket q and the start of bucket q + 1
+    for (int32_t i = tid; i < d; i += blockDim.x) {
+      const int32_t e = buf[i];
+      const int32_t q = bucket(e);
+      const int32_t lo = q ? cnt[q - 1] : 0;
+      const int32_t hi = cnt[q];
+      int32_t rk = lo;
+      for (int32_t j = lo; j < hi; ++j) {
+        const int32_t y = buf[j];
+        rk += (y < e || (y == e && j < i)) ? 1 : 0;
+      }
+      dst[b + rk] = e;
+    }
     __syncthreads();
   }
 }
