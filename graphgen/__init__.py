@@ -9,6 +9,8 @@ Workloads (degrees i.i.d. from Pld([a,b), gamma), P[k] ~ k^-gamma):
 * ``small``:  n = 8192,  Pld([5, 500), 2.0),      graph seed 1
 * ``mid``:    n = 2^20,  Pld([10, 2^16), 2.0),    graph seed 1
 * ``large``:  n = 2^24,  Pld([20, 2^20), 2.2),    graph seed 1
+* ``hubs``:   n = 2^24,  Pld([1, 2^16), 2.5),     graph seed 3 (sparse, about ten
+  nodes of degree above 8192: the bitmap-set path at the full id range)
 """
 from __future__ import annotations
 
@@ -27,6 +29,8 @@ WORKLOADS = {
     "small": dict(n=8192, a=5, b=500, gamma=2.0, seed=1),
     "mid": dict(n=1 << 20, a=10, b=1 << 16, gamma=2.0, seed=1),
     "large": dict(n=1 << 24, a=20, b=1 << 20, gamma=2.2, seed=1),
+    # sparse graph over 2^24 ids with a handful of nodes above degree 8192
+    "hubs": dict(n=1 << 24, a=1, b=1 << 16, gamma=2.5, seed=3),
 }
 
 _lib = None

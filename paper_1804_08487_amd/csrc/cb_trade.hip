@@ -343,7 +343,8 @@ __device__ __forceinline__ int32_t queue_pop(const TradeArgs& A, int32_t* q, int
     const int sh = (start + i) % shards;
     int32_t* head = &A.ctrl[cw(head0 + sh)];
     const int32_t h = load_agent(head);
-    if (h >= load_agent(&A.ctrl[cw(tail0 + sh)])) continue;
+    // h >= L only after a push overflowed the shard (an error is raised then)
+    if (h >= load_agent(&A.ctrl[cw(tail0 + sh)]) || h >= A.L) continue;
     if (!atomic_cas(head, h, h + 1)) continue;
     int32_t* slot = &q[(int64_t)sh * A.L + h];
     int32_t k;
@@ -662,7 +663,7 @@ __device__ __forceinline__ void extract_chunk(const TradeArgs& A, int32_t k, int
         if (at + idx < hi[t]) store_agent_u64(&X[at + idx], make_entry(x, side, kTagUnknown));
         ++idx;
       }
-      if (l == 0) sc[jj] = 0;
+      if (l == 0) store_agent(&sc[jj], 0);
     }
   }
   if (ballot(bad) && l == 0) raise_error(A, kErrGather, k, 4000000 + c);

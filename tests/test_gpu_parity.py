@@ -1,9 +1,11 @@
 """Parity of the HIP path with the oracle, through the C ABI, on the GPU.
 
 Bit-exact integer results are the bar: every downloaded adjacency must equal
-the oracle's bytes; the matching and the dependency counts are compared
-element by element; at the full large size the matching and dependency
-counts are compared in full and the trade result by its invariants."""
+the oracle's bytes, and the matching and the dependency counts are compared
+element by element, on small graphs under every tier-forcing option set, on
+graphs with a hub or bunched neighbour ids, and on the small workload (every
+round of ten). The full-size workloads are covered by
+``test_gpu_full_size.py``."""
 import os
 import sys
 

@@ -238,3 +238,76 @@ def test_oracle_two_steps_frequencies_match_exact(orc):
     nz = [j for j in range(len(states)) if two[j] > 0]
     assert counts[[j for j in range(len(states)) if two[j] == 0]].sum() == 0
     assert _chi2_ok(counts[nz], [float(two[j]) for j in nz])
+
+
+# Exact one-step rows of a global trade from fixed states, derived once by an
+# independent brute force in rational arithmetic (every node order, every
+# split): the enumerator above must reproduce them. States are edge sets; rows
+# are over the lexicographic order of the state space.
+def _two_triangles(state):
+    adj = {x: set() for x in range(6)}
+    for a, b in state:
+        adj[a].add(b)
+        adj[b].add(a)
+    return all(len(adj[a] & adj[b]) == 1 for a, b in state)
+
+
+def test_enumerator_exact_rows_odd_n_path():
+    states, P = exact_enum.transition_matrix((1, 2, 2, 2, 1))
+    start = states.index(((0, 1), (1, 2), (2, 3), (3, 4)))
+    assert start == 0
+    assert P[start] == [Fraction(68, 135), Fraction(59, 540), Fraction(59, 540), Fraction(13, 540),
+                        Fraction(13, 540), Fraction(2, 15), Fraction(13, 135)]
+
+
+def test_enumerator_exact_rows_small_even():
+    states, P = exact_enum.transition_matrix((1, 1, 2, 2))
+    assert len(states) == 2 and P[0][0] == Fraction(5, 6) and P[0][1] == Fraction(1, 6)
+    states, P = exact_enum.transition_matrix((2, 2, 2, 2))
+    assert len(states) == 3
+    assert all(P[i][j] == (Fraction(2, 3) if i == j else Fraction(1, 6)) for i in range(3) for j in range(3))
+    states, P = exact_enum.transition_matrix((1, 1, 2, 2, 2, 2))
+    assert len(states) == 31 and P[0][0] == Fraction(2, 9)
+
+
+def test_enumerator_exact_rows_five_cycle():
+    states, P = exact_enum.transition_matrix((2, 2, 2, 2, 2))
+    start = states.index(((0, 1), (0, 2), (1, 3), (2, 4), (3, 4)))
+    assert len(states) == 12
+    assert P[start][start] == Fraction(1, 3)
+    assert sum(1 for p in P[start] if p == 0) == 1
+
+
+def test_enumerator_exact_rows_six_nodes_two_classes():
+    tri = ((0, 1), (0, 2), (1, 2), (3, 4), (3, 5), (4, 5))
+    row = exact_enum.global_trade_row(exact_enum.from_edges(6, tri))
+    assert row[tri] == Fraction(31, 270)
+    assert sum(p for s, p in row.items() if _two_triangles(s)) == Fraction(7, 27)
+    assert sum(p for s, p in row.items() if not _two_triangles(s)) == Fraction(20, 27)
+    c6 = ((0, 1), (0, 5), (1, 2), (2, 3), (3, 4), (4, 5))
+    row = exact_enum.global_trade_row(exact_enum.from_edges(6, c6))
+    assert row[c6] == Fraction(193, 1620)
+    assert sum(p for s, p in row.items() if _two_triangles(s)) == Fraction(10, 81)
+
+
+# ---------------------------------------------------------------- graph check
+
+@pytest.mark.parametrize("name,n,rp,col,code", [
+    ("row_ptr0", 2, [1, 1, 2], [1, 0], -1),
+    ("non_monotone", 2, [0, -1, 0], [0], -2),
+    ("negative_id", 2, [0, 1, 2], [-1, 0], -3),
+    ("id_beyond_n", 2, [0, 1, 2], [2, 0], -3),
+    ("self_loop", 2, [0, 2, 3], [0, 1, 0], -4),
+    ("unsorted_row", 3, [0, 2, 3, 4], [2, 1, 0, 0], -5),
+    ("duplicate", 3, [0, 3, 4, 5], [1, 1, 2, 0, 0], -5),
+    ("asymmetric", 3, [0, 1, 2, 2], [1, 2], -6),
+    ("odd_entries", 2, [0, 1, 1], [1], -6),
+])
+def test_check_graph_rejects(orc, name, n, rp, col, code):
+    assert orc.check_graph(np.array(rp, np.int64), np.array(col, np.int32)) == code
+
+
+def test_check_graph_accepts_simple_symmetric(orc):
+    rp, col = graphgen.edge_list_to_csr(5, [(0, 1), (0, 4), (1, 2), (3, 4)])
+    assert orc.check_graph(rp, col) == 0
+    assert orc.check_graph(np.zeros(4, np.int64), np.zeros(0, np.int32)) == 0
