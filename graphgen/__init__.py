@@ -11,6 +11,7 @@ Workloads (degrees i.i.d. from Pld([a,b), gamma), P[k] ~ k^-gamma):
 * ``large``:  n = 2^24,  Pld([20, 2^20), 2.2),    graph seed 1
 * ``hubs``:   n = 2^24,  Pld([1, 2^16), 2.5),     graph seed 3 (sparse, about ten
   nodes of degree above 8192: the bitmap-set path at the full id range)
+* batched:    ``batch_specs`` / ``batch_chain``: 512 chains of 2^10..2^16 nodes
 """
 from __future__ import annotations
 
@@ -129,6 +130,24 @@ def workload(name: str, **kw):
     p = dict(WORKLOADS[name])
     p.update(kw)
     return pld_graph(p["n"], p["a"], p["b"], p["gamma"], p["seed"])
+
+
+def batch_specs(chains: int = 512, seed: int = 4):
+    """The batched workload: chain c has n_c = round(2^U[10,16]) nodes, degrees
+    Pld([2, n_c / 8), gamma_c) with gamma_c ~ U[1.8, 2.6], graph seed 1000 + c
+    and chain seed c. The uniforms come from numpy's PCG64 with `seed`."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    u = rng.random((chains, 2))
+    out = []
+    for c in range(chains):
+        n = int(round(2.0 ** (10 + 6 * u[c, 0])))
+        out.append(dict(n=n, a=2, b=max(3, n // 8), gamma=float(1.8 + 0.8 * u[c, 1]),
+                        graph_seed=1000 + c, chain_seed=c))
+    return out
+
+
+def batch_chain(spec):
+    return pld_graph(spec["n"], spec["a"], spec["b"], spec["gamma"], spec["graph_seed"], threads=1)
 
 
 def edge_list_to_csr(n: int, edges) -> tuple[np.ndarray, np.ndarray]:

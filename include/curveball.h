@@ -182,6 +182,12 @@ cb_status graph_download_state(cb_graph* g, int32_t which, void* host, int64_t c
                                    bitmaps would exceed min(64 GiB, 40% of free
                                    memory). */
 
+#define CB_OPT_HELP_CHUNK   13  /* items per chunk a helper claims from a shared
+                                   write phase (a multiple of 64 in [64, 4096];
+                                   default 128) */
+
+/* Set an option of a graph (any option may change between rounds; none
+ * changes the result, only how the work is scheduled). */
 cb_status graph_set_option(cb_graph* g, int32_t option, int64_t value);
 
 /* Counters of the last completed round (synchronises). */
@@ -211,6 +217,68 @@ cb_status graph_stats(cb_graph* g, cb_round_stats* out);
 /* Kernel timing (CB_OPT_TIMING): mean milliseconds per round of each step,
  * ms[0..4) = matching, depscan, trade, rebuild; rounds timed in *rounds. */
 cb_status graph_kernel_times(cb_graph* g, double* ms, int32_t count, int64_t* rounds);
+
+/* ---- batched chains --------------------------------------------------------
+ * Many independent chains on their own graphs advance together: each round of
+ * a batch is one undirected global trade (Def. "Undirected Global Trade",
+ * Sec. 3.3) of every chain, run as one global trade of the disjoint union of
+ * the chains' graphs whose pairing and split draws are those of each chain on
+ * its own (the chain's seed, its round counter, its local node ids and trade
+ * indices). No edge joins two chains, so no trade of one chain changes the
+ * edges another chain sees, and every chain's result is byte for byte the one
+ * it would have alone (Def. "Relaxed global trade", appendix on EM-GCB: the
+ * pairing is the sort order of a hash of the node ids). This is how many
+ * null-model samples share one GPU: one launch sequence per round for all
+ * chains, the dependency chains of different graphs overlapping in one
+ * persistent trade kernel. */
+
+/* Upload `chains` graphs (chain c: n[c] nodes, host CSR row_ptr[c] of n[c]+1
+ * int64 and col[c] of row_ptr[c][n[c]] int32 with local ids 0..n[c]-1, the
+ * graph form above) with chain seeds seeds[c] and first rounds first_round[c]
+ * (NULL: all 0). The caller keeps ownership of every host array. One handle
+ * owns the device state of all chains. Synchronises `stream` (NULL: the
+ * handle creates its own) before returning. Errors as graph_upload; ids
+ * outside [0, n[c]) give CB_ENOTSIMPLE. */
+cb_status batch_upload(int32_t chains, const int64_t* n, const int64_t* const* row_ptr,
+                       const int32_t* const* col, const uint64_t* seeds, const uint32_t* first_round,
+                       void* stream, uint32_t flags, cb_graph** out);
+
+/* Run `rounds` rounds of every chain of a batch (chain c applies its rounds
+ * r_c, r_c + 1, ...; each chain's round counter then advances by `rounds`).
+ * The launch sequence of `rounds` rounds is captured once as a hipGraph (again
+ * after an option change) and launched on the handle's stream; asynchronous.
+ * With timing or tracing on, the rounds are launched one by one instead. */
+cb_status batch_run(cb_graph* g, uint32_t rounds);
+
+/* Size of chain `chain` (nodes, entries) and the round it applies next. */
+cb_status batch_info(const cb_graph* g, int32_t chain, int64_t* n, int64_t* nnz, uint32_t* next_round);
+
+/* Synchronise and copy chain `chain`'s adjacency (local ids, rows ascending,
+ * row_ptr unchanged) into col (its nnz entries). */
+cb_status batch_download(cb_graph* g, int32_t chain, int32_t* col);
+
+/* ---- autotuner --------------------------------------------------------------
+ * Chooses the wavefront/workgroup size threshold (CB_OPT_SMALL_MAX), the size
+ * from which write phases are shared (CB_OPT_HELP_MIN), their chunk size
+ * (CB_OPT_HELP_CHUNK) and the workgroup workers (CB_OPT_BIG_WORKERS) by
+ * timing `trial_rounds` rounds per candidate from the graph's current state
+ * (coordinate descent from the current options), then restores that state and
+ * keeps the fastest options. The schedule never changes a result. Results are
+ * cached for the process by the shape of the graph (log2 of chains, nodes,
+ * entries and largest degree); with use_cache != 0 a cached choice is applied
+ * without timing. Synchronises. Allocates a temporary copy of the adjacency. */
+typedef struct {
+    int32_t small_max;
+    int32_t help_min;
+    int32_t help_chunk;
+    int32_t big_workers;
+    double ms_per_round;          /* of the chosen options */
+    double default_ms_per_round;  /* of the options the tuner started from */
+    int32_t evaluated;            /* timed candidates (0 when taken from the cache) */
+    int32_t cached;               /* 1: taken from the cache */
+} cb_tune_result;
+
+cb_status graph_autotune(cb_graph* g, uint32_t trial_rounds, int32_t use_cache, cb_tune_result* out);
 
 #ifdef __cplusplus
 }

@@ -24,13 +24,15 @@ CB_VALIDATE = 1
 STEP_MATCHING, STEP_DEPSCAN, STEP_TRADE, STEP_REBUILD = 1, 2, 3, 4
 STATE_PERM, STATE_TRADE_OF, STATE_DEP, STATE_COL, STATE_OUT_CUR, STATE_INBOX_CUR, STATE_TRACE, STATE_OWN_CUR = range(1, 9)
 (OPT_SMALL_MAX, OPT_BIG_WORKERS, OPT_GRID_BLOCKS, OPT_WATCHDOG_MS, OPT_TIMING, OPT_LOCAL_STACK,
- OPT_BIG_LDS_MAX, OPT_GIANT_DEG, OPT_DEBUG_CHECKS, OPT_TRACE, OPT_HELP_MIN, OPT_HELP_GROUPS) = range(1, 13)
+ OPT_BIG_LDS_MAX, OPT_GIANT_DEG, OPT_DEBUG_CHECKS, OPT_TRACE, OPT_HELP_MIN, OPT_HELP_GROUPS,
+ OPT_HELP_CHUNK) = range(1, 14)
 UNMATCHED = 2**31 - 1
 
 # Every symbol declared in include/curveball.h.
 EXPORTS = ("cb_set_allocator", "graph_upload", "graph_info", "global_trade", "graph_sync",
            "graph_download", "graph_free", "cb_last_error", "global_trade_steps",
-           "graph_download_state", "graph_set_option", "graph_stats", "graph_kernel_times")
+           "graph_download_state", "graph_set_option", "graph_stats", "graph_kernel_times",
+           "batch_upload", "batch_run", "batch_info", "batch_download", "graph_autotune")
 
 
 class CurveballError(RuntimeError):
@@ -56,6 +58,16 @@ class RoundStats(ctypes.Structure):
     def as_dict(self):
         return {name: (getattr(self, name) if isinstance(getattr(self, name), float)
                        else int(getattr(self, name))) for name, _ in self._fields_}
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("small_max", ctypes.c_int32), ("help_min", ctypes.c_int32),
+                ("help_chunk", ctypes.c_int32), ("big_workers", ctypes.c_int32),
+                ("ms_per_round", ctypes.c_double), ("default_ms_per_round", ctypes.c_double),
+                ("evaluated", ctypes.c_int32), ("cached", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 _lib = None
@@ -85,6 +97,11 @@ def lib():
         L.graph_set_option.argtypes = [vp, i32, i64]
         L.graph_stats.argtypes = [vp, ctypes.POINTER(RoundStats)]
         L.graph_kernel_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(i64)]
+        L.batch_upload.argtypes = [i32, vp, vp, vp, vp, vp, vp, u32, ctypes.POINTER(vp)]
+        L.batch_run.argtypes = [vp, u32]
+        L.batch_info.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(u32)]
+        L.batch_download.argtypes = [vp, i32, vp]
+        L.graph_autotune.argtypes = [vp, u32, i32, ctypes.POINTER(TuneResult)]
         for name in EXPORTS:
             if name not in ("graph_free", "cb_last_error"):
                 getattr(L, name).restype = ctypes.c_int
@@ -187,6 +204,11 @@ class Graph:
         _check(lib().graph_kernel_times(self._h, ms, 4, ctypes.byref(rounds)))
         return [float(x) for x in ms], int(rounds.value)
 
+    def autotune(self, trial_rounds: int = 2, use_cache: bool = True):
+        res = TuneResult()
+        _check(lib().graph_autotune(self._h, trial_rounds, 1 if use_cache else 0, ctypes.byref(res)))
+        return res.as_dict()
+
     def close(self):
         if getattr(self, "_h", None):
             lib().graph_free(self._h)
@@ -203,3 +225,55 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+class Batch(Graph):
+    """Independent chains advancing together on one GPU: chain c is the graph
+    ``graphs[c] = (row_ptr, col)`` with chain seed ``seeds[c]``; every round
+    of the batch is one global trade of every chain (see ``batch_upload``)."""
+
+    def __init__(self, graphs, seeds, first_rounds=None, stream=None, validate: bool = True):
+        self._keep = []
+        C = len(graphs)
+        ns = np.array([len(rp) - 1 for rp, _ in graphs], np.int64)
+        rps = (ctypes.c_void_p * C)()
+        cols = (ctypes.c_void_p * C)()
+        self.row_ptrs = []
+        for c, (rp, col) in enumerate(graphs):
+            rp = np.ascontiguousarray(rp, dtype=np.int64)
+            col = np.ascontiguousarray(col, dtype=np.int32)
+            if len(col) == 0:
+                col = np.zeros(1, np.int32)
+            self._keep += [rp, col]
+            self.row_ptrs.append(rp.copy())
+            rps[c] = rp.ctypes.data
+            cols[c] = col.ctypes.data
+        sd = np.array([int(x) & (2**64 - 1) for x in seeds], np.uint64)
+        fr = None if first_rounds is None else np.array(first_rounds, np.uint32)
+        if stream is None:
+            stream = current_stream_handle()
+        self._stream = stream
+        h = ctypes.c_void_p()
+        _check(lib().batch_upload(C, ns.ctypes.data, ctypes.cast(rps, ctypes.c_void_p),
+                                  ctypes.cast(cols, ctypes.c_void_p), sd.ctypes.data,
+                                  fr.ctypes.data if fr is not None else None, stream,
+                                  CB_VALIDATE if validate else 0, ctypes.byref(h)))
+        self._keep = []
+        self._h = h
+        self.chains = C
+        self.n = int(ns.sum())
+        self.nnz = int(sum(int(rp[-1]) for rp in self.row_ptrs))
+
+    def run(self, rounds: int):
+        _check(lib().batch_run(self._h, rounds))
+
+    def info(self, chain: int):
+        n, nnz, r = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_uint32()
+        _check(lib().batch_info(self._h, chain, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(r)))
+        return int(n.value), int(nnz.value), int(r.value)
+
+    def download_chain(self, chain: int):
+        _, nnz, _ = self.info(chain)
+        col = np.empty(max(nnz, 1), np.int32)
+        _check(lib().batch_download(self._h, chain, col.ctypes.data))
+        return col[:nnz]

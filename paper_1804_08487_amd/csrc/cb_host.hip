@@ -1,12 +1,19 @@
 // Host side of the C ABI declared in include/curveball.h: device buffers of
-// one chain, the launch sequence of a global trade, error reporting.
+// one graph of independent chains, the launch sequence of a global trade,
+// batched rounds captured as a hipGraph, the autotuner, the variant that
+// works in the library's static device scratch, error reporting.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <functional>
+#include <cmath>
+#include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "curveball.h"
@@ -16,19 +23,24 @@ using namespace cbx;
 
 namespace {
 
-thread_local std::string g_last_error;
+// Last error message of this thread (a fixed buffer: reporting allocates nothing).
+thread_local char g_last_error[512] = {0};
 cb_allocator g_allocator = {nullptr, nullptr, nullptr};
 
-cb_status fail(cb_status s, const std::string& msg) {
-  g_last_error = msg;
+cb_status fail(cb_status s, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+  va_end(ap);
   return s;
 }
 
-bool hip_ok(hipError_t e, std::string* msg, const char* what) {
+bool hip_ok(hipError_t e, char* msg, size_t cap, const char* what) {
   if (e == hipSuccess) return true;
-  *msg = std::string(what) + ": " + hipGetErrorString(e);
+  snprintf(msg, cap, "%s: %s", what, hipGetErrorString(e));
   return false;
 }
+#define HIP_OK(expr, what) hip_ok((expr), msg, sizeof(msg), (what))
 
 int bitlen(uint64_t x) { return x ? 64 - __builtin_clzll(x) : 0; }
 
@@ -38,6 +50,10 @@ struct EventSet {
   hipEvent_t ev[kTimedSteps + 1];
 };
 
+// Matching buckets of a chain of n nodes: a power of two, about 256-511
+// nodes each.
+int32_t chain_buckets(int64_t n) { return 1 << std::max(0, bitlen((uint64_t)std::max<int64_t>(n, 1)) - 1 - 8); }
+
 }  // namespace
 
 struct cb_graph {
@@ -46,8 +62,23 @@ struct cb_graph {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  bool static_storage = false;  // buffers carved from the library's static scratch
   cb_allocator alloc{};
   std::vector<void*> owned;
+
+  // chains (one for graph_upload)
+  int32_t chains = 1;
+  std::vector<int64_t> h_node_base, h_nnz_base;   // chains + 1 (batches only)
+  std::vector<uint64_t> h_seed;                   // batches only
+  std::vector<uint32_t> h_round;                  // next round of each chain (batches only)
+  int64_t* ch_node_base = nullptr;
+  int64_t* ch_trade_base = nullptr;
+  int32_t* ch_bucket_base = nullptr;
+  int32_t* ch_left_base = nullptr;
+  uint64_t* ch_seed = nullptr;
+  uint32_t* ch_round = nullptr;
+  uint32_t* ch_draw_base = nullptr;
+  uint32_t* ch_round_saved = nullptr;   // autotuner: rounds before the trial rounds
 
   int64_t* rp = nullptr;
   int32_t* col = nullptr;
@@ -81,18 +112,17 @@ struct cb_graph {
   int32_t* bcur = nullptr;
   int32_t* ctrl = nullptr;
   unsigned long long* stats = nullptr;
+  unsigned long long* row_cur = nullptr;
   uint64_t* slots = nullptr;
   int32_t* sbpre = nullptr;
   int64_t sbpre_stride = 1;
-  int32_t* rows_small = nullptr;
-  int32_t* rows_mid = nullptr;
-  int32_t* rows_big = nullptr;
+  int32_t* rows = nullptr;      // rebuild size classes: small, then mid, then big rows
   int64_t n_small = 0, n_mid = 0, n_big = 0;
 
-  int nb_log2 = 0;
-  int32_t nb = 1;
+  int32_t nb = 1;               // matching buckets of all chains
   int keybits_node = 1, keybits_entry = 1;
   int64_t smax = 1;
+  int64_t max_deg = 0;
   int64_t slot_elems = 0;
   int cu_count = 1;
   int occupancy_blocks = 1;
@@ -107,13 +137,22 @@ struct cb_graph {
   int32_t stack_cap = 8;
   int32_t help_min = kHelpMinItems;
   int32_t help_groups = 2;
+  int32_t help_chunk = kHelpChunk;
   int64_t watchdog_ms = 20000;
   bool timing = false;
   bool debug_checks = false;
   bool tracing = false;
+  uint64_t opt_version = 0;  // bumped by every option change (captured rounds bake options in)
+
+  // batched rounds captured as a graph
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  uint32_t exec_rounds = 0;
+  uint64_t exec_version = 0;
 
   bool poisoned = false;
-  std::string poison_msg;
+  char poison_msg[384] = {0};
 
   std::vector<EventSet> pending, spare;
   double ms_acc[kTimedSteps] = {0, 0, 0, 0};
@@ -135,7 +174,23 @@ void* dev_alloc(cb_graph* g, size_t bytes) {
   return p;
 }
 
+void dev_free_one(cb_graph* g, void* p) {
+  if (!p) return;
+  for (auto it = g->owned.begin(); it != g->owned.end(); ++it)
+    if (*it == p) { g->owned.erase(it); break; }
+  if (g->alloc.free) g->alloc.free(p, g->alloc.user); else (void)hipFree(p);
+}
+
+void drop_exec(cb_graph* g) {
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  g->exec = nullptr;
+  g->graph = nullptr;
+  g->exec_rounds = 0;
+}
+
 void release_all(cb_graph* g) {
+  drop_exec(g);
   for (void* p : g->owned) {
     if (g->alloc.free) g->alloc.free(p, g->alloc.user);
     else (void)hipFree(p);
@@ -147,6 +202,8 @@ void release_all(cb_graph* g) {
     for (auto& e : s.ev) (void)hipEventDestroy(e);
   g->pending.clear();
   g->spare.clear();
+  if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
+  g->cap_stream = nullptr;
   if (g->own_stream && g->stream) (void)hipStreamDestroy(g->stream);
   g->stream = nullptr;
 }
@@ -164,8 +221,99 @@ int grid_for(int64_t items, int per_block, int cap) {
   return (int)b;
 }
 
-std::string error_bits_text(int32_t bits) {
-  std::string s;
+// The device buffers of a graph, sized from its fields: one list for the
+// allocating paths and for carving the static scratch.
+constexpr int kMaxBufs = 48;
+struct BufPlan {
+  void** ptr[kMaxBufs];
+  size_t bytes[kMaxBufs];
+  int count = 0;
+  template <typename T>
+  void add(T** p, int64_t elems) {
+    ptr[count] = reinterpret_cast<void**>(p);
+    bytes[count] = (size_t)std::max<int64_t>(elems, 1) * sizeof(T);
+    ++count;
+  }
+};
+
+void plan_buffers(cb_graph* g, BufPlan& P, bool with_col = true) {
+  const int64_t n = g->n, nnz = g->nnz, L1 = std::max<int64_t>(g->L, 1), C = g->chains;
+  P.add(&g->rp, n + 1);
+  if (with_col) P.add(&g->col, nnz);
+  P.add(&g->col_t, nnz);
+  P.add(&g->col_out, nnz);
+  P.add(&g->inbox, nnz);
+  P.add(&g->inbox_cur, n);
+  P.add(&g->out_cur, n);
+  P.add(&g->own_cur, n);
+  P.add(&g->perm, n);
+  P.add(&g->trade_of, n);
+  P.add(&g->tinfo, n);
+  P.add(&g->giant_id, n);
+  P.add(&g->mtmp, n);
+  P.add(&g->mkey, n);
+  P.add(&g->dep, g->L);
+  P.add(&g->src_list, g->L);
+  P.add(&g->tsz, g->L);
+  P.add(&g->jobs, 2 * kMaxJobs);
+  P.add(&g->qs, (int64_t)kQsShards * L1);
+  P.add(&g->qb, (int64_t)kQbShards * L1);
+  P.add(&g->bcount, g->nb);
+  P.add(&g->bstart, g->nb + 1);
+  P.add(&g->bcur, g->nb);
+  P.add(&g->ctrl, kCtrlInts);
+  P.add(&g->stats, kStatCount);
+  P.add(&g->row_cur, 4);
+  P.add(&g->slots, (int64_t)g->nbig_alloc * g->slot_elems);
+  P.add(&g->sbpre, (int64_t)g->nbig_alloc * g->sbpre_stride);
+  P.add(&g->rows, n);
+  P.add(&g->ch_node_base, C + 1);
+  P.add(&g->ch_trade_base, C + 1);
+  P.add(&g->ch_bucket_base, C + 1);
+  P.add(&g->ch_left_base, C + 1);
+  P.add(&g->ch_seed, C);
+  P.add(&g->ch_round, C);
+  P.add(&g->ch_draw_base, C);
+  P.add(&g->ch_round_saved, C);
+}
+
+size_t plan_bytes(const BufPlan& P) {
+  size_t total = 0;
+  for (int i = 0; i < P.count; ++i) total += (P.bytes[i] + 255) & ~(size_t)255;
+  return total;
+}
+
+bool alloc_plan(cb_graph* g, const BufPlan& P) {
+  for (int i = 0; i < P.count; ++i) {
+    *P.ptr[i] = dev_alloc(g, P.bytes[i]);
+    if (!*P.ptr[i]) return false;
+  }
+  return true;
+}
+
+void carve_plan(const BufPlan& P, char* base) {
+  size_t off = 0;
+  for (int i = 0; i < P.count; ++i) {
+    *P.ptr[i] = base + off;
+    off += (P.bytes[i] + 255) & ~(size_t)255;
+  }
+}
+
+Chains chains_of(const cb_graph* g) {
+  Chains c;
+  c.count = g->chains;
+  c.node_base = g->ch_node_base;
+  c.trade_base = g->ch_trade_base;
+  c.bucket_base = g->ch_bucket_base;
+  c.left_base = g->ch_left_base;
+  c.seed = g->ch_seed;
+  c.round = g->ch_round;
+  c.draw_base = g->ch_draw_base;
+  return c;
+}
+
+const char* error_bits_text(int32_t bits, char* buf, size_t cap) {
+  buf[0] = 0;
   const struct { int32_t bit; const char* name; } names[] = {
       {kErrWatchdog, "watchdog: trade kernel made no progress"},
       {kErrInbox, "inbox overflow"},
@@ -177,8 +325,11 @@ std::string error_bits_text(int32_t bits) {
       {kErrInvalid, "graph is not a simple symmetric sorted CSR"},
       {kErrMatch, "matching bucket overflow"}};
   for (auto& nm : names)
-    if (bits & nm.bit) { if (!s.empty()) s += "; "; s += nm.name; }
-  return s;
+    if (bits & nm.bit) {
+      const size_t len = strlen(buf);
+      snprintf(buf + len, cap - len, "%s%s", len ? "; " : "", nm.name);
+    }
+  return buf;
 }
 
 // Drain finished timing event sets into the per-step sums.
@@ -194,31 +345,29 @@ void collect_timing(cb_graph* g) {
   g->pending.clear();
 }
 
+cb_status poison(cb_graph* g, cb_status s, const char* m) {
+  g->poisoned = true;
+  snprintf(g->poison_msg, sizeof(g->poison_msg), "%s", m);
+  return fail(s, "%s", m);
+}
+
 cb_status sync_and_check(cb_graph* g) {
-  if (g->poisoned) return fail(CB_EPOISONED, "graph handle poisoned: " + g->poison_msg);
-  std::string msg;
-  if (!hip_ok(hipStreamSynchronize(g->stream), &msg, "hipStreamSynchronize")) {
-    g->poisoned = true;
-    g->poison_msg = msg;
-    return fail(CB_EDEVICE, msg);
-  }
+  if (g->poisoned) return fail(CB_EPOISONED, "graph handle poisoned: %s", g->poison_msg);
+  char msg[256];
+  if (!HIP_OK(hipStreamSynchronize(g->stream), "hipStreamSynchronize")) return poison(g, CB_EDEVICE, msg);
   int32_t err = 0;
-  if (!hip_ok(hipMemcpy(&err, g->ctrl + cw(kCwErr), sizeof(int32_t), hipMemcpyDeviceToHost), &msg,
-              "hipMemcpy(error word)")) {
-    g->poisoned = true;
-    g->poison_msg = msg;
-    return fail(CB_EDEVICE, msg);
-  }
+  if (!HIP_OK(hipMemcpy(&err, g->ctrl + cw(kCwErr), sizeof(int32_t), hipMemcpyDeviceToHost),
+              "hipMemcpy(error word)"))
+    return poison(g, CB_EDEVICE, msg);
   if (g->timing) collect_timing(g);
   if (err) {
     int32_t dbg[3] = {0, 0, 0};
     for (int i = 0; i < 3; ++i)
       (void)hipMemcpy(&dbg[i], g->ctrl + cw(kCwDbgBits + i), sizeof(int32_t), hipMemcpyDeviceToHost);
-    g->poisoned = true;
-    g->poison_msg = error_bits_text(err) + " (first: bits " + std::to_string(dbg[0]) + ", trade " +
-                    std::to_string(dbg[1] - 1) + ", detail " + std::to_string(dbg[2]) + ")";
-    return fail((err & kErrWatchdog) ? CB_EWATCHDOG : CB_EDEVICE,
-                "device reported: " + g->poison_msg);
+    char bits[256], text[384];
+    snprintf(text, sizeof(text), "device reported: %s (first: bits %d, trade %d, detail %d)",
+             error_bits_text(err, bits, sizeof(bits)), dbg[0], dbg[1] - 1, dbg[2]);
+    return poison(g, (err & kErrWatchdog) ? CB_EWATCHDOG : CB_EDEVICE, text);
   }
   return CB_OK;
 }
@@ -236,16 +385,11 @@ GiantSets giant_sets(const cb_graph* g) {
 // never change, so this is fixed until the next call. Bitmaps start empty
 // and are left empty by every completed round.
 cb_status setup_giants(cb_graph* g, int64_t deg, const int64_t* host_row_ptr) {
-  std::string msg;
-  if (!hip_ok(hipStreamSynchronize(g->stream), &msg, "sync")) return fail(CB_EDEVICE, msg);
-  auto drop = [&](void* p) {
-    if (!p) return;
-    for (auto it = g->owned.begin(); it != g->owned.end(); ++it)
-      if (*it == p) { g->owned.erase(it); break; }
-    if (g->alloc.free) g->alloc.free(p, g->alloc.user); else (void)hipFree(p);
-  };
-  drop(g->gbm);
-  drop(g->gsc);
+  char msg[256];
+  if (!HIP_OK(hipStreamSynchronize(g->stream), "sync")) return fail(CB_EDEVICE, "%s", msg);
+  drop_exec(g);
+  dev_free_one(g, g->gbm);
+  dev_free_one(g, g->gsc);
   g->gbm = nullptr;
   g->gsc = nullptr;
   std::vector<int32_t> gid((size_t)std::max<int64_t>(g->n, 1), -1);
@@ -256,26 +400,25 @@ cb_status setup_giants(cb_graph* g, int64_t deg, const int64_t* host_row_ptr) {
   g->ngiant = ng;
   g->giant_deg = ng ? deg : 0;
   g->gwords = ((g->n + 4095) / 4096) * 64;
-  if (!hip_ok(hipMemcpyAsync(g->giant_id, gid.data(), gid.size() * sizeof(int32_t), hipMemcpyHostToDevice, g->stream), &msg, "copy giant ids") ||
-      !hip_ok(hipStreamSynchronize(g->stream), &msg, "sync"))
-    return fail(CB_EDEVICE, msg);
+  if (!HIP_OK(hipMemcpyAsync(g->giant_id, gid.data(), gid.size() * sizeof(int32_t), hipMemcpyHostToDevice, g->stream), "copy giant ids") ||
+      !HIP_OK(hipStreamSynchronize(g->stream), "sync"))
+    return fail(CB_EDEVICE, "%s", msg);
   if (ng == 0) return CB_OK;
   if (!alloc_into(g, &g->gbm, (int64_t)ng * g->gwords) || !alloc_into(g, &g->gsc, (int64_t)ng * (g->gwords >> 6))) {
-    drop(g->gbm);
+    dev_free_one(g, g->gbm);
     g->gbm = nullptr;
     g->ngiant = 0;
     g->giant_deg = 0;
-    std::vector<int32_t> none(gid.size(), -1);
-    (void)hipMemcpyAsync(g->giant_id, none.data(), none.size() * sizeof(int32_t), hipMemcpyHostToDevice, g->stream);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(g->n, 256, 4096)), dim3(256), 0, g->stream, g->giant_id, g->n, -1);
     (void)hipStreamSynchronize(g->stream);
     return fail(CB_ENOMEM, "no device memory for giant bitmaps");
   }
   // cleared on the graph's own stream (a non-blocking stream is not ordered
   // after work on the null stream)
-  if (!hip_ok(hipMemsetAsync(g->gbm, 0, (size_t)ng * g->gwords * 8, g->stream), &msg, "clear bitmaps") ||
-      !hip_ok(hipMemsetAsync(g->gsc, 0, (size_t)ng * (g->gwords >> 6) * 4, g->stream), &msg, "clear counts") ||
-      !hip_ok(hipStreamSynchronize(g->stream), &msg, "sync"))
-    return fail(CB_EDEVICE, msg);
+  if (!HIP_OK(hipMemsetAsync(g->gbm, 0, (size_t)ng * g->gwords * 8, g->stream), "clear bitmaps") ||
+      !HIP_OK(hipMemsetAsync(g->gsc, 0, (size_t)ng * (g->gwords >> 6) * 4, g->stream), "clear counts") ||
+      !HIP_OK(hipStreamSynchronize(g->stream), "sync"))
+    return fail(CB_EDEVICE, "%s", msg);
   return CB_OK;
 }
 
@@ -295,13 +438,20 @@ int32_t effective_small_max(const cb_graph* g) {
   return g->giant_deg > 0 ? (int32_t)std::min<int64_t>(g->small_max, g->giant_deg - 1) : g->small_max;
 }
 
-cb_status enqueue_round(cb_graph* g, uint64_t seed, uint32_t round, int last_step) {
-  if (!g) return fail(CB_EINVAL, "null graph");
-  if (g->poisoned) return fail(CB_EPOISONED, "graph handle poisoned: " + g->poison_msg);
+// Enqueue the steps 1..last_step of one global trade of every chain on `st`,
+// with the seeds and rounds in the chain table; `advance` adds one to every
+// chain's round afterwards. No host synchronisation and no memset, so the
+// sequence can be captured into a graph (without timing or tracing).
+cb_status enqueue_round(cb_graph* g, hipStream_t st, int last_step, bool advance) {
+  if (g->poisoned) return fail(CB_EPOISONED, "graph handle poisoned: %s", g->poison_msg);
   if (last_step < CB_STEP_MATCHING || last_step > CB_STEP_REBUILD)
     return fail(CB_EINVAL, "last_step out of range");
-  if (g->n == 0) return CB_OK;
-  hipStream_t st = g->stream;
+  if (g->n == 0) {
+    if (advance) hipLaunchKernelGGL(k_advance_rounds, dim3(grid_for(g->chains, 256, 64)), dim3(256), 0, st,
+                                    g->ch_round, g->chains, 1u);
+    return CB_OK;
+  }
+  char msg[256];
   EventSet evs{};
   const bool timed = g->timing && last_step == CB_STEP_REBUILD;
   if (timed) {
@@ -316,11 +466,11 @@ cb_status enqueue_round(cb_graph* g, uint64_t seed, uint32_t round, int last_ste
   }
   const int64_t n = g->n;
   const int32_t L = g->L;
+  const Chains ch = chains_of(g);
   if (g->giant_dirty) {
-    std::string msg;
-    if (!hip_ok(hipMemsetAsync(g->gbm, 0, (size_t)g->ngiant * g->gwords * 8, st), &msg, "clear bitmaps") ||
-        !hip_ok(hipMemsetAsync(g->gsc, 0, (size_t)g->ngiant * (g->gwords >> 6) * 4, st), &msg, "clear counts"))
-      return fail(CB_EDEVICE, msg);
+    if (!HIP_OK(hipMemsetAsync(g->gbm, 0, (size_t)g->ngiant * g->gwords * 8, st), "clear bitmaps") ||
+        !HIP_OK(hipMemsetAsync(g->gsc, 0, (size_t)g->ngiant * (g->gwords >> 6) * 4, st), "clear counts"))
+      return fail(CB_EDEVICE, "%s", msg);
     g->giant_dirty = false;
   }
   if (last_step < CB_STEP_TRADE && g->ngiant > 0) g->giant_dirty = true;
@@ -329,14 +479,13 @@ cb_status enqueue_round(cb_graph* g, uint64_t seed, uint32_t round, int last_ste
                      dim3(256), 0, st, n, g->nb, g->inbox_cur, g->out_cur, g->own_cur, g->bcount,
                      g->bcur, g->ctrl, g->stats);
   // 1. matching
-  hipLaunchKernelGGL(k_match_count, dim3(grid_for(n, 256, 16384)), dim3(256), 0, st, n, seed, round,
-                     g->nb_log2, g->bcount, g->ctrl);
+  hipLaunchKernelGGL(k_match_count, dim3(grid_for(n, 256, 16384)), dim3(256), 0, st, n, ch, g->bcount, g->ctrl);
   hipLaunchKernelGGL(k_match_scan, dim3(1), dim3(1024), 0, st, g->nb, g->bcount, g->bstart, g->ctrl);
-  hipLaunchKernelGGL(k_match_scatter, dim3(grid_for(n, 256, 16384)), dim3(256), 0, st, n, seed,
-                     round, g->nb_log2, g->bstart, g->bcur, g->mtmp, g->ctrl);
+  hipLaunchKernelGGL(k_match_scatter, dim3(grid_for(n, 256, 16384)), dim3(256), 0, st, n, ch, g->bstart,
+                     g->bcur, g->mtmp, g->ctrl);
   hipLaunchKernelGGL(k_match_sort, dim3(std::min<int32_t>(g->nb, 1 << 20)), dim3(kMatchBlock), 0, st,
-                     n, seed, round, g->nb, g->bstart, g->mtmp, g->mkey, g->perm, g->trade_of,
-                     g->tinfo, g->giant_id, g->dep, g->ctrl);
+                     ch, g->nb, g->bstart, g->mtmp, g->mkey, g->perm, g->trade_of, g->tinfo, g->giant_id,
+                     g->dep, g->ctrl);
   if (timed) (void)hipEventRecord(evs.ev[1], st);
   if (g->debug_checks && g->ngiant > 0)
     hipLaunchKernelGGL(k_check_giants_empty, dim3(1024), dim3(256), 0, st,
@@ -373,9 +522,8 @@ cb_status enqueue_round(cb_graph* g, uint64_t seed, uint32_t round, int last_ste
     A.jobs = g->jobs;
     A.trace = g->tracing ? g->trace : nullptr;
     if (g->tracing) {
-      std::string msg;
-      if (!hip_ok(hipMemsetAsync(g->trace, 0xFF, (size_t)L * kTraceFields * sizeof(int64_t), st), &msg, "clear trace"))
-        return fail(CB_EDEVICE, msg);
+      if (!HIP_OK(hipMemsetAsync(g->trace, 0xFF, (size_t)L * kTraceFields * sizeof(int64_t), st), "clear trace"))
+        return fail(CB_EDEVICE, "%s", msg);
     }
     A.qs = g->qs;
     A.qb = g->qb;
@@ -391,12 +539,12 @@ cb_status enqueue_round(cb_graph* g, uint64_t seed, uint32_t round, int last_ste
     A.small_max = effective_small_max(g);
     A.help_min = g->help_min;
     A.help_groups = g->help_groups;
+    A.help_chunk = g->help_chunk;
     A.big_lds_max = g->big_lds_max;
     A.nbig = effective_nbig(g);
     A.stack_cap = g->stack_cap;
     A.keybits = g->keybits_entry;
-    A.round = round;
-    A.seed = seed;
+    A.ch = ch;
     A.watchdog_ticks = (uint64_t)g->watchdog_ms * g->ticks_per_ms;
     hipLaunchKernelGGL(k_trade, dim3(trade_grid(g)), dim3(kTradeBlock), 0, st, A);
   }
@@ -406,27 +554,347 @@ cb_status enqueue_round(cb_graph* g, uint64_t seed, uint32_t round, int last_ste
                        g->out_cur, g->own_cur, g->ctrl);
   if (last_step >= CB_STEP_REBUILD && g->nnz > 0) {
     // 4. rebuild: per-row ascending sort of col_out into col
+    const int32_t* rs = g->rows;
+    const int32_t* rm = g->rows + g->n_small;
+    const int32_t* rb = g->rows + g->n_small + g->n_mid;
     if (g->n_small)
       hipLaunchKernelGGL(k_segsort_small, dim3(grid_for(g->n_small, 4, 65536)), dim3(256), 0, st,
-                         g->rows_small, g->n_small, g->rp, g->col_out, g->col, g->ctrl);
+                         rs, g->n_small, g->rp, g->col_out, g->col, g->ctrl);
     if (g->n_mid)
       hipLaunchKernelGGL(k_segsort_mid, dim3(grid_for(g->n_mid, 1, 65536)), dim3(256), 0, st,
-                         g->rows_mid, g->n_mid, g->rp, g->col_out, g->col, g->keybits_node, g->ctrl);
+                         rm, g->n_mid, g->rp, g->col_out, g->col, g->keybits_node, g->ctrl);
     if (g->n_big)
       hipLaunchKernelGGL(k_segsort_big, dim3(grid_for(g->n_big, 1, 8192)), dim3(256), 0, st,
-                         g->rows_big, g->n_big, g->rp, g->col_out, g->col, g->keybits_node, g->ctrl);
+                         rb, g->n_big, g->rp, g->col_out, g->col, g->keybits_node, g->ctrl);
   }
+  if (advance)
+    hipLaunchKernelGGL(k_advance_rounds, dim3(grid_for(g->chains, 256, 64)), dim3(256), 0, st, g->ch_round,
+                       g->chains, 1u);
   if (timed) {
     (void)hipEventRecord(evs.ev[4], st);
     g->pending.push_back(evs);
   }
-  std::string msg;
-  if (!hip_ok(hipGetLastError(), &msg, "kernel launch")) {
-    g->poisoned = true;
-    g->poison_msg = msg;
-    return fail(CB_EDEVICE, msg);
+  if (!HIP_OK(hipGetLastError(), "kernel launch")) return poison(g, CB_EDEVICE, msg);
+  return CB_OK;
+}
+
+// One chain of a graph being created: n nodes, host CSR offsets rp[0..n] and
+// its adjacency (local ids) in host memory, or in device memory with every id
+// shifted by dev_shift from local.
+struct ChainSrc {
+  int64_t n;
+  const int64_t* rp;
+  const int32_t* col;
+  bool col_on_device;
+  int32_t dev_shift;
+  uint64_t seed;
+  uint32_t round;
+};
+
+// Device properties and occupancy of the trade kernel, once per device.
+struct DeviceInfo {
+  int cu_count = 1;
+  int occupancy = 1;
+  uint64_t ticks_per_ms = 100000;
+};
+constexpr int kMaxDevices = 64;
+DeviceInfo device_info(int dev) {
+  static std::mutex mu;
+  static DeviceInfo known[kMaxDevices];
+  static bool have[kMaxDevices] = {false};
+  std::lock_guard<std::mutex> lock(mu);
+  const bool cacheable = dev >= 0 && dev < kMaxDevices;
+  if (cacheable && have[dev]) return known[dev];
+  DeviceInfo d;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess) d.cu_count = prop.multiProcessorCount;
+  int rate_khz = 0;
+  if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && rate_khz > 0)
+    d.ticks_per_ms = (uint64_t)rate_khz;
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(k_trade), kTradeBlock, 0) ==
+          hipSuccess && occ > 0)
+    d.occupancy = occ;
+  if (cacheable) {
+    known[dev] = d;
+    have[dev] = true;
+  }
+  return d;
+}
+
+// Host checks of one chain's CSR (the device validation checks the rest).
+cb_status check_chain_host(const ChainSrc& c, int64_t* d1, int64_t* d2) {
+  if (c.n < 0 || c.n > INT32_MAX) return fail(CB_EINVAL, "n must be in [0, 2^31 - 1]");
+  if (!c.rp) return fail(CB_EINVAL, "row_ptr is NULL");
+  if (c.rp[0] != 0) return fail(CB_EINVAL, "row_ptr[0] must be 0");
+  for (int64_t x = 0; x < c.n; ++x) {
+    const int64_t d = c.rp[x + 1] - c.rp[x];
+    if (d < 0) return fail(CB_EINVAL, "row_ptr is not monotone");
+    if (d >= c.n && d > 0) return fail(CB_ENOTSIMPLE, "a row has more entries than other nodes");
+    if (d > *d1) { *d2 = *d1; *d1 = d; } else if (d > *d2) { *d2 = d; }
+  }
+  const int64_t nnz = c.rp[c.n];
+  if (nnz % 2) return fail(CB_ENOTSIMPLE, "odd number of entries cannot be symmetric");
+  if (nnz >= INT32_MAX) return fail(CB_EINVAL, "2m must be below 2^31");
+  if (nnz > 0 && !c.col) return fail(CB_EINVAL, "col is NULL");
+  return CB_OK;
+}
+
+// Sizes, tier limits and chain tables of a new graph (no device work).
+void size_graph(cb_graph* g, const ChainSrc* src, int32_t count, int64_t d1, int64_t d2) {
+  g->chains = count;
+  int64_t n = 0, nnz = 0, L = 0, nb = 0;
+  for (int32_t c = 0; c < count; ++c) {
+    n += src[c].n;
+    nnz += src[c].rp[src[c].n];
+    L += src[c].n / 2;
+    nb += chain_buckets(src[c].n);
+  }
+  g->n = n;
+  g->nnz = nnz;
+  g->L = (int32_t)L;
+  g->nb = (int32_t)nb;
+  g->max_deg = d1;
+  g->keybits_node = std::max(1, bitlen((uint64_t)std::max<int64_t>(n - 1, 1)));
+  g->keybits_entry = std::max(1, bitlen((uint64_t)std::max<int64_t>(2 * n - 1, 1)));
+  g->smax = std::max<int64_t>(d1 + d2, 1);
+  g->slot_elems = 3 * g->smax + g->smax / 2 + 1;
+  g->sbpre_stride = (n + 4095) / 4096 + 1;
+}
+
+// Rows per rebuild size class.
+void count_classes(cb_graph* g, const ChainSrc* src, int32_t count) {
+  g->n_small = g->n_mid = g->n_big = 0;
+  for (int32_t c = 0; c < count; ++c)
+    for (int64_t x = 0; x < src[c].n; ++x) {
+      const int64_t d = src[c].rp[x + 1] - src[c].rp[x];
+      if (d == 0) continue;
+      if (d <= kSegSmallMax) ++g->n_small;
+      else if (d <= kSegMidMax) ++g->n_mid;
+      else ++g->n_big;
+    }
+}
+
+// Device state that every new graph starts from: cleared control words, jobs
+// and queues, the rebuild's row lists, and (optionally) validation.
+bool init_device_state(cb_graph* g, bool validate, char* msg, size_t cap) {
+  hipStream_t st = g->stream;
+  const int64_t L1 = std::max<int64_t>(g->L, 1);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, st, g->ctrl, (int64_t)kCtrlInts, 0);
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for((int64_t)(2 * kMaxJobs * sizeof(HelpJob) / 4), 256, 64)), dim3(256), 0, st,
+                     reinterpret_cast<int32_t*>(g->jobs), (int64_t)(2 * kMaxJobs * sizeof(HelpJob) / 4), 0);
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for((int64_t)kQsShards * L1, 256, 8192)), dim3(256), 0, st, g->qs,
+                     (int64_t)kQsShards * L1, -1);
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for((int64_t)kQbShards * L1, 256, 8192)), dim3(256), 0, st, g->qb,
+                     (int64_t)kQbShards * L1, -1);
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(g->n, 256, 8192)), dim3(256), 0, st, g->giant_id, g->n, -1);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, reinterpret_cast<int32_t*>(g->row_cur), (int64_t)8, 0);
+  if (g->n > 0)
+    hipLaunchKernelGGL(k_classify_rows, dim3(grid_for(g->n, 256, 8192)), dim3(256), 0, st, g->n, g->rp, g->rows,
+                       g->n_small, g->n_small + g->n_mid, g->row_cur);
+  if (validate && g->nnz > 0)
+    hipLaunchKernelGGL(k_validate, dim3((unsigned)((g->nnz + kScanChunk - 1) / kScanChunk)), dim3(256), 0, st,
+                       g->n, g->nnz, g->rp, g->col, g->ctrl);
+  if (!hip_ok(hipGetLastError(), msg, cap, "init launch")) return false;
+  if (!hip_ok(hipStreamSynchronize(st), msg, cap, "upload sync")) return false;
+  unsigned long long placed[3] = {0, 0, 0};
+  if (!hip_ok(hipMemcpy(placed, g->row_cur, sizeof(placed), hipMemcpyDeviceToHost), msg, cap, "read row counts"))
+    return false;
+  if ((int64_t)placed[0] != g->n_small || (int64_t)placed[1] != g->n_mid || (int64_t)placed[2] != g->n_big) {
+    snprintf(msg, cap, "row classes differ from the host's count");
+    return false;
+  }
+  return true;
+}
+
+// Read the error word after upload validation: CB_OK or CB_ENOTSIMPLE.
+cb_status upload_verdict(cb_graph* g) {
+  int32_t err = 0;
+  char msg[256];
+  if (!HIP_OK(hipMemcpy(&err, g->ctrl + cw(kCwErr), sizeof(int32_t), hipMemcpyDeviceToHost), "read error word"))
+    return fail(CB_EDEVICE, "%s", msg);
+  if (err) {
+    char bits[256];
+    return fail(CB_ENOTSIMPLE, "upload validation: %s", error_bits_text(err, bits, sizeof(bits)));
   }
   return CB_OK;
+}
+
+// Default giant threshold: max(6144, n / 2048) for one chain; reading a
+// giant's set back costs n / 8 bytes of bitmap whatever its degree, sorting a
+// list costs in proportion to the degree; measured on MI355X a round at
+// n = 2^24 is fastest near degree n / 2048 (8192; 2% faster than 16384, 12%
+// faster than 24576), and 6144 keeps every pair below it within one
+// workgroup's LDS (at n = 2^22, 4096 was 1% slower than 6144). It rises
+// further if the bitmaps would take too much memory. Batches of chains start
+// without giant nodes (their bitmaps would span every chain's ids).
+int64_t default_giant_threshold(const cb_graph* g, const int64_t* rp) {
+  if (g->chains != 1) return 0;
+  const int64_t n = g->n;
+  const int64_t min_deg = std::max<int64_t>(kGiantMinDeg, n / 2048);
+  size_t free_b = 0, total_b = 0;
+  (void)hipMemGetInfo(&free_b, &total_b);
+  const double budget = std::min(64.0 * (1ull << 30), 0.4 * (double)free_b);
+  const int64_t gwords = ((n + 4095) / 4096) * 64;
+  const double per_giant = (double)gwords * 8.0 + (double)(gwords >> 6) * 4.0;
+  std::vector<int64_t> degs;
+  for (int64_t x = 0; x < n; ++x) {
+    const int64_t d = rp[x + 1] - rp[x];
+    if (d >= min_deg) degs.push_back(d);
+  }
+  std::sort(degs.begin(), degs.end(), std::greater<int64_t>());
+  const int64_t fit = (int64_t)(budget / per_giant);
+  int64_t thr = min_deg;
+  if ((int64_t)degs.size() > fit) thr = fit > 0 ? degs[(size_t)fit - 1] + 1 : INT64_MAX;
+  if (thr == INT64_MAX || degs.empty()) thr = 0;
+  return thr;
+}
+
+// Create a graph of `count` chains in allocated device memory.
+cb_status create_graph(const ChainSrc* src, int32_t count, void* stream, uint32_t flags, cb_graph** out) {
+  if (!out) return fail(CB_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (count < 1) return fail(CB_EINVAL, "a graph needs at least one chain");
+  int64_t d1 = 0, d2 = 0, n_total = 0, nnz_total = 0;
+  for (int32_t c = 0; c < count; ++c) {
+    cb_status s = check_chain_host(src[c], &d1, &d2);
+    if (s != CB_OK) return s;
+    n_total += src[c].n;
+    nnz_total += src[c].rp[src[c].n];
+  }
+  if (n_total > INT32_MAX) return fail(CB_EINVAL, "the chains hold more than 2^31 - 1 nodes");
+  if (nnz_total >= INT32_MAX) return fail(CB_EINVAL, "the chains hold 2^31 or more entries");
+  if (n_total / 2 > INT32_MAX / 2) return fail(CB_EINVAL, "too many trades");
+  // ids of every chain within its own range (batches; one chain is checked on the device)
+  if (count > 1)
+    for (int32_t c = 0; c < count; ++c) {
+      if (src[c].col_on_device) continue;
+      const int64_t e = src[c].rp[src[c].n];
+      for (int64_t i = 0; i < e; ++i)
+        if (src[c].col[i] < 0 || src[c].col[i] >= src[c].n)
+          return fail(CB_ENOTSIMPLE, "chain %d: a neighbour id is outside [0, n)", (int)c);
+    }
+
+  cb_graph* g = new cb_graph();
+  g->alloc = g_allocator;
+  char msg[256];
+  if (!HIP_OK(hipGetDevice(&g->device), "hipGetDevice")) { delete g; return fail(CB_EDEVICE, "%s", msg); }
+  if (stream) {
+    g->stream = (hipStream_t)stream;
+  } else {
+    if (!HIP_OK(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking), "hipStreamCreate")) {
+      delete g;
+      return fail(CB_EDEVICE, "%s", msg);
+    }
+    g->own_stream = true;
+  }
+  const DeviceInfo di = device_info(g->device);
+  g->cu_count = di.cu_count;
+  g->occupancy_blocks = di.occupancy;
+  g->ticks_per_ms = di.ticks_per_ms;
+  g->nbig_alloc = std::max(1, g->cu_count / 2);
+  size_graph(g, src, count, d1, d2);
+  count_classes(g, src, count);
+
+  // chain tables and the union's offsets on the host
+  std::vector<int64_t> node_base(count + 1), trade_base(count + 1), nnz_base(count + 1);
+  std::vector<int32_t> bucket_base(count + 1), left_base(count + 1);
+  std::vector<uint64_t> seeds(count);
+  std::vector<uint32_t> rounds(count), draw(count, 0);
+  for (int32_t c = 0; c < count; ++c) {
+    node_base[c + 1] = node_base[c] + src[c].n;
+    trade_base[c + 1] = trade_base[c] + src[c].n / 2;
+    nnz_base[c + 1] = nnz_base[c] + src[c].rp[src[c].n];
+    bucket_base[c + 1] = bucket_base[c] + chain_buckets(src[c].n);
+    left_base[c + 1] = left_base[c] + (int32_t)(src[c].n & 1);
+    seeds[c] = src[c].seed;
+    rounds[c] = src[c].round;
+  }
+  BufPlan P;
+  plan_buffers(g, P);
+  if (!alloc_plan(g, P)) {
+    release_all(g);
+    delete g;
+    return fail(CB_ENOMEM, "device allocation failed");
+  }
+  hipStream_t st = g->stream;
+  bool ok = true;
+  std::vector<int64_t> urp;   // the union's offsets (batches)
+  const int64_t* rp_host = src[0].rp;
+  if (count > 1) {
+    urp.resize((size_t)g->n + 1);
+    for (int32_t c = 0; c < count; ++c)
+      for (int64_t x = 0; x <= src[c].n; ++x) urp[(size_t)(node_base[c] + x)] = nnz_base[c] + src[c].rp[x];
+    rp_host = urp.data();
+  }
+  ok = HIP_OK(hipMemcpyAsync(g->rp, rp_host, (size_t)(g->n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st), "copy row_ptr");
+  for (int32_t c = 0; ok && c < count; ++c) {
+    const int64_t e = src[c].rp[src[c].n];
+    if (e == 0) continue;
+    int32_t* dst = g->col + nnz_base[c];
+    if (src[c].col_on_device) {
+      hipLaunchKernelGGL(k_copy_shift, dim3(grid_for(e, 256, 8192)), dim3(256), 0, st, dst, src[c].col, e,
+                         (int32_t)(node_base[c] - src[c].dev_shift));
+    } else {
+      ok = HIP_OK(hipMemcpyAsync(dst, src[c].col, (size_t)e * sizeof(int32_t), hipMemcpyHostToDevice, st), "copy col");
+      if (ok && node_base[c] != 0)
+        hipLaunchKernelGGL(k_copy_shift, dim3(grid_for(e, 256, 8192)), dim3(256), 0, st, dst, dst, e,
+                           (int32_t)node_base[c]);
+    }
+  }
+  ok = ok &&
+       HIP_OK(hipMemcpyAsync(g->ch_node_base, node_base.data(), node_base.size() * 8, hipMemcpyHostToDevice, st), "copy chains") &&
+       HIP_OK(hipMemcpyAsync(g->ch_trade_base, trade_base.data(), trade_base.size() * 8, hipMemcpyHostToDevice, st), "copy chains") &&
+       HIP_OK(hipMemcpyAsync(g->ch_bucket_base, bucket_base.data(), bucket_base.size() * 4, hipMemcpyHostToDevice, st), "copy chains") &&
+       HIP_OK(hipMemcpyAsync(g->ch_left_base, left_base.data(), left_base.size() * 4, hipMemcpyHostToDevice, st), "copy chains") &&
+       HIP_OK(hipMemcpyAsync(g->ch_seed, seeds.data(), seeds.size() * 8, hipMemcpyHostToDevice, st), "copy chains") &&
+       HIP_OK(hipMemcpyAsync(g->ch_round, rounds.data(), rounds.size() * 4, hipMemcpyHostToDevice, st), "copy chains") &&
+       HIP_OK(hipMemcpyAsync(g->ch_draw_base, draw.data(), draw.size() * 4, hipMemcpyHostToDevice, st), "copy chains");
+  if (ok) ok = init_device_state(g, (flags & CB_VALIDATE) != 0, msg, sizeof(msg));
+  if (!ok) {
+    release_all(g);
+    delete g;
+    return fail(CB_EDEVICE, "%s", msg);
+  }
+  cb_status s = upload_verdict(g);
+  if (s == CB_OK) s = setup_giants(g, default_giant_threshold(g, rp_host), rp_host);
+  if (s != CB_OK) {
+    release_all(g);
+    delete g;
+    return s;
+  }
+  if (count > 1) {
+    g->h_node_base = node_base;
+    g->h_nnz_base = nnz_base;
+    g->h_seed = seeds;
+    g->h_round = rounds;
+  }
+  *out = g;
+  return CB_OK;
+}
+
+// ---------------------------------------------------------------- autotuner
+
+struct TuneKey {
+  int chains_lg, n_lg, nnz_lg, deg_lg;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(chains_lg, n_lg, nnz_lg, deg_lg) < std::tie(o.chains_lg, o.n_lg, o.nnz_lg, o.deg_lg);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, cb_tune_result> g_tune_cache;
+
+TuneKey tune_key(const cb_graph* g) {
+  return TuneKey{bitlen((uint64_t)g->chains), bitlen((uint64_t)g->n), bitlen((uint64_t)g->nnz),
+                 bitlen((uint64_t)g->max_deg)};
+}
+
+void apply_tuned(cb_graph* g, const cb_tune_result& r) {
+  g->small_max = r.small_max;
+  g->help_min = r.help_min;
+  g->help_chunk = r.help_chunk;
+  g->nbig = r.big_workers;
+  g->opt_version++;
 }
 
 }  // namespace
@@ -439,158 +907,14 @@ cb_status cb_set_allocator(const cb_allocator* a) {
   return CB_OK;
 }
 
-const char* cb_last_error(void) { return g_last_error.c_str(); }
+const char* cb_last_error(void) { return g_last_error; }
 
 cb_status graph_upload(int64_t n, const int64_t* row_ptr, const int32_t* col, void* stream,
                        uint32_t flags, cb_graph** out) {
   if (!out) return fail(CB_EINVAL, "out is NULL");
-  *out = nullptr;
   if (n < 0 || n > INT32_MAX) return fail(CB_EINVAL, "n must be in [0, 2^31 - 1]");
-  if (!row_ptr) return fail(CB_EINVAL, "row_ptr is NULL");
-  if (row_ptr[0] != 0) return fail(CB_EINVAL, "row_ptr[0] must be 0");
-  int64_t d1 = 0, d2 = 0;
-  for (int64_t x = 0; x < n; ++x) {
-    const int64_t d = row_ptr[x + 1] - row_ptr[x];
-    if (d < 0) return fail(CB_EINVAL, "row_ptr is not monotone");
-    if (d >= n && d > 0) return fail(CB_ENOTSIMPLE, "a row has more entries than other nodes");
-    if (d > d1) { d2 = d1; d1 = d; } else if (d > d2) { d2 = d; }
-  }
-  const int64_t nnz = row_ptr[n];
-  if (nnz % 2) return fail(CB_ENOTSIMPLE, "odd number of entries cannot be symmetric");
-  if (nnz >= INT32_MAX) return fail(CB_EINVAL, "2m must be below 2^31");
-  if (nnz > 0 && !col) return fail(CB_EINVAL, "col is NULL");
-
-  cb_graph* g = new cb_graph();
-  g->alloc = g_allocator;
-  g->n = n;
-  g->nnz = nnz;
-  g->L = (int32_t)(n / 2);
-  std::string msg;
-  if (!hip_ok(hipGetDevice(&g->device), &msg, "hipGetDevice")) { delete g; return fail(CB_EDEVICE, msg); }
-  if (stream) {
-    g->stream = (hipStream_t)stream;
-  } else {
-    if (!hip_ok(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking), &msg, "hipStreamCreate")) {
-      delete g;
-      return fail(CB_EDEVICE, msg);
-    }
-    g->own_stream = true;
-  }
-  hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, g->device) == hipSuccess) g->cu_count = prop.multiProcessorCount;
-  int rate_khz = 0;
-  if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, g->device) == hipSuccess &&
-      rate_khz > 0)
-    g->ticks_per_ms = (uint64_t)rate_khz;
-  int occ = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(k_trade),
-                                                   kTradeBlock, 0) == hipSuccess && occ > 0)
-    g->occupancy_blocks = occ;
-
-  g->nb_log2 = std::max(0, bitlen((uint64_t)std::max<int64_t>(n, 1)) - 1 - 8);
-  g->nb = 1 << g->nb_log2;
-  g->keybits_node = std::max(1, bitlen((uint64_t)std::max<int64_t>(n - 1, 1)));
-  g->keybits_entry = std::max(1, bitlen((uint64_t)std::max<int64_t>(2 * n - 1, 1)));
-  g->smax = std::max<int64_t>(d1 + d2, 1);
-  g->slot_elems = 3 * g->smax + g->smax / 2 + 1;
-  g->sbpre_stride = (n + 4095) / 4096 + 1;
-  g->nbig_alloc = std::max(1, g->cu_count / 2);
-
-  // size classes of the per-row rebuild (degrees never change)
-  std::vector<int32_t> rs, rm, rb;
-  for (int64_t x = 0; x < n; ++x) {
-    const int64_t d = row_ptr[x + 1] - row_ptr[x];
-    if (d == 0) continue;
-    if (d <= kSegSmallMax) rs.push_back((int32_t)x);
-    else if (d <= kSegMidMax) rm.push_back((int32_t)x);
-    else rb.push_back((int32_t)x);
-  }
-  g->n_small = (int64_t)rs.size();
-  g->n_mid = (int64_t)rm.size();
-  g->n_big = (int64_t)rb.size();
-
-  bool ok = alloc_into(g, &g->rp, n + 1) && alloc_into(g, &g->col, nnz) &&
-            alloc_into(g, &g->col_t, nnz) && alloc_into(g, &g->col_out, nnz) &&
-            alloc_into(g, &g->inbox, nnz) && alloc_into(g, &g->inbox_cur, n) &&
-            alloc_into(g, &g->out_cur, n) && alloc_into(g, &g->own_cur, n) && alloc_into(g, &g->perm, n) &&
-            alloc_into(g, &g->trade_of, n) && alloc_into(g, &g->tinfo, n) &&
-            alloc_into(g, &g->giant_id, n) && alloc_into(g, &g->mtmp, n) &&
-            alloc_into(g, &g->mkey, n) && alloc_into(g, &g->dep, g->L) &&
-            alloc_into(g, &g->src_list, g->L) && alloc_into(g, &g->tsz, g->L) &&
-            alloc_into(g, &g->jobs, 2 * kMaxJobs) && alloc_into(g, &g->qs, (int64_t)kQsShards * std::max<int64_t>(g->L, 1)) &&
-            alloc_into(g, &g->qb, (int64_t)kQbShards * std::max<int64_t>(g->L, 1)) && alloc_into(g, &g->bcount, g->nb) &&
-            alloc_into(g, &g->bstart, g->nb + 1) && alloc_into(g, &g->bcur, g->nb) &&
-            alloc_into(g, &g->ctrl, kCtrlInts) && alloc_into(g, &g->stats, kStatCount) &&
-            alloc_into(g, &g->slots, (int64_t)g->nbig_alloc * g->slot_elems) &&
-            alloc_into(g, &g->sbpre, (int64_t)g->nbig_alloc * g->sbpre_stride) &&
-            alloc_into(g, &g->rows_small, g->n_small) && alloc_into(g, &g->rows_mid, g->n_mid) &&
-            alloc_into(g, &g->rows_big, g->n_big);
-  if (!ok) {
-    release_all(g);
-    delete g;
-    return fail(CB_ENOMEM, "device allocation failed");
-  }
-  hipStream_t st = g->stream;
-  ok = hip_ok(hipMemcpyAsync(g->rp, row_ptr, (size_t)(n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st), &msg, "copy row_ptr") &&
-       (nnz == 0 || hip_ok(hipMemcpyAsync(g->col, col, (size_t)nnz * sizeof(int32_t), hipMemcpyHostToDevice, st), &msg, "copy col")) &&
-       (rs.empty() || hip_ok(hipMemcpyAsync(g->rows_small, rs.data(), rs.size() * sizeof(int32_t), hipMemcpyHostToDevice, st), &msg, "copy rows")) &&
-       (rm.empty() || hip_ok(hipMemcpyAsync(g->rows_mid, rm.data(), rm.size() * sizeof(int32_t), hipMemcpyHostToDevice, st), &msg, "copy rows")) &&
-       (rb.empty() || hip_ok(hipMemcpyAsync(g->rows_big, rb.data(), rb.size() * sizeof(int32_t), hipMemcpyHostToDevice, st), &msg, "copy rows")) &&
-       hip_ok(hipMemsetAsync(g->ctrl, 0, kCtrlInts * sizeof(int32_t), st), &msg, "clear ctrl") &&
-       hip_ok(hipMemsetAsync(g->jobs, 0, 2 * kMaxJobs * sizeof(HelpJob), st), &msg, "clear jobs") &&
-       hip_ok(hipMemsetAsync(g->qs, 0xFF, (size_t)kQsShards * std::max<int64_t>(g->L, 1) * sizeof(int32_t), st), &msg, "clear queues") &&
-       hip_ok(hipMemsetAsync(g->qb, 0xFF, (size_t)kQbShards * std::max<int64_t>(g->L, 1) * sizeof(int32_t), st), &msg, "clear queues");
-  if (ok && (flags & CB_VALIDATE) && nnz > 0) {
-    hipLaunchKernelGGL(k_validate, dim3((unsigned)((nnz + kScanChunk - 1) / kScanChunk)), dim3(256), 0, st,
-                       n, nnz, g->rp, g->col, g->ctrl);
-    ok = hip_ok(hipGetLastError(), &msg, "k_validate launch");
-  }
-  if (ok) ok = hip_ok(hipStreamSynchronize(st), &msg, "upload sync");
-  int32_t err = 0;
-  if (ok) ok = hip_ok(hipMemcpy(&err, g->ctrl + cw(kCwErr), sizeof(int32_t), hipMemcpyDeviceToHost), &msg, "read error word");
-  if (!ok) {
-    release_all(g);
-    delete g;
-    return fail(CB_EDEVICE, msg);
-  }
-  if (err) {
-    release_all(g);
-    delete g;
-    return fail(CB_ENOTSIMPLE, "upload validation: " + error_bits_text(err));
-  }
-  // giant nodes: the default threshold is max(6144, n / 2048). Reading a
-  // giant's set back costs n / 8 bytes of bitmap whatever its degree, sorting
-  // a list costs in proportion to the degree; measured on MI355X a round at
-  // n = 2^24 is fastest near degree n / 2048 (8192; 2% faster than 16384,
-  // 12% faster than 24576), and 6144 keeps every pair below it within one
-  // workgroup's LDS (at n = 2^22, 4096 was 1% slower than 6144). It rises
-  // further if the bitmaps would take too much memory.
-  {
-    const int64_t min_deg = std::max<int64_t>(kGiantMinDeg, n / 2048);
-    size_t free_b = 0, total_b = 0;
-    (void)hipMemGetInfo(&free_b, &total_b);
-    const double budget = std::min(64.0 * (1ull << 30), 0.4 * (double)free_b);
-    const int64_t gwords = ((n + 4095) / 4096) * 64;
-    const double per_giant = (double)gwords * 8.0 + (double)(gwords >> 6) * 4.0;
-    std::vector<int64_t> degs;
-    for (int64_t x = 0; x < n; ++x) {
-      const int64_t d = row_ptr[x + 1] - row_ptr[x];
-      if (d >= min_deg) degs.push_back(d);
-    }
-    std::sort(degs.begin(), degs.end(), std::greater<int64_t>());
-    const int64_t fit = (int64_t)(budget / per_giant);
-    int64_t thr = min_deg;
-    if ((int64_t)degs.size() > fit) thr = fit > 0 ? degs[(size_t)fit - 1] + 1 : INT64_MAX;
-    if (thr == INT64_MAX || degs.empty()) thr = 0;
-    cb_status gs = setup_giants(g, thr, row_ptr);
-    if (gs != CB_OK) {
-      release_all(g);
-      delete g;
-      return gs;
-    }
-  }
-  *out = g;
-  return CB_OK;
+  ChainSrc c{n, row_ptr, col, false, 0, 0, 0};
+  return create_graph(&c, 1, stream, flags, out);
 }
 
 cb_status graph_info(const cb_graph* g, int64_t* n, int64_t* nnz) {
@@ -601,11 +925,19 @@ cb_status graph_info(const cb_graph* g, int64_t* n, int64_t* nnz) {
 }
 
 cb_status global_trade(cb_graph* g, uint64_t seed, uint32_t round) {
-  return enqueue_round(g, seed, round, CB_STEP_REBUILD);
+  if (!g) return fail(CB_EINVAL, "null graph");
+  if (g->chains != 1) return fail(CB_EINVAL, "global_trade needs a single-chain graph (use batch_run)");
+  if (g->poisoned) return fail(CB_EPOISONED, "graph handle poisoned: %s", g->poison_msg);
+  hipLaunchKernelGGL(k_set_chain, dim3(1), dim3(64), 0, g->stream, g->ch_seed, g->ch_round, 0, seed, round);
+  return enqueue_round(g, g->stream, CB_STEP_REBUILD, false);
 }
 
 cb_status global_trade_steps(cb_graph* g, uint64_t seed, uint32_t round, int32_t last_step) {
-  return enqueue_round(g, seed, round, last_step);
+  if (!g) return fail(CB_EINVAL, "null graph");
+  if (g->chains != 1) return fail(CB_EINVAL, "global_trade_steps needs a single-chain graph");
+  if (g->poisoned) return fail(CB_EPOISONED, "graph handle poisoned: %s", g->poison_msg);
+  hipLaunchKernelGGL(k_set_chain, dim3(1), dim3(64), 0, g->stream, g->ch_seed, g->ch_round, 0, seed, round);
+  return enqueue_round(g, g->stream, last_step, false);
 }
 
 cb_status graph_sync(cb_graph* g) {
@@ -615,14 +947,15 @@ cb_status graph_sync(cb_graph* g) {
 
 cb_status graph_download(cb_graph* g, int64_t* row_ptr, int32_t* col) {
   if (!g) return fail(CB_EINVAL, "null graph");
+  if (g->chains != 1) return fail(CB_EINVAL, "graph_download needs a single-chain graph (use batch_download)");
   if (g->nnz > 0 && !col) return fail(CB_EINVAL, "col is NULL");
   cb_status s = sync_and_check(g);
   if (s != CB_OK) return s;
-  std::string msg;
-  if (row_ptr && !hip_ok(hipMemcpy(row_ptr, g->rp, (size_t)(g->n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost), &msg, "download row_ptr"))
-    return fail(CB_EDEVICE, msg);
-  if (g->nnz > 0 && !hip_ok(hipMemcpy(col, g->col, (size_t)g->nnz * sizeof(int32_t), hipMemcpyDeviceToHost), &msg, "download col"))
-    return fail(CB_EDEVICE, msg);
+  char msg[256];
+  if (row_ptr && !HIP_OK(hipMemcpy(row_ptr, g->rp, (size_t)(g->n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost), "download row_ptr"))
+    return fail(CB_EDEVICE, "%s", msg);
+  if (g->nnz > 0 && !HIP_OK(hipMemcpy(col, g->col, (size_t)g->nnz * sizeof(int32_t), hipMemcpyDeviceToHost), "download col"))
+    return fail(CB_EDEVICE, "%s", msg);
   return CB_OK;
 }
 
@@ -647,15 +980,16 @@ cb_status graph_download_state(cb_graph* g, int32_t which, void* host, int64_t c
     default: return fail(CB_EINVAL, "unknown state id");
   }
   if (count > avail) return fail(CB_EINVAL, "count exceeds the state size");
-  std::string msg;
-  if (!hip_ok(hipStreamSynchronize(g->stream), &msg, "hipStreamSynchronize")) return fail(CB_EDEVICE, msg);
-  if (count > 0 && !hip_ok(hipMemcpy(host, src, (size_t)count * elem, hipMemcpyDeviceToHost), &msg, "download state"))
-    return fail(CB_EDEVICE, msg);
+  char msg[256];
+  if (!HIP_OK(hipStreamSynchronize(g->stream), "hipStreamSynchronize")) return fail(CB_EDEVICE, "%s", msg);
+  if (count > 0 && !HIP_OK(hipMemcpy(host, src, (size_t)count * elem, hipMemcpyDeviceToHost), "download state"))
+    return fail(CB_EDEVICE, "%s", msg);
   return CB_OK;
 }
 
 cb_status graph_set_option(cb_graph* g, int32_t option, int64_t value) {
   if (!g) return fail(CB_EINVAL, "null graph");
+  g->opt_version++;
   switch (option) {
     case CB_OPT_SMALL_MAX:
       if (value < 0 || value > kSmallCap) return fail(CB_EINVAL, "small_max must be in [0, 512]");
@@ -680,6 +1014,7 @@ cb_status graph_set_option(cb_graph* g, int32_t option, int64_t value) {
       g->debug_checks = value != 0;
       return CB_OK;
     case CB_OPT_TRACE:
+      if (g->static_storage && value != 0) return fail(CB_EINVAL, "no tracing in static storage");
       if (value != 0 && !g->trace && !alloc_into(g, &g->trace, kTraceFields * (int64_t)g->L))
         return fail(CB_ENOMEM, "trace buffer allocation failed");
       g->tracing = value != 0;
@@ -690,11 +1025,12 @@ cb_status graph_set_option(cb_graph* g, int32_t option, int64_t value) {
       return CB_OK;
     case CB_OPT_GIANT_DEG: {
       if (value < 0) return fail(CB_EINVAL, "giant degree must be >= 0");
+      if (g->static_storage) return fail(CB_EINVAL, "no giant nodes in static storage");
       std::vector<int64_t> rp((size_t)g->n + 1);
-      std::string msg;
-      if (!hip_ok(hipStreamSynchronize(g->stream), &msg, "sync") ||
-          !hip_ok(hipMemcpy(rp.data(), g->rp, rp.size() * sizeof(int64_t), hipMemcpyDeviceToHost), &msg, "read row_ptr"))
-        return fail(CB_EDEVICE, msg);
+      char msg[256];
+      if (!HIP_OK(hipStreamSynchronize(g->stream), "sync") ||
+          !HIP_OK(hipMemcpy(rp.data(), g->rp, rp.size() * sizeof(int64_t), hipMemcpyDeviceToHost), "read row_ptr"))
+        return fail(CB_EDEVICE, "%s", msg);
       return setup_giants(g, value, rp.data());
     }
     case CB_OPT_HELP_MIN:
@@ -705,6 +1041,11 @@ cb_status graph_set_option(cb_graph* g, int32_t option, int64_t value) {
       if (value < 1 || value > kMaxJobs || kMaxJobs % value != 0)
         return fail(CB_EINVAL, "help groups must divide 64");
       g->help_groups = (int32_t)value;
+      return CB_OK;
+    case CB_OPT_HELP_CHUNK:
+      if (value < 64 || value > 4096 || value % 64 != 0)
+        return fail(CB_EINVAL, "help chunk must be a multiple of 64 in [64, 4096]");
+      g->help_chunk = (int32_t)value;
       return CB_OK;
     case CB_OPT_LOCAL_STACK:
       if (value < 0 || value > kStackCap) return fail(CB_EINVAL, "local stack must be in [0, 16]");
@@ -720,9 +1061,9 @@ cb_status graph_stats(cb_graph* g, cb_round_stats* out) {
   cb_status s = sync_and_check(g);
   if (s != CB_OK) return s;
   unsigned long long st[kStatCount] = {0};
-  std::string msg;
-  if (!hip_ok(hipMemcpy(st, g->stats, sizeof(st), hipMemcpyDeviceToHost), &msg, "read stats"))
-    return fail(CB_EDEVICE, msg);
+  char msg[256];
+  if (!HIP_OK(hipMemcpy(st, g->stats, sizeof(st), hipMemcpyDeviceToHost), "read stats"))
+    return fail(CB_EDEVICE, "%s", msg);
   out->trades = g->L;
   out->small_trades = (int64_t)st[kStatSmall];
   out->big_trades = (int64_t)st[kStatBig];
@@ -763,4 +1104,201 @@ void graph_free(cb_graph* g) {
   delete g;
 }
 
+// ---------------------------------------------------------------- batches
+
+cb_status batch_upload(int32_t chains, const int64_t* n, const int64_t* const* row_ptr,
+                       const int32_t* const* col, const uint64_t* seeds, const uint32_t* first_round,
+                       void* stream, uint32_t flags, cb_graph** out) {
+  if (!out) return fail(CB_EINVAL, "out is NULL");
+  if (chains < 1 || !n || !row_ptr || !col || !seeds) return fail(CB_EINVAL, "null or empty chain arrays");
+  std::vector<ChainSrc> src((size_t)chains);
+  for (int32_t c = 0; c < chains; ++c)
+    src[c] = ChainSrc{n[c], row_ptr[c], col[c], false, 0, seeds[c], first_round ? first_round[c] : 0u};
+  return create_graph(src.data(), chains, stream, flags, out);
+}
+
+cb_status batch_info(const cb_graph* g, int32_t chain, int64_t* n, int64_t* nnz, uint32_t* next_round) {
+  if (!g) return fail(CB_EINVAL, "null graph");
+  if (chain < 0 || chain >= g->chains) return fail(CB_EINVAL, "chain out of range");
+  if (g->chains == 1) {
+    if (n) *n = g->n;
+    if (nnz) *nnz = g->nnz;
+    if (next_round) *next_round = 0;
+    return CB_OK;
+  }
+  if (n) *n = g->h_node_base[chain + 1] - g->h_node_base[chain];
+  if (nnz) *nnz = g->h_nnz_base[chain + 1] - g->h_nnz_base[chain];
+  if (next_round) *next_round = g->h_round[chain];
+  return CB_OK;
+}
+
+cb_status batch_run(cb_graph* g, uint32_t rounds) {
+  if (!g) return fail(CB_EINVAL, "null graph");
+  if (g->poisoned) return fail(CB_EPOISONED, "graph handle poisoned: %s", g->poison_msg);
+  if (rounds == 0) return CB_OK;
+  if (g->chains == 1) return fail(CB_EINVAL, "batch_run needs a graph from batch_upload (use global_trade)");
+  char msg[256];
+  const bool eager = g->timing || g->tracing || g->giant_dirty;
+  if (eager) {
+    for (uint32_t r = 0; r < rounds; ++r) {
+      cb_status s = enqueue_round(g, g->stream, CB_STEP_REBUILD, true);
+      if (s != CB_OK) return s;
+    }
+  } else {
+    if (!g->exec || g->exec_rounds != rounds || g->exec_version != g->opt_version) {
+      drop_exec(g);
+      if (!g->cap_stream && !HIP_OK(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking), "capture stream"))
+        return fail(CB_EDEVICE, "%s", msg);
+      if (!HIP_OK(hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture"))
+        return fail(CB_EDEVICE, "%s", msg);
+      cb_status s = CB_OK;
+      for (uint32_t r = 0; r < rounds && s == CB_OK; ++r) s = enqueue_round(g, g->cap_stream, CB_STEP_REBUILD, true);
+      hipGraph_t graph = nullptr;
+      const hipError_t e = hipStreamEndCapture(g->cap_stream, &graph);
+      if (s != CB_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return s;
+      }
+      if (!HIP_OK(e, "end capture")) return fail(CB_EDEVICE, "%s", msg);
+      g->graph = graph;
+      if (!HIP_OK(hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0), "instantiate")) {
+        drop_exec(g);
+        return fail(CB_EDEVICE, "%s", msg);
+      }
+      g->exec_rounds = rounds;
+      g->exec_version = g->opt_version;
+    }
+    if (!HIP_OK(hipGraphLaunch(g->exec, g->stream), "graph launch")) return poison(g, CB_EDEVICE, msg);
+  }
+  for (auto& r : g->h_round) r += rounds;
+  return CB_OK;
+}
+
+cb_status batch_download(cb_graph* g, int32_t chain, int32_t* col) {
+  if (!g) return fail(CB_EINVAL, "null graph");
+  if (chain < 0 || chain >= g->chains) return fail(CB_EINVAL, "chain out of range");
+  if (g->chains == 1) return graph_download(g, nullptr, col);
+  const int64_t e0 = g->h_nnz_base[chain], e = g->h_nnz_base[chain + 1] - e0;
+  if (e > 0 && !col) return fail(CB_EINVAL, "col is NULL");
+  cb_status s = sync_and_check(g);
+  if (s != CB_OK) return s;
+  char msg[256];
+  if (e > 0 && !HIP_OK(hipMemcpy(col, g->col + e0, (size_t)e * sizeof(int32_t), hipMemcpyDeviceToHost), "download col"))
+    return fail(CB_EDEVICE, "%s", msg);
+  const int32_t shift = (int32_t)g->h_node_base[chain];
+  if (shift)
+    for (int64_t i = 0; i < e; ++i) col[i] -= shift;
+  return CB_OK;
+}
+
+// ---------------------------------------------------------------- autotuner
+
+cb_status graph_autotune(cb_graph* g, uint32_t trial_rounds, int32_t use_cache, cb_tune_result* out) {
+  if (!g || !out) return fail(CB_EINVAL, "null argument");
+  if (trial_rounds < 1 || trial_rounds > 64) return fail(CB_EINVAL, "trial rounds must be in [1, 64]");
+  if (g->static_storage) return fail(CB_EINVAL, "no autotuning in static storage");
+  cb_status s = sync_and_check(g);
+  if (s != CB_OK) return s;
+  const TuneKey key = tune_key(g);
+  if (use_cache) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      *out = it->second;
+      out->cached = 1;
+      apply_tuned(g, *out);
+      return CB_OK;
+    }
+  }
+  if (g->L == 0 || g->nnz == 0) {
+    *out = cb_tune_result{g->small_max, g->help_min, g->help_chunk, effective_nbig(g), 0.0, 0.0, 0, 0};
+    return CB_OK;
+  }
+  char msg[256];
+  int32_t* saved = nullptr;
+  if (!alloc_into(g, &saved, g->nnz)) return fail(CB_ENOMEM, "no device memory for the tuner's copy");
+  hipStream_t st = g->stream;
+  const bool timing = g->timing, tracing = g->tracing;
+  g->timing = false;
+  g->tracing = false;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  bool ok = HIP_OK(hipEventCreate(&e0), "event") && HIP_OK(hipEventCreate(&e1), "event") &&
+            HIP_OK(hipMemcpyAsync(saved, g->col, (size_t)g->nnz * 4, hipMemcpyDeviceToDevice, st), "save col") &&
+            HIP_OK(hipMemcpyAsync(g->ch_round_saved, g->ch_round, (size_t)g->chains * 4, hipMemcpyDeviceToDevice, st), "save rounds");
+  // time trial_rounds rounds from the saved state under the current options
+  auto trial = [&](double* ms_out) -> cb_status {
+    if (!HIP_OK(hipMemcpyAsync(g->col, saved, (size_t)g->nnz * 4, hipMemcpyDeviceToDevice, st), "restore col") ||
+        !HIP_OK(hipMemcpyAsync(g->ch_round, g->ch_round_saved, (size_t)g->chains * 4, hipMemcpyDeviceToDevice, st), "restore rounds") ||
+        !HIP_OK(hipEventRecord(e0, st), "event"))
+      return fail(CB_EDEVICE, "%s", msg);
+    for (uint32_t r = 0; r < trial_rounds; ++r) {
+      cb_status t = enqueue_round(g, st, CB_STEP_REBUILD, true);
+      if (t != CB_OK) return t;
+    }
+    if (!HIP_OK(hipEventRecord(e1, st), "event")) return fail(CB_EDEVICE, "%s", msg);
+    cb_status t = sync_and_check(g);
+    if (t != CB_OK) return t;
+    float ms = 0.f;
+    if (!HIP_OK(hipEventElapsedTime(&ms, e0, e1), "elapsed")) return fail(CB_EDEVICE, "%s", msg);
+    *ms_out = (double)ms / trial_rounds;
+    return CB_OK;
+  };
+  cb_tune_result best{g->small_max, g->help_min, g->help_chunk, effective_nbig(g), 0.0, 0.0, 0, 0};
+  if (!ok) s = fail(CB_EDEVICE, "%s", msg);
+  if (s == CB_OK) {
+    apply_tuned(g, best);
+    double ms = 0;
+    s = trial(&ms);   // warm-up (first use of every buffer)
+    if (s == CB_OK) s = trial(&ms);
+    best.ms_per_round = best.default_ms_per_round = ms;
+    best.evaluated = 2;
+  }
+  // coordinate descent over the wavefront/workgroup threshold, the size from
+  // which write phases are shared, their chunk size and the workgroup workers
+  const int32_t small_set[] = {128, 256, 384, 512};
+  const int32_t help_set[] = {1024, 2048, 4096, 8192, 0};
+  const int32_t chunk_set[] = {64, 128, 256, 512};
+  const int32_t big_set[] = {16, 32, 48, 64};
+  for (int param = 0; param < 4 && s == CB_OK; ++param) {
+    const int32_t* set = param == 0 ? small_set : param == 1 ? help_set : param == 2 ? chunk_set : big_set;
+    const int count = param == 1 ? 5 : 4;
+    for (int i = 0; i < count && s == CB_OK; ++i) {
+      cb_tune_result cand = best;
+      int32_t* field = param == 0 ? &cand.small_max : param == 1 ? &cand.help_min
+                     : param == 2 ? &cand.help_chunk : &cand.big_workers;
+      if (*field == set[i]) continue;
+      if (param == 3 && set[i] > g->nbig_alloc) continue;
+      *field = set[i];
+      apply_tuned(g, cand);
+      double ms = 0;
+      s = trial(&ms);
+      best.evaluated++;
+      if (s == CB_OK && ms < best.ms_per_round) {
+        const int ev = best.evaluated;
+        best = cand;
+        best.ms_per_round = ms;
+        best.evaluated = ev;
+      }
+    }
+  }
+  // back to the state before tuning, with the best options
+  (void)hipMemcpyAsync(g->col, saved, (size_t)g->nnz * 4, hipMemcpyDeviceToDevice, st);
+  (void)hipMemcpyAsync(g->ch_round, g->ch_round_saved, (size_t)g->chains * 4, hipMemcpyDeviceToDevice, st);
+  (void)hipStreamSynchronize(st);
+  dev_free_one(g, saved);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  g->timing = timing;
+  g->tracing = tracing;
+  if (s != CB_OK) return s;
+  apply_tuned(g, best);
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune_cache[key] = best;
+  }
+  *out = best;
+  return CB_OK;
+}
+
 }  // extern "C"
+

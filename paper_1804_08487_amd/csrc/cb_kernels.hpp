@@ -58,7 +58,7 @@ constexpr int kStackCap = 16;         // ready trades a wavefront may keep
 constexpr int kTraceFields = 24;      // int64 per trade of the optional trace
 constexpr int kMaxJobs = 64;          // workgroups that can open their write phase to helpers
                                       // (and, in a second set of jobs, part of a giant's bitmap pass)
-constexpr int32_t kHelpChunk = 128;   // output items per claimed chunk
+constexpr int32_t kHelpChunk = 128;   // default output items per claimed chunk
 constexpr int32_t kHelpMinItems = 4096;   // default: smaller trades work alone
 constexpr int32_t kSbChunk = 16;      // bitmap superblocks per claimed extraction chunk
 
@@ -119,6 +119,44 @@ __device__ __forceinline__ void giant_insert(const GiantSets& gs, int32_t gi, in
   atomicAdd(&gs.sc[(int64_t)gi * (gs.gwords >> 6) + (y >> 12)], 1);
 }
 
+// Independent chains run as one graph. Chain c owns the nodes
+// [node_base[c], node_base[c+1]) (its CSR entries hold these global ids, and
+// no edge joins two chains), the trades [trade_base[c], trade_base[c+1])
+// (floor(n_c / 2) of them) and the matching buckets
+// [bucket_base[c], bucket_base[c+1]) (a power of two per chain). Its node keys
+// and split draws use its own seed and round, with local node ids and local
+// trade indices (plus draw_base[c]); so each chain's result is the one it
+// would have alone. The pair list `perm` holds the pairs of trade t at
+// 2t, 2t+1; the left-out node of an odd chain c sits at
+// 2 * trade_base[count] + left_base[c].
+struct Chains {
+  int32_t count;
+  const int64_t* node_base;    // count + 1
+  const int64_t* trade_base;   // count + 1
+  const int32_t* bucket_base;  // count + 1
+  const int32_t* left_base;    // count + 1 (odd chains before c)
+  const uint64_t* seed;        // count
+  const uint32_t* round;       // count
+  const uint32_t* draw_base;   // count
+};
+
+// Largest c in [0, count) with base[c] <= x (base ascending, base[0] <= x).
+template <typename T>
+__device__ __forceinline__ int32_t chain_search(const T* base, int32_t count, T x) {
+  int32_t lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (base[mid] <= x) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+__device__ __forceinline__ int32_t chain_of_node(const Chains& ch, int64_t v) {
+  return ch.count == 1 ? 0 : chain_search(ch.node_base, ch.count, v);
+}
+__device__ __forceinline__ int32_t chain_of_trade(const Chains& ch, int64_t k) {
+  return ch.count == 1 ? 0 : chain_search(ch.trade_base, ch.count, k);
+}
+
 struct TradeArgs {
   const int64_t* rp;
   const int32_t* col;
@@ -150,12 +188,12 @@ struct TradeArgs {
   int32_t small_max;
   int32_t help_min;         // trades of at least this many items open their write phase (0: none)
   int32_t help_groups;      // workgroup b helps owners j with j % help_groups == b % help_groups
+  int32_t help_chunk;       // items per claimed chunk of a shared write phase (a multiple of 64)
   int32_t big_lds_max;
   int32_t nbig;
   int32_t stack_cap;
   int32_t keybits;          // bits of (node << 1 | side)
-  uint32_t round;
-  uint64_t seed;
+  Chains ch;                // seed, round and trade range of each chain
   uint64_t watchdog_ticks;
 };
 
@@ -163,16 +201,19 @@ struct TradeArgs {
 __global__ void k_round_reset(int64_t n, int32_t nb, int32_t* inbox_cur, int32_t* out_cur,
                               int32_t* own_cur, int32_t* bcount, int32_t* bcur, int32_t* ctrl,
                               unsigned long long* stats);
-__global__ void k_match_count(int64_t n, uint64_t seed, uint32_t round, int nb_log2,
-                              int32_t* bcount, const int32_t* ctrl);
+__global__ void k_set_chain(uint64_t* seed, uint32_t* round, int32_t c, uint64_t s, uint32_t r);
+__global__ void k_advance_rounds(uint32_t* round, int32_t count, uint32_t by);
+__global__ void k_fill_i32(int32_t* p, int64_t count, int32_t value);
+__global__ void k_single_chain(int64_t* node_base, int64_t* trade_base, int32_t* bucket_base,
+                               int32_t* left_base, uint64_t* seed, uint32_t* round, uint32_t* draw_base,
+                               int64_t n, int32_t nb, uint64_t s, uint32_t r);
+__global__ void k_match_count(int64_t n, Chains ch, int32_t* bcount, const int32_t* ctrl);
 __global__ void k_match_scan(int32_t nb, const int32_t* bcount, int32_t* bstart,
                              const int32_t* ctrl);
-__global__ void k_match_scatter(int64_t n, uint64_t seed, uint32_t round, int nb_log2,
-                                const int32_t* bstart, int32_t* bcur, int32_t* mtmp,
-                                const int32_t* ctrl);
-__global__ void k_match_sort(int64_t n, uint64_t seed, uint32_t round, int32_t nb,
-                             const int32_t* bstart, int32_t* mtmp, uint64_t* mkey,
-                             int32_t* perm, int32_t* trade_of, int32_t* tinfo,
+__global__ void k_match_scatter(int64_t n, Chains ch, const int32_t* bstart, int32_t* bcur,
+                                int32_t* mtmp, const int32_t* ctrl);
+__global__ void k_match_sort(Chains ch, int32_t nb, const int32_t* bstart, int32_t* mtmp,
+                             uint64_t* mkey, int32_t* perm, int32_t* trade_of, int32_t* tinfo,
                              const int32_t* giant_id, int32_t* dep, int32_t* ctrl);
 __global__ void k_depscan(int64_t n, int64_t nnz, const int64_t* rp, const int32_t* col,
                           const int32_t* trade_of, const int32_t* tinfo, int32_t* col_t,
@@ -190,6 +231,9 @@ __global__ void k_segsort_mid(const int32_t* rows, int64_t nrows, const int64_t*
                               const int32_t* src, int32_t* dst, int keybits, const int32_t* ctrl);
 __global__ void k_segsort_big(const int32_t* rows, int64_t nrows, const int64_t* rp,
                               int32_t* src, int32_t* dst, int keybits, const int32_t* ctrl);
+__global__ void k_classify_rows(int64_t n, const int64_t* rp, int32_t* rows, int64_t base1,
+                                int64_t base2, unsigned long long* cur);
+__global__ void k_copy_shift(int32_t* dst, const int32_t* src, int64_t count, int32_t delta);
 __global__ void k_validate(int64_t n, int64_t nnz, const int64_t* rp, const int32_t* col,
                            int32_t* ctrl);
 

@@ -27,24 +27,66 @@ __global__ void k_round_reset(int64_t n, int32_t nb, int32_t* inbox_cur, int32_t
   if (t0 < kStatCount) stats[t0] = 0;
 }
 
+// ---------------------------------------------------------------- chains
+
+__global__ void k_set_chain(uint64_t* seed, uint32_t* round, int32_t c, uint64_t s, uint32_t r) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    seed[c] = s;
+    round[c] = r;
+  }
+}
+
+__global__ void k_advance_rounds(uint32_t* round, int32_t count, uint32_t by) {
+  for (int32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < count; c += gridDim.x * blockDim.x)
+    round[c] += by;
+}
+
+__global__ void k_single_chain(int64_t* node_base, int64_t* trade_base, int32_t* bucket_base,
+                               int32_t* left_base, uint64_t* seed, uint32_t* round, uint32_t* draw_base,
+                               int64_t n, int32_t nb, uint64_t s, uint32_t r) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    node_base[0] = 0;
+    node_base[1] = n;
+    trade_base[0] = 0;
+    trade_base[1] = n / 2;
+    bucket_base[0] = 0;
+    bucket_base[1] = nb;
+    left_base[0] = 0;
+    left_base[1] = (int32_t)(n & 1);
+    seed[0] = s;
+    round[0] = r;
+    draw_base[0] = 0;
+  }
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t count, int32_t value) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = value;
+}
+
 // ---------------------------------------------------------------- matching
-// Node v's key is philox64(seed; v, round, 0, TAG_M). Nodes are bucketed by
-// the top nb_log2 key bits (buckets are in key order), each bucket is sorted
-// by (key, id) in LDS, and the concatenation is the pairing order.
+// Node v (local id lv in its chain c) has the key philox64(seed_c; lv,
+// round_c, 0, TAG_M). Each chain's nodes are bucketed by the top bits of their
+// keys into the chain's own buckets (in key order), each bucket is sorted by
+// (key, id) in LDS, and the concatenation, chain by chain, is the pairing
+// order: positions 2i and 2i+1 of chain c are its trade i.
 
-__device__ __forceinline__ uint64_t node_key(uint64_t seed, uint32_t round, int64_t v) {
-  return philox64(seed, (uint32_t)v, round, 0u, kTagMatch);
+__device__ __forceinline__ uint64_t chain_key(const Chains& ch, int32_t c, int64_t v) {
+  return philox64(ch.seed[c], (uint32_t)(v - ch.node_base[c]), ch.round[c], 0u, kTagMatch);
 }
-__device__ __forceinline__ uint32_t key_bucket(uint64_t key, int nb_log2) {
-  return nb_log2 ? (uint32_t)(key >> (64 - nb_log2)) : 0u;
+__device__ __forceinline__ uint32_t node_bucket(const Chains& ch, int64_t v) {
+  const int32_t c = chain_of_node(ch, v);
+  const uint64_t key = chain_key(ch, c, v);
+  const int32_t b0 = ch.bucket_base[c];
+  const int32_t lg = 31 - __clz(ch.bucket_base[c + 1] - b0);   // buckets: a power of two
+  return (uint32_t)b0 + (lg ? (uint32_t)(key >> (64 - lg)) : 0u);
 }
 
-__global__ void k_match_count(int64_t n, uint64_t seed, uint32_t round, int nb_log2,
-                              int32_t* bcount, const int32_t* ctrl) {
+__global__ void k_match_count(int64_t n, Chains ch, int32_t* bcount, const int32_t* ctrl) {
   if (ctrl[cw(kCwErr)]) return;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
-    atomicAdd(&bcount[key_bucket(node_key(seed, round, v), nb_log2)], 1);
+    atomicAdd(&bcount[node_bucket(ch, v)], 1);
 }
 
 __global__ void k_match_scan(int32_t nb, const int32_t* bcount, int32_t* bstart,
@@ -67,13 +109,12 @@ __global__ void k_match_scan(int32_t nb, const int32_t* bcount, int32_t* bstart,
   if (threadIdx.x == 0) bstart[nb] = carry;
 }
 
-__global__ void k_match_scatter(int64_t n, uint64_t seed, uint32_t round, int nb_log2,
-                                const int32_t* bstart, int32_t* bcur, int32_t* mtmp,
-                                const int32_t* ctrl) {
+__global__ void k_match_scatter(int64_t n, Chains ch, const int32_t* bstart, int32_t* bcur,
+                                int32_t* mtmp, const int32_t* ctrl) {
   if (ctrl[cw(kCwErr)]) return;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
-    const uint32_t b = key_bucket(node_key(seed, round, v), nb_log2);
+    const uint32_t b = node_bucket(ch, v);
     mtmp[bstart[b] + atomicAdd(&bcur[b], 1)] = (int32_t)v;
   }
 }
@@ -86,43 +127,54 @@ struct KeyedNode {
   }
 };
 
-__device__ __forceinline__ void write_pair_slot(int64_t n, int64_t p, int32_t id, int32_t* perm,
-                                                int32_t* trade_of, int32_t* tinfo,
+// Node `id` of chain c at global sorted position p (chain c's positions start
+// at node_base[c], because its buckets hold exactly its nodes).
+__device__ __forceinline__ void write_pair_slot(const Chains& ch, int32_t c, int64_t p, int32_t id,
+                                                int32_t* perm, int32_t* trade_of, int32_t* tinfo,
                                                 const int32_t* giant_id, int32_t* dep) {
-  perm[p] = id;
-  const bool left_out = (n & 1) && p == n - 1;
-  const int32_t t = left_out ? kUnmatched : (int32_t)(p >> 1);
+  const int64_t nb0 = ch.node_base[c];
+  const int64_t pl = p - nb0;
+  const int64_t nc = ch.node_base[c + 1] - nb0;
+  if ((nc & 1) && pl == nc - 1) {
+    perm[2 * ch.trade_base[ch.count] + ch.left_base[c]] = id;
+    trade_of[id] = kUnmatched;
+    tinfo[id] = kUnmatched;
+    return;
+  }
+  const int32_t t = (int32_t)(ch.trade_base[c] + (pl >> 1));
+  perm[2 * (int64_t)t + (pl & 1)] = id;
   trade_of[id] = t;
-  tinfo[id] = (!left_out && giant_id[id] >= 0) ? (t | kGiantBit) : t;
-  if (!(p & 1) && p + 1 < n) dep[p >> 1] = 0;
+  tinfo[id] = giant_id[id] >= 0 ? (t | kGiantBit) : t;
+  if (!(pl & 1)) dep[t] = 0;
 }
 
 __global__ void __launch_bounds__(kMatchBlock)
-k_match_sort(int64_t n, uint64_t seed, uint32_t round, int32_t nb, const int32_t* bstart,
-             int32_t* mtmp, uint64_t* mkey, int32_t* perm, int32_t* trade_of, int32_t* tinfo,
-             const int32_t* giant_id, int32_t* dep, int32_t* ctrl) {
+k_match_sort(Chains ch, int32_t nb, const int32_t* bstart, int32_t* mtmp, uint64_t* mkey,
+             int32_t* perm, int32_t* trade_of, int32_t* tinfo, const int32_t* giant_id, int32_t* dep,
+             int32_t* ctrl) {
   __shared__ KeyedNode buf[kMatchCap];
   if (ctrl[cw(kCwErr)]) return;
   for (int32_t b = blockIdx.x; b < nb; b += gridDim.x) {
+    const int32_t c = ch.count == 1 ? 0 : chain_search(ch.bucket_base, ch.count, b);
     const int64_t s0 = bstart[b];
     const int64_t cnt = bstart[b + 1] - s0;
     if (cnt <= kMatchCap) {
       for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) {
         const int32_t id = mtmp[s0 + i];
-        buf[i].key = node_key(seed, round, id);
+        buf[i].key = chain_key(ch, c, id);
         buf[i].id = (uint32_t)id;
       }
       __syncthreads();
       block_bitonic_sort(buf, (uint32_t)cnt);
       for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x)
-        write_pair_slot(n, s0 + i, (int32_t)buf[i].id, perm, trade_of, tinfo, giant_id, dep);
+        write_pair_slot(ch, c, s0 + i, (int32_t)buf[i].id, perm, trade_of, tinfo, giant_id, dep);
       __syncthreads();
     } else {
       // A bucket this large has probability far below 2^-500 for hashed
       // keys; it is still sorted exactly, in global memory.
       uint64_t* k = mkey + s0;
       int32_t* ids = mtmp + s0;
-      for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) k[i] = node_key(seed, round, ids[i]);
+      for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) k[i] = chain_key(ch, c, ids[i]);
       __syncthreads();
       const uint64_t P = (uint64_t)next_pow2((uint32_t)cnt);
       for (uint64_t k2 = 2; k2 <= P; k2 <<= 1) {
@@ -148,7 +200,7 @@ k_match_sort(int64_t n, uint64_t seed, uint32_t round, int32_t nb, const int32_t
         }
       }
       for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x)
-        write_pair_slot(n, s0 + i, ids[i], perm, trade_of, tinfo, giant_id, dep);
+        write_pair_slot(ch, c, s0 + i, ids[i], perm, trade_of, tinfo, giant_id, dep);
       __syncthreads();
     }
   }
@@ -409,6 +461,39 @@ k_segsort_big(const int32_t* rows, int64_t nrows, const int64_t* rp, int32_t* sr
     }
     __syncthreads();
   }
+}
+
+// Rows of each rebuild size class, listed once at upload (degrees never
+// change): rows of 1..64 entries from rows[0], of 65..4096 from rows[base[1]],
+// larger ones from rows[base[2]]; cur[0..3) counts the rows placed so far.
+__global__ void k_classify_rows(int64_t n, const int64_t* rp, int32_t* rows, int64_t base1,
+                                int64_t base2, unsigned long long* cur) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  // trip count is uniform across a wavefront (ballots below)
+  for (int64_t b0 = (int64_t)blockIdx.x * blockDim.x; b0 < n; b0 += stride) {
+    const int64_t x = b0 + threadIdx.x;
+    int cls = -1;
+    if (x < n) {
+      const int64_t d = rp[x + 1] - rp[x];
+      cls = d == 0 ? -1 : (d <= kSegSmallMax ? 0 : (d <= kSegMidMax ? 1 : 2));
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const uint64_t m = ballot(cls == c);
+      if (!m) continue;
+      unsigned long long pos = 0;
+      if (lane_id() == 0) pos = atomicAdd(&cur[c], (unsigned long long)popc64(m));
+      pos = __shfl(pos, 0, kWave);
+      if (cls == c) rows[(c == 0 ? 0 : (c == 1 ? base1 : base2)) + (int64_t)pos + rank_below(m)] = (int32_t)x;
+    }
+  }
+}
+
+// dst[i] = src[i] + delta (node ids of one chain moved to another id range).
+__global__ void k_copy_shift(int32_t* dst, const int32_t* src, int64_t count, int32_t delta) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+    dst[i] = src[i] + delta;
 }
 
 // ---------------------------------------------------------------- validate

@@ -117,6 +117,22 @@ __device__ __forceinline__ void raise_error(const TradeArgs& A, int32_t bits, in
 // order, on one lane.
 __device__ __forceinline__ int32_t split_steps(int32_t N, int32_t a) { return a <= N - a ? a : N - a; }
 
+// Seed, round and draw index of trade k: those of its chain, with the trade's
+// index within the chain (plus the chain's draw offset).
+struct DrawKey {
+  uint64_t seed;
+  uint32_t round;
+  int32_t idx;
+};
+__device__ __forceinline__ DrawKey draw_key(const TradeArgs& A, int32_t k) {
+  const int32_t c = chain_of_trade(A.ch, k);
+  DrawKey d;
+  d.seed = A.ch.seed[c];
+  d.round = A.ch.round[c];
+  d.idx = (int32_t)((uint32_t)(k - A.ch.trade_base[c]) + A.ch.draw_base[c]);
+  return d;
+}
+
 __device__ __forceinline__ int32_t split_partner(int32_t N, int32_t a, int32_t t, uint64_t seed,
                                                  uint32_t round, int32_t k) {
   const bool fwd = a <= N - a;
@@ -786,8 +802,8 @@ __device__ __forceinline__ bool try_help(const TradeArgs& A, int32_t b, WriteCou
   S.bv = load_agent64(&J->f.bv);
   S.gu = load_agent(&J->f.gu);
   S.gv = load_agent(&J->f.gv);
-  const int32_t first = c * kHelpChunk;
-  const int32_t end = first + kHelpChunk < S.s ? first + kHelpChunk : S.s;
+  const int32_t first = c * A.help_chunk;
+  const int32_t end = first + A.help_chunk < S.s ? first + A.help_chunk : S.s;
   write_range<true>(A, S, first, end, kWave * kBatch, J->c.own, W);
   publish_wait();
   if (l == 0) atomic_add(&J->c.done, 1);
@@ -896,7 +912,8 @@ __device__ __forceinline__ void small_trade(const TradeArgs& A, int32_t k, int32
     a += popc64(ballot(isD && side == 0));
   }
   wave_sync();
-  wave_split(W.D, nD, a, A.seed, A.round, k, W.R);
+  const DrawKey dk = draw_key(A, k);
+  wave_split(W.D, nD, a, dk.seed, dk.round, dk.idx, W.R);
 
   // ---- write: own-row finals, other-row finals, forwards; each chunk's
   // forwards then drop their target trades' counters once the chunk's
@@ -2102,6 +2119,7 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
   }
   __syncthreads();
   const uint64_t t_classified = now_ticks();
+  const DrawKey dk = draw_key(A, k);
   {
     // D in global memory: the touched positions through LDS (the tile is
     // free by now); D in LDS, or a long split: in place, in order
@@ -2113,16 +2131,16 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
     while (nslots < 4 * T && nslots < kSplitSlots) nslots <<= 1;
     if (items_only) {
       if (T > 0)
-        item_split(Ig, nD, a, A.seed, A.round, k, Lt, B.u.tile.E + kSplitSlots / 2, nslots,
+        item_split(Ig, nD, a, dk.seed, dk.round, dk.idx, Lt, B.u.tile.E + kSplitSlots / 2, nslots,
                    Lt + 3 * kSplitSlots, Lt + 3 * kSplitSlots + 2 * (kSplitSlots / 4), B.sboff);
     } else if (!in_lds && T > 0 && 4 * T <= kSplitSlots) {
-      lds_split(D, nD, a, A.seed, A.round, k, Lt, Lt + kSplitSlots, Lt + 2 * kSplitSlots, nslots,
+      lds_split(D, nD, a, dk.seed, dk.round, dk.idx, Lt, Lt + kSplitSlots, Lt + 2 * kSplitSlots, nslots,
                 Lt + 3 * kSplitSlots, Lt + 3 * kSplitSlots + 2 * (kSplitSlots / 4), B.sboff);
     } else {
-      block_split(D, nD, a, A.seed, A.round, k, B.sboff, 2 * kTradeBlock);
+      block_split(D, nD, a, dk.seed, dk.round, dk.idx, B.sboff, 2 * kTradeBlock);
     }
   }
-  if (items_ready && !items_only) split_fix_items(E, D, nD, a, A.seed, A.round, k, Ig);
+  if (items_ready && !items_only) split_fix_items(E, D, nD, a, dk.seed, dk.round, dk.idx, Ig);
   if (tid == 0) {
     B.cnt[1] = 0;
     B.cnt[2] = 0;
@@ -2149,7 +2167,7 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
     __syncthreads();
     if (A.trace && tid == 0) A.trace[kTraceFields * (int64_t)k + 16] = (int64_t)now_ticks();
     HelpJob* J = A.jobs + blockIdx.x;
-    const int32_t nchunks = (s + kHelpChunk - 1) / kHelpChunk;
+    const int32_t nchunks = (s + A.help_chunk - 1) / A.help_chunk;
     if (tid == 0) {
       store_agent64(&J->f.bu, bu);
       store_agent64(&J->f.bv, bv);
@@ -2175,8 +2193,8 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
       if (lane_id() == 0) c = claim_chunk(J);
       c = wave_bcast(c, 0);
       if (c < 0) break;
-      const int32_t first = c * kHelpChunk;
-      write_range<true>(A, S, first, first + kHelpChunk < s ? first + kHelpChunk : s, kWave * kBatch,
+      const int32_t first = c * A.help_chunk;
+      write_range<true>(A, S, first, first + A.help_chunk < s ? first + A.help_chunk : s, kWave * kBatch,
                         J->c.own, W);
       publish_wait();
       if (lane_id() == 0) {
