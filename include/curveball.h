@@ -280,6 +280,24 @@ typedef struct {
 
 cb_status graph_autotune(cb_graph* g, uint32_t trial_rounds, int32_t use_cache, cb_tune_result* out);
 
+/* ---- no device allocation -------------------------------------------------
+ * For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc). One global trade
+ * (the result of graph_upload + global_trade(seed, round) + graph_download,
+ * byte for byte) of a graph the caller holds: row_ptr in host memory (n+1
+ * int64), col in device memory (row_ptr[n] int32, the graph form above; read
+ * and overwritten with the result). Every other buffer lives in the library's
+ * static device array of 64 MiB (each GPU the library runs on holds its own
+ * copy until the process ends); no device or host allocation is made. A graph
+ * that needs more than the array holds is rejected with CB_EINVAL before any
+ * device work. Calls on one GPU run one after the other (the array keeps the
+ * last call's contents and every call sets up what it needs); the call
+ * synchronises `stream` (NULL: the null stream) before returning. Errors are
+ * reported by the return value; there is no handle to poison. Giant-node
+ * bitmaps, tracing and timing are not available on this path. */
+cb_status global_trade_static(int64_t n, const int64_t* row_ptr, int32_t* col, uint64_t seed,
+                              uint32_t round, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -32,7 +32,8 @@ UNMATCHED = 2**31 - 1
 EXPORTS = ("cb_set_allocator", "graph_upload", "graph_info", "global_trade", "graph_sync",
            "graph_download", "graph_free", "cb_last_error", "global_trade_steps",
            "graph_download_state", "graph_set_option", "graph_stats", "graph_kernel_times",
-           "batch_upload", "batch_run", "batch_info", "batch_download", "graph_autotune")
+           "batch_upload", "batch_run", "batch_info", "batch_download", "graph_autotune",
+           "global_trade_static")
 
 
 class CurveballError(RuntimeError):
@@ -102,6 +103,7 @@ def lib():
         L.batch_info.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(u32)]
         L.batch_download.argtypes = [vp, i32, vp]
         L.graph_autotune.argtypes = [vp, u32, i32, ctypes.POINTER(TuneResult)]
+        L.global_trade_static.argtypes = [i64, vp, vp, u64, u32, vp]
         for name in EXPORTS:
             if name not in ("graph_free", "cb_last_error"):
                 getattr(L, name).restype = ctypes.c_int
@@ -147,6 +149,15 @@ def current_stream_handle():
     """hipStream_t of PyTorch's current stream on the current device."""
     import torch
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def global_trade_static(row_ptr, col_device_ptr: int, seed: int, rnd: int, stream=None):
+    """One global trade of a graph held by the caller (host row_ptr, device col
+    at `col_device_ptr`, overwritten with the result), with no allocation."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    if stream is None:
+        stream = current_stream_handle()
+    _check(lib().global_trade_static(len(rp) - 1, rp.ctypes.data, col_device_ptr, seed, rnd, stream))
 
 
 class Graph:

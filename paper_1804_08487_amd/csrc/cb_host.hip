@@ -1302,3 +1302,76 @@ cb_status graph_autotune(cb_graph* g, uint32_t trial_rounds, int32_t use_cache, 
 
 }  // extern "C"
 
+
+// ---------------------------------------------------------------- static scratch
+// One global trade of a caller-held graph with every buffer in this array
+// (for callers that cannot allocate device memory). Each GPU holds its own
+// copy of the array, at its own address, from library load to process end.
+namespace {
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+struct StaticDevice {
+  std::mutex mu;           // calls on one device run one after the other
+  bool ready = false;
+  char* ptr = nullptr;     // device address of this device's `scratch`
+  cb_graph g;              // host-side state of the last call
+};
+StaticDevice g_static[kMaxDevices];
+}  // namespace
+
+extern "C" cb_status global_trade_static(int64_t n, const int64_t* row_ptr, int32_t* col, uint64_t seed,
+                                         uint32_t round, void* stream) {
+  if (n < 0 || n > INT32_MAX) return fail(CB_EINVAL, "n must be in [0, 2^31 - 1]");
+  int dev = 0;
+  char msg[256];
+  if (!HIP_OK(hipGetDevice(&dev), "hipGetDevice")) return fail(CB_EDEVICE, "%s", msg);
+  if (dev < 0 || dev >= kMaxDevices) return fail(CB_EINVAL, "device index beyond %d", kMaxDevices);
+  StaticDevice& S = g_static[dev];
+  std::lock_guard<std::mutex> lock(S.mu);
+  if (!S.ready) {
+    // the array's name is a host-side stand-in: its device address comes from
+    // the runtime, once per device, with that device current
+    void* p = nullptr;
+    if (!HIP_OK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)"))
+      return fail(CB_EDEVICE, "%s", msg);
+    S.ptr = static_cast<char*>(p);
+    S.ready = true;
+  }
+  ChainSrc c{n, row_ptr, col, true, 0, seed, round};
+  int64_t d1 = 0, d2 = 0;
+  cb_status s = check_chain_host(c, &d1, &d2);
+  if (s != CB_OK) return s;
+  cb_graph* g = &S.g;
+  *g = cb_graph();
+  g->static_storage = true;
+  g->device = dev;
+  g->stream = (hipStream_t)stream;
+  const DeviceInfo di = device_info(dev);
+  g->cu_count = di.cu_count;
+  g->occupancy_blocks = di.occupancy;
+  g->ticks_per_ms = di.ticks_per_ms;
+  g->nbig_alloc = std::max(1, std::min(16, g->cu_count / 2));
+  size_graph(g, &c, 1, d1, d2);
+  count_classes(g, &c, 1);
+  BufPlan P;
+  plan_buffers(g, P, false);
+  const size_t need = plan_bytes(P);
+  if (need > kStaticScratchBytes)
+    return fail(CB_EINVAL, "graph needs %zu bytes of scratch; the static array holds %zu", need, kStaticScratchBytes);
+  carve_plan(P, S.ptr);
+  g->col = col;
+  hipStream_t st = g->stream;
+  if (!HIP_OK(hipMemcpyAsync(g->rp, row_ptr, (size_t)(n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st), "copy row_ptr"))
+    return fail(CB_EDEVICE, "%s", msg);
+  hipLaunchKernelGGL(k_single_chain, dim3(1), dim3(64), 0, st, g->ch_node_base, g->ch_trade_base, g->ch_bucket_base,
+                     g->ch_left_base, g->ch_seed, g->ch_round, g->ch_draw_base, n, g->nb, seed, round);
+  if (!init_device_state(g, false, msg, sizeof(msg))) return fail(CB_EDEVICE, "%s", msg);
+  g->gwords = ((n + 4095) / 4096) * 64;
+  s = enqueue_round(g, st, CB_STEP_REBUILD, false);
+  if (s != CB_OK) return s;
+  return sync_and_check(g);
+}
