@@ -186,6 +186,22 @@ cb_status graph_download_state(cb_graph* g, int32_t which, void* host, int64_t c
                                    write phase (a multiple of 64 in [64, 4096];
                                    default 128) */
 
+#define CB_OPT_IDLE_BACKOFF 15  /* longest sleep of an idle wavefront worker
+                                   between polls of the ready queues, in units of
+                                   2048 cycles (1..1024; default 128, about
+                                   110 us) */
+#define CB_OPT_FUSE_NEXT    14  /* 1 (default): a full round also prepares the next
+                                   one (its matching, run once this round's trade
+                                   kernel is done, and its dependency scan, done
+                                   by the rebuild as it writes each row); the next
+                                   round then starts at its sources. A single
+                                   chain is prepared for (seed, round + 1); a
+                                   call with another (seed, round) starts over.
+                                   After a full round the state arrays
+                                   (CB_STATE_PERM, _TRADE_OF, _DEP) hold the
+                                   prepared round's. 0: every round runs all
+                                   steps. */
+
 /* Set an option of a graph (any option may change between rounds; none
  * changes the result, only how the work is scheduled). */
 cb_status graph_set_option(cb_graph* g, int32_t option, int64_t value);
@@ -258,9 +274,11 @@ cb_status batch_info(const cb_graph* g, int32_t chain, int64_t* n, int64_t* nnz,
 cb_status batch_download(cb_graph* g, int32_t chain, int32_t* col);
 
 /* ---- autotuner --------------------------------------------------------------
- * Chooses the wavefront/workgroup size threshold (CB_OPT_SMALL_MAX), the size
- * from which write phases are shared (CB_OPT_HELP_MIN), their chunk size
- * (CB_OPT_HELP_CHUNK) and the workgroup workers (CB_OPT_BIG_WORKERS) by
+ * Chooses the idle wavefronts' back-off (CB_OPT_IDLE_BACKOFF), their local
+ * stack of ready trades (CB_OPT_LOCAL_STACK), the wavefront/workgroup size
+ * threshold (CB_OPT_SMALL_MAX), the size from which write phases are shared
+ * (CB_OPT_HELP_MIN), their chunk size (CB_OPT_HELP_CHUNK) and the workgroup
+ * workers (CB_OPT_BIG_WORKERS) by
  * timing `trial_rounds` rounds per candidate from the graph's current state
  * (coordinate descent from the current options), then restores that state and
  * keeps the fastest options. The schedule never changes a result. Results are
@@ -272,6 +290,8 @@ typedef struct {
     int32_t help_min;
     int32_t help_chunk;
     int32_t big_workers;
+    int32_t local_stack;          /* CB_OPT_LOCAL_STACK */
+    int32_t idle_backoff;         /* CB_OPT_IDLE_BACKOFF */
     double ms_per_round;          /* of the chosen options */
     double default_ms_per_round;  /* of the options the tuner started from */
     int32_t evaluated;            /* timed candidates (0 when taken from the cache) */

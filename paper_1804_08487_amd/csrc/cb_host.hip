@@ -138,11 +138,19 @@ struct cb_graph {
   int32_t help_min = kHelpMinItems;
   int32_t help_groups = 2;
   int32_t help_chunk = kHelpChunk;
+  int32_t idle_backoff = 128;
   int64_t watchdog_ms = 20000;
   bool timing = false;
   bool debug_checks = false;
   bool tracing = false;
   uint64_t opt_version = 0;  // bumped by every option change (captured rounds bake options in)
+  bool fuse_next = true;     // the rebuild also prepares the next round (matching + dependency scan)
+
+  // a round prepared by the previous one's rebuild: its matching, dependency
+  // counts, per-entry trade information and giant bitmap seeds are in place
+  bool prepared = false;
+  uint64_t prep_seed = 0;    // single chain: the (seed, round) it was prepared for
+  uint32_t prep_round = 0;
 
   // batched rounds captured as a graph
   hipStream_t cap_stream = nullptr;
@@ -150,6 +158,7 @@ struct cb_graph {
   hipGraphExec_t exec = nullptr;
   uint32_t exec_rounds = 0;
   uint64_t exec_version = 0;
+  bool exec_prepared = false;   // the captured rounds start from a prepared round
 
   bool poisoned = false;
   char poison_msg[384] = {0};
@@ -388,6 +397,7 @@ cb_status setup_giants(cb_graph* g, int64_t deg, const int64_t* host_row_ptr) {
   char msg[256];
   if (!HIP_OK(hipStreamSynchronize(g->stream), "sync")) return fail(CB_EDEVICE, "%s", msg);
   drop_exec(g);
+  g->prepared = false;   // a prepared round's bitmap seeds and giant bits are for the old sets
   dev_free_one(g, g->gbm);
   dev_free_one(g, g->gsc);
   g->gbm = nullptr;
@@ -438,11 +448,39 @@ int32_t effective_small_max(const cb_graph* g) {
   return g->giant_deg > 0 ? (int32_t)std::min<int64_t>(g->small_max, g->giant_deg - 1) : g->small_max;
 }
 
+// Forget a prepared round (its bitmap seeds are cleared before the next scan).
+void unprepare(cb_graph* g) {
+  if (g->prepared && g->ngiant > 0) g->giant_dirty = true;
+  g->prepared = false;
+}
+
+// Matching kernels of the round in the chain table (keys, buckets, pairs,
+// trade_of, tinfo, zeroed dep).
+void enqueue_matching(cb_graph* g, hipStream_t st) {
+  const int64_t n = g->n;
+  const Chains ch = chains_of(g);
+  hipLaunchKernelGGL(k_match_count, dim3(grid_for(n, 256, 16384)), dim3(256), 0, st, n, ch, g->bcount, g->ctrl);
+  hipLaunchKernelGGL(k_match_scan, dim3(1), dim3(1024), 0, st, g->nb, g->bcount, g->bstart, g->ctrl);
+  hipLaunchKernelGGL(k_match_scatter, dim3(grid_for(n, 256, 16384)), dim3(256), 0, st, n, ch, g->bstart,
+                     g->bcur, g->mtmp, g->ctrl);
+  hipLaunchKernelGGL(k_match_sort, dim3(std::min<int32_t>(g->nb, 1 << 20)), dim3(kMatchBlock), 0, st,
+                     ch, g->nb, g->bstart, g->mtmp, g->mkey, g->perm, g->trade_of, g->tinfo, g->giant_id,
+                     g->dep, g->ctrl);
+}
+
 // Enqueue the steps 1..last_step of one global trade of every chain on `st`,
 // with the seeds and rounds in the chain table; `advance` adds one to every
-// chain's round afterwards. No host synchronisation and no memset, so the
-// sequence can be captured into a graph (without timing or tracing).
-cb_status enqueue_round(cb_graph* g, hipStream_t st, int last_step, bool advance) {
+// chain's round afterwards. A round prepared by the previous one starts at
+// its sources. A full round prepares the next one when fusion is on: the
+// next round's matching needs no graph data (it only overwrites this round's
+// matching, dead once the trade kernel is done), and the rebuild then scans
+// every row it writes for the next round; a single chain is prepared for
+// (seed, round + 1), set by `next_seed`/`next_round`. No host
+// synchronisation and no memset when nothing is left over from a partial
+// round, so the sequence can be captured into a graph (without timing or
+// tracing).
+cb_status enqueue_round(cb_graph* g, hipStream_t st, int last_step, bool advance,
+                        bool single_next = false, uint64_t next_seed = 0, uint32_t next_round = 0) {
   if (g->poisoned) return fail(CB_EPOISONED, "graph handle poisoned: %s", g->poison_msg);
   if (last_step < CB_STEP_MATCHING || last_step > CB_STEP_REBUILD)
     return fail(CB_EINVAL, "last_step out of range");
@@ -467,6 +505,9 @@ cb_status enqueue_round(cb_graph* g, hipStream_t st, int last_step, bool advance
   const int64_t n = g->n;
   const int32_t L = g->L;
   const Chains ch = chains_of(g);
+  const bool from_prepared = g->prepared && last_step == CB_STEP_REBUILD;
+  if (!from_prepared) unprepare(g);
+  g->prepared = false;
   if (g->giant_dirty) {
     if (!HIP_OK(hipMemsetAsync(g->gbm, 0, (size_t)g->ngiant * g->gwords * 8, st), "clear bitmaps") ||
         !HIP_OK(hipMemsetAsync(g->gsc, 0, (size_t)g->ngiant * (g->gwords >> 6) * 4, st), "clear counts"))
@@ -479,20 +520,14 @@ cb_status enqueue_round(cb_graph* g, hipStream_t st, int last_step, bool advance
                      dim3(256), 0, st, n, g->nb, g->inbox_cur, g->out_cur, g->own_cur, g->bcount,
                      g->bcur, g->ctrl, g->stats);
   // 1. matching
-  hipLaunchKernelGGL(k_match_count, dim3(grid_for(n, 256, 16384)), dim3(256), 0, st, n, ch, g->bcount, g->ctrl);
-  hipLaunchKernelGGL(k_match_scan, dim3(1), dim3(1024), 0, st, g->nb, g->bcount, g->bstart, g->ctrl);
-  hipLaunchKernelGGL(k_match_scatter, dim3(grid_for(n, 256, 16384)), dim3(256), 0, st, n, ch, g->bstart,
-                     g->bcur, g->mtmp, g->ctrl);
-  hipLaunchKernelGGL(k_match_sort, dim3(std::min<int32_t>(g->nb, 1 << 20)), dim3(kMatchBlock), 0, st,
-                     ch, g->nb, g->bstart, g->mtmp, g->mkey, g->perm, g->trade_of, g->tinfo, g->giant_id,
-                     g->dep, g->ctrl);
+  if (!from_prepared) enqueue_matching(g, st);
   if (timed) (void)hipEventRecord(evs.ev[1], st);
-  if (g->debug_checks && g->ngiant > 0)
+  if (g->debug_checks && g->ngiant > 0 && !from_prepared)
     hipLaunchKernelGGL(k_check_giants_empty, dim3(1024), dim3(256), 0, st,
                        (int64_t)g->ngiant * (g->gwords >> 6), g->gsc, g->ctrl);
   if (last_step >= CB_STEP_DEPSCAN) {
     // 2. dependency scan + sources
-    if (g->nnz > 0)
+    if (g->nnz > 0 && !from_prepared)
       hipLaunchKernelGGL(k_depscan, dim3((unsigned)((g->nnz + kScanChunk - 1) / kScanChunk)), dim3(256),
                          0, st, n, g->nnz, g->rp, g->col, g->trade_of, g->tinfo, g->col_t, g->dep,
                          giant_sets(g), g->ctrl);
@@ -540,6 +575,7 @@ cb_status enqueue_round(cb_graph* g, hipStream_t st, int last_step, bool advance
     A.help_min = g->help_min;
     A.help_groups = g->help_groups;
     A.help_chunk = g->help_chunk;
+    A.idle_backoff = g->idle_backoff;
     A.big_lds_max = g->big_lds_max;
     A.nbig = effective_nbig(g);
     A.stack_cap = g->stack_cap;
@@ -552,24 +588,44 @@ cb_status enqueue_round(cb_graph* g, hipStream_t st, int last_step, bool advance
   if (last_step >= CB_STEP_TRADE && L > 0)
     hipLaunchKernelGGL(k_check_rows, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, n, g->rp,
                        g->out_cur, g->own_cur, g->ctrl);
+  if (advance)
+    hipLaunchKernelGGL(k_advance_rounds, dim3(grid_for(g->chains, 256, 64)), dim3(256), 0, st, g->ch_round,
+                       g->chains, 1u);
+  // the next round's matching, before the rebuild that scans for it
+  const bool lookahead = last_step == CB_STEP_REBUILD && g->fuse_next && (advance || single_next);
+  NextScan N{};
+  if (lookahead) {
+    if (single_next)
+      hipLaunchKernelGGL(k_set_chain, dim3(1), dim3(64), 0, st, g->ch_seed, g->ch_round, 0, next_seed, next_round);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(g->nb, 256, 1024)), dim3(256), 0, st, g->bcount, (int64_t)g->nb, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(g->nb, 256, 1024)), dim3(256), 0, st, g->bcur, (int64_t)g->nb, 0);
+    enqueue_matching(g, st);
+    N.tinfo = g->tinfo;
+    N.trade_of = g->trade_of;
+    N.col_t = g->col_t;
+    N.dep = g->dep;
+    N.gs = giant_sets(g);
+  }
   if (last_step >= CB_STEP_REBUILD && g->nnz > 0) {
-    // 4. rebuild: per-row ascending sort of col_out into col
+    // 4. rebuild: per-row ascending sort of col_out into col (+ the next round's scan)
     const int32_t* rs = g->rows;
     const int32_t* rm = g->rows + g->n_small;
     const int32_t* rb = g->rows + g->n_small + g->n_mid;
     if (g->n_small)
       hipLaunchKernelGGL(k_segsort_small, dim3(grid_for(g->n_small, 4, 65536)), dim3(256), 0, st,
-                         rs, g->n_small, g->rp, g->col_out, g->col, g->ctrl);
+                         rs, g->n_small, g->rp, g->col_out, g->col, N, g->ctrl);
     if (g->n_mid)
       hipLaunchKernelGGL(k_segsort_mid, dim3(grid_for(g->n_mid, 1, 65536)), dim3(256), 0, st,
-                         rm, g->n_mid, g->rp, g->col_out, g->col, g->keybits_node, g->ctrl);
+                         rm, g->n_mid, g->rp, g->col_out, g->col, g->keybits_node, N, g->ctrl);
     if (g->n_big)
       hipLaunchKernelGGL(k_segsort_big, dim3(grid_for(g->n_big, 1, 8192)), dim3(256), 0, st,
-                         rb, g->n_big, g->rp, g->col_out, g->col, g->keybits_node, g->ctrl);
+                         rb, g->n_big, g->rp, g->col_out, g->col, g->keybits_node, N, g->ctrl);
   }
-  if (advance)
-    hipLaunchKernelGGL(k_advance_rounds, dim3(grid_for(g->chains, 256, 64)), dim3(256), 0, st, g->ch_round,
-                       g->chains, 1u);
+  if (lookahead) {
+    g->prepared = true;
+    g->prep_seed = next_seed;
+    g->prep_round = next_round;
+  }
   if (timed) {
     (void)hipEventRecord(evs.ev[4], st);
     g->pending.push_back(evs);
@@ -894,7 +950,20 @@ void apply_tuned(cb_graph* g, const cb_tune_result& r) {
   g->help_min = r.help_min;
   g->help_chunk = r.help_chunk;
   g->nbig = r.big_workers;
+  g->stack_cap = r.local_stack;
+  g->idle_backoff = r.idle_backoff;
   g->opt_version++;
+}
+
+cb_tune_result current_options(const cb_graph* g) {
+  cb_tune_result r{};
+  r.small_max = g->small_max;
+  r.help_min = g->help_min;
+  r.help_chunk = g->help_chunk;
+  r.big_workers = effective_nbig(g);
+  r.local_stack = g->stack_cap;
+  r.idle_backoff = g->idle_backoff;
+  return r;
 }
 
 }  // namespace
@@ -928,14 +997,18 @@ cb_status global_trade(cb_graph* g, uint64_t seed, uint32_t round) {
   if (!g) return fail(CB_EINVAL, "null graph");
   if (g->chains != 1) return fail(CB_EINVAL, "global_trade needs a single-chain graph (use batch_run)");
   if (g->poisoned) return fail(CB_EPOISONED, "graph handle poisoned: %s", g->poison_msg);
-  hipLaunchKernelGGL(k_set_chain, dim3(1), dim3(64), 0, g->stream, g->ch_seed, g->ch_round, 0, seed, round);
-  return enqueue_round(g, g->stream, CB_STEP_REBUILD, false);
+  if (g->prepared && (g->prep_seed != seed || g->prep_round != round)) unprepare(g);
+  if (!g->prepared)
+    hipLaunchKernelGGL(k_set_chain, dim3(1), dim3(64), 0, g->stream, g->ch_seed, g->ch_round, 0, seed, round);
+  // prepare (seed, round + 1), the round a chain applies next
+  return enqueue_round(g, g->stream, CB_STEP_REBUILD, false, round != UINT32_MAX, seed, round + 1u);
 }
 
 cb_status global_trade_steps(cb_graph* g, uint64_t seed, uint32_t round, int32_t last_step) {
   if (!g) return fail(CB_EINVAL, "null graph");
   if (g->chains != 1) return fail(CB_EINVAL, "global_trade_steps needs a single-chain graph");
   if (g->poisoned) return fail(CB_EPOISONED, "graph handle poisoned: %s", g->poison_msg);
+  unprepare(g);
   hipLaunchKernelGGL(k_set_chain, dim3(1), dim3(64), 0, g->stream, g->ch_seed, g->ch_round, 0, seed, round);
   return enqueue_round(g, g->stream, last_step, false);
 }
@@ -1047,6 +1120,14 @@ cb_status graph_set_option(cb_graph* g, int32_t option, int64_t value) {
         return fail(CB_EINVAL, "help chunk must be a multiple of 64 in [64, 4096]");
       g->help_chunk = (int32_t)value;
       return CB_OK;
+    case CB_OPT_IDLE_BACKOFF:
+      if (value < 1 || value > 1024) return fail(CB_EINVAL, "idle back-off must be in [1, 1024]");
+      g->idle_backoff = (int32_t)value;
+      return CB_OK;
+    case CB_OPT_FUSE_NEXT:
+      if (value != 0 && value != 1) return fail(CB_EINVAL, "fuse must be 0 or 1");
+      g->fuse_next = value != 0;
+      return CB_OK;
     case CB_OPT_LOCAL_STACK:
       if (value < 0 || value > kStackCap) return fail(CB_EINVAL, "local stack must be in [0, 16]");
       g->stack_cap = (int32_t)value;
@@ -1145,7 +1226,9 @@ cb_status batch_run(cb_graph* g, uint32_t rounds) {
       if (s != CB_OK) return s;
     }
   } else {
-    if (!g->exec || g->exec_rounds != rounds || g->exec_version != g->opt_version) {
+    if (!g->exec || g->exec_rounds != rounds || g->exec_version != g->opt_version ||
+        g->exec_prepared != g->prepared) {
+      const bool start_prepared = g->prepared;
       drop_exec(g);
       if (!g->cap_stream && !HIP_OK(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking), "capture stream"))
         return fail(CB_EDEVICE, "%s", msg);
@@ -1167,6 +1250,10 @@ cb_status batch_run(cb_graph* g, uint32_t rounds) {
       }
       g->exec_rounds = rounds;
       g->exec_version = g->opt_version;
+      g->exec_prepared = start_prepared;
+    } else {
+      // replaying: the state moves through the same rounds as when captured
+      g->prepared = g->fuse_next;
     }
     if (!HIP_OK(hipGraphLaunch(g->exec, g->stream), "graph launch")) return poison(g, CB_EDEVICE, msg);
   }
@@ -1211,7 +1298,7 @@ cb_status graph_autotune(cb_graph* g, uint32_t trial_rounds, int32_t use_cache, 
     }
   }
   if (g->L == 0 || g->nnz == 0) {
-    *out = cb_tune_result{g->small_max, g->help_min, g->help_chunk, effective_nbig(g), 0.0, 0.0, 0, 0};
+    *out = current_options(g);
     return CB_OK;
   }
   char msg[256];
@@ -1227,6 +1314,7 @@ cb_status graph_autotune(cb_graph* g, uint32_t trial_rounds, int32_t use_cache, 
             HIP_OK(hipMemcpyAsync(g->ch_round_saved, g->ch_round, (size_t)g->chains * 4, hipMemcpyDeviceToDevice, st), "save rounds");
   // time trial_rounds rounds from the saved state under the current options
   auto trial = [&](double* ms_out) -> cb_status {
+    unprepare(g);
     if (!HIP_OK(hipMemcpyAsync(g->col, saved, (size_t)g->nnz * 4, hipMemcpyDeviceToDevice, st), "restore col") ||
         !HIP_OK(hipMemcpyAsync(g->ch_round, g->ch_round_saved, (size_t)g->chains * 4, hipMemcpyDeviceToDevice, st), "restore rounds") ||
         !HIP_OK(hipEventRecord(e0, st), "event"))
@@ -1243,7 +1331,7 @@ cb_status graph_autotune(cb_graph* g, uint32_t trial_rounds, int32_t use_cache, 
     *ms_out = (double)ms / trial_rounds;
     return CB_OK;
   };
-  cb_tune_result best{g->small_max, g->help_min, g->help_chunk, effective_nbig(g), 0.0, 0.0, 0, 0};
+  cb_tune_result best = current_options(g);
   if (!ok) s = fail(CB_EDEVICE, "%s", msg);
   if (s == CB_OK) {
     apply_tuned(g, best);
@@ -1253,21 +1341,30 @@ cb_status graph_autotune(cb_graph* g, uint32_t trial_rounds, int32_t use_cache, 
     best.ms_per_round = best.default_ms_per_round = ms;
     best.evaluated = 2;
   }
-  // coordinate descent over the wavefront/workgroup threshold, the size from
-  // which write phases are shared, their chunk size and the workgroup workers
-  const int32_t small_set[] = {128, 256, 384, 512};
-  const int32_t help_set[] = {1024, 2048, 4096, 8192, 0};
-  const int32_t chunk_set[] = {64, 128, 256, 512};
-  const int32_t big_set[] = {16, 32, 48, 64};
-  for (int param = 0; param < 4 && s == CB_OK; ++param) {
-    const int32_t* set = param == 0 ? small_set : param == 1 ? help_set : param == 2 ? chunk_set : big_set;
-    const int count = param == 1 ? 5 : 4;
-    for (int i = 0; i < count && s == CB_OK; ++i) {
+  // coordinate descent over the idle wavefronts' back-off, their local stack
+  // of ready trades, the wavefront/workgroup threshold, the size from which
+  // write phases are shared, their chunk size and the workgroup workers
+  struct Param {
+    int32_t cb_tune_result::*field;
+    int32_t values[6];
+    int count;
+  };
+  const Param params[] = {
+      {&cb_tune_result::idle_backoff, {2, 8, 32, 128}, 4},
+      {&cb_tune_result::local_stack, {0, 1, 2, 4, 8, 16}, 6},
+      {&cb_tune_result::small_max, {128, 256, 384, 512}, 4},
+      {&cb_tune_result::help_min, {1024, 2048, 4096, 8192, 0}, 5},
+      {&cb_tune_result::help_chunk, {64, 128, 256, 512}, 4},
+      {&cb_tune_result::big_workers, {16, 32, 48, 64}, 4},
+  };
+  for (const Param& P : params) {
+    if (s != CB_OK) break;
+    for (int i = 0; i < P.count && s == CB_OK; ++i) {
       cb_tune_result cand = best;
-      int32_t* field = param == 0 ? &cand.small_max : param == 1 ? &cand.help_min
-                     : param == 2 ? &cand.help_chunk : &cand.big_workers;
-      if (*field == set[i]) continue;
-      if (param == 3 && set[i] > g->nbig_alloc) continue;
+      int32_t* field = &(cand.*P.field);
+      if (*field == P.values[i]) continue;
+      if (P.field == &cb_tune_result::big_workers && P.values[i] > g->nbig_alloc) continue;
+      const int32_t* set = P.values;
       *field = set[i];
       apply_tuned(g, cand);
       double ms = 0;
@@ -1282,6 +1379,7 @@ cb_status graph_autotune(cb_graph* g, uint32_t trial_rounds, int32_t use_cache, 
     }
   }
   // back to the state before tuning, with the best options
+  unprepare(g);
   (void)hipMemcpyAsync(g->col, saved, (size_t)g->nnz * 4, hipMemcpyDeviceToDevice, st);
   (void)hipMemcpyAsync(g->ch_round, g->ch_round_saved, (size_t)g->chains * 4, hipMemcpyDeviceToDevice, st);
   (void)hipStreamSynchronize(st);

@@ -189,6 +189,7 @@ struct TradeArgs {
   int32_t help_min;         // trades of at least this many items open their write phase (0: none)
   int32_t help_groups;      // workgroup b helps owners j with j % help_groups == b % help_groups
   int32_t help_chunk;       // items per claimed chunk of a shared write phase (a multiple of 64)
+  int32_t idle_backoff;     // longest sleep of an idle wavefront worker, in units of 2048 cycles
   int32_t big_lds_max;
   int32_t nbig;
   int32_t stack_cap;
@@ -225,12 +226,25 @@ __global__ void k_trade(TradeArgs A);
 __global__ void k_check_giants_empty(int64_t total_sb, const int32_t* sc, int32_t* ctrl);
 __global__ void k_check_rows(int64_t n, const int64_t* rp, const int32_t* out_cur,
                              const int32_t* own_cur, int32_t* ctrl);
+// The next round's dependency scan, done by the rebuild as it writes each
+// row (the next round's matching is already in tinfo / trade_of; tinfo null:
+// no scan). Per entry e of row x with neighbour y: col_t[e] = tinfo[y]; if x
+// is matched, y's trade comes before x's adds one to dep[trade_of[x]], and a
+// giant x puts every other neighbour y into its bitmap set.
+struct NextScan {
+  const int32_t* tinfo;
+  const int32_t* trade_of;
+  int32_t* col_t;
+  int32_t* dep;
+  GiantSets gs;
+};
 __global__ void k_segsort_small(const int32_t* rows, int64_t nrows, const int64_t* rp,
-                                const int32_t* src, int32_t* dst, const int32_t* ctrl);
+                                const int32_t* src, int32_t* dst, NextScan N, const int32_t* ctrl);
 __global__ void k_segsort_mid(const int32_t* rows, int64_t nrows, const int64_t* rp,
-                              const int32_t* src, int32_t* dst, int keybits, const int32_t* ctrl);
+                              const int32_t* src, int32_t* dst, int keybits, NextScan N,
+                              const int32_t* ctrl);
 __global__ void k_segsort_big(const int32_t* rows, int64_t nrows, const int64_t* rp,
-                              int32_t* src, int32_t* dst, int keybits, const int32_t* ctrl);
+                              int32_t* src, int32_t* dst, int keybits, NextScan N, const int32_t* ctrl);
 __global__ void k_classify_rows(int64_t n, const int64_t* rp, int32_t* rows, int64_t base1,
                                 int64_t base2, unsigned long long* cur);
 __global__ void k_copy_shift(int32_t* dst, const int32_t* src, int64_t count, int32_t delta);

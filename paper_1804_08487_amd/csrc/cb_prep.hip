@@ -339,11 +339,42 @@ __global__ void k_check_rows(int64_t n, const int64_t* rp, const int32_t* out_cu
 
 // ---------------------------------------------------------------- rebuild
 // Row x of src (its entries in any order) is written ascending to row x of
-// dst. Size classes are fixed at upload because degrees never change.
+// dst. Size classes are fixed at upload because degrees never change. With a
+// NextScan the rebuild also does the next round's dependency scan of every
+// entry it writes (the same counts, trade information and bitmap seeds as
+// k_depscan), so that scan does not read the adjacency again.
+
+struct RowScan {
+  int32_t k = kUnmatched;   // next round's trade of the row's node
+  int32_t gi = -1;          // its giant index
+};
+__device__ __forceinline__ RowScan row_scan(const NextScan& N, int32_t x) {
+  RowScan r;
+  if (N.tinfo) {
+    r.k = N.trade_of[x];
+    r.gi = N.gs.bm ? N.gs.giant_id[x] : -1;
+  }
+  return r;
+}
+// Entry e (neighbour y) of a row: 1 if it counts towards the row's trade's
+// dependencies.
+__device__ __forceinline__ int32_t scan_entry(const NextScan& N, const RowScan& r, int64_t e, int32_t y) {
+  const int32_t ti = N.tinfo[y];
+  N.col_t[e] = ti;
+  if (r.k == kUnmatched) return 0;
+  if (tinfo_trade(ti) < r.k) return 1;
+  if (r.gi >= 0) giant_insert(N.gs, r.gi, y);
+  return 0;
+}
+// Wave-level sum of the counts, added once per wavefront (every lane active).
+__device__ __forceinline__ void add_dep(const NextScan& N, const RowScan& r, int32_t cnt) {
+  const int32_t tot = wave_sum(cnt);
+  if (lane_id() == 0 && tot && r.k != kUnmatched) atomicAdd(&N.dep[r.k], tot);
+}
 
 __global__ void __launch_bounds__(256)
 k_segsort_small(const int32_t* rows, int64_t nrows, const int64_t* rp, const int32_t* src,
-                int32_t* dst, const int32_t* ctrl) {
+                int32_t* dst, NextScan N, const int32_t* ctrl) {
   if (ctrl[cw(kCwErr)]) return;
   const int l = lane_id();
   const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -365,6 +396,10 @@ k_segsort_small(const int32_t* rows, int64_t nrows, const int64_t* rp, const int
       }
     }
     if (l < d) dst[b + l] = v;
+    if (N.tinfo) {
+      const RowScan rs = row_scan(N, x);
+      add_dep(N, rs, l < d ? scan_entry(N, rs, b + l, v) : 0);
+    }
   }
 }
 
@@ -377,7 +412,7 @@ constexpr int kSegMidPer = kSegMidMax / 256;   // ids per thread
 constexpr int32_t kSegBucketMax = 256;
 __global__ void __launch_bounds__(256)
 k_segsort_mid(const int32_t* rows, int64_t nrows, const int64_t* rp, const int32_t* src,
-              int32_t* dst, int keybits, const int32_t* ctrl) {
+              int32_t* dst, int keybits, NextScan N, const int32_t* ctrl) {
   __shared__ int32_t buf[kSegMidMax];
   __shared__ int32_t cnt[kSegMidMax / 16];
   __shared__ int32_t scan[256 / 64 + 1];
@@ -420,6 +455,12 @@ k_segsort_mid(const int32_t* rows, int64_t nrows, const int64_t* rp, const int32
       __syncthreads();
       block_bitonic_sort(buf, (uint32_t)d);
       for (int32_t i = tid; i < d; i += blockDim.x) dst[b + i] = buf[i];
+      if (N.tinfo) {
+        const RowScan rs = row_scan(N, x);
+        int32_t cnt = 0;
+        for (int32_t i = tid; i < d; i += blockDim.x) cnt += scan_entry(N, rs, b + i, buf[i]);
+        add_dep(N, rs, cnt);
+      }
       __syncthreads();
       continue;
     }
@@ -430,6 +471,8 @@ k_segsort_mid(const int32_t* rows, int64_t nrows, const int64_t* rp, const int32
       if (tid + q * 256 < d) buf[atomicAdd(&cnt[bucket(v[q])], 1)] = v[q];
     __syncthreads();
     // cnt[q] is now the end of bucket q and the start of bucket q + 1
+    const RowScan rs = row_scan(N, x);
+    int32_t dcnt = 0;
     for (int32_t i = tid; i < d; i += blockDim.x) {
       const int32_t e = buf[i];
       const int32_t q = bucket(e);
@@ -441,14 +484,16 @@ k_segsort_mid(const int32_t* rows, int64_t nrows, const int64_t* rp, const int32
         rk += (y < e || (y == e && j < i)) ? 1 : 0;
       }
       dst[b + rk] = e;
+      if (N.tinfo) dcnt += scan_entry(N, rs, b + rk, e);
     }
+    if (N.tinfo) add_dep(N, rs, dcnt);
     __syncthreads();
   }
 }
 
 __global__ void __launch_bounds__(256)
 k_segsort_big(const int32_t* rows, int64_t nrows, const int64_t* rp, int32_t* src,
-              int32_t* dst, int keybits, const int32_t* ctrl) {
+              int32_t* dst, int keybits, NextScan N, const int32_t* ctrl) {
   __shared__ RadixLds R;
   if (ctrl[cw(kCwErr)]) return;
   for (int64_t r = blockIdx.x; r < nrows; r += gridDim.x) {
@@ -458,6 +503,12 @@ k_segsort_big(const int32_t* rows, int64_t nrows, const int64_t* rp, int32_t* sr
     int32_t* out = block_radix_sort<int32_t>(src + b, dst + b, d, keybits, R);
     if (out != dst + b) {
       for (int64_t i = threadIdx.x; i < d; i += blockDim.x) dst[b + i] = out[i];
+    }
+    if (N.tinfo) {
+      const RowScan rs = row_scan(N, x);
+      int32_t cnt = 0;
+      for (int64_t i = threadIdx.x; i < d; i += blockDim.x) cnt += scan_entry(N, rs, b + i, out[i]);
+      add_dep(N, rs, cnt);
     }
     __syncthreads();
   }

@@ -993,11 +993,11 @@ __device__ void wave_flush(const TradeArgs& A, WaveState& S) {
 constexpr int32_t kFlushEvery = 32;   // trades between progress flushes
 // An idle wavefront worker scans this many ready-queue shards per poll
 // (rotating; the many idle wavefronts cover every shard between them) and
-// sleeps up to kSmallMaxBackoff * 32 * 64 cycles (about 110 us) between
-// polls, which keeps the polls of the shared control words from crowding the
-// memory side.
+// sleeps up to A.idle_backoff * 32 * 64 cycles (about 110 us at the default
+// 128) between polls, which keeps the polls of the shared control words from
+// crowding the memory side on large graphs; small graphs, where ready trades
+// would wait for a sleeping poller, want a short back-off.
 constexpr int kQsScan = 1;
-constexpr int32_t kSmallMaxBackoff = 128;
 
 __device__ __forceinline__ void small_worker(const TradeArgs& A, WaveLds& W) {
   const int l = lane_id();
@@ -1045,7 +1045,7 @@ __device__ __forceinline__ void small_worker(const TradeArgs& A, WaveLds& W) {
         continue;
       }
       idle_backoff(backoff);
-      backoff = backoff < kSmallMaxBackoff ? backoff * 2 : kSmallMaxBackoff;
+      backoff = backoff < A.idle_backoff ? backoff * 2 : A.idle_backoff;
       continue;
     }
     backoff = 1;

@@ -232,3 +232,66 @@ def test_upload_validation_rejects(name):
     with pytest.raises(cb.CurveballError) as e:
         cb.Graph(rp, col)
     assert e.value.status == cb.CB_ENOTSIMPLE
+
+
+# ---- the next round prepared by the rebuild (cross-round fusion)
+
+@pytest.mark.parametrize("giant", [0, 20])
+def test_prepared_round_state_equals_oracle(orc, giant):
+    """After a full round the next round's matching and dependency counts
+    (computed by the lookahead matching and the rebuild's scan) equal the
+    oracle's for (seed, round + 1) on the new graph."""
+    rp, col = graphgen.pld_graph(3000, 2, 300, 2.0, 11)
+    n = len(rp) - 1
+    g = cb.Graph(rp, col)
+    g.set_option(cb.OPT_GIANT_DEG, giant)
+    ref = col
+    for r in range(3):
+        g.global_trade(4, r)
+        ref, _ = orc.global_trade(rp, ref, 4, r)
+        assert np.array_equal(g.download(), ref)
+        o_perm, o_tof = orc.matching(n, 4, r + 1)
+        assert np.array_equal(g.state(cb.STATE_PERM), o_perm), f"round {r + 1} perm"
+        assert np.array_equal(g.state(cb.STATE_TRADE_OF), o_tof), f"round {r + 1} trade_of"
+        assert np.array_equal(g.state(cb.STATE_DEP), orc.depcount(rp, ref, o_tof, o_perm)), f"round {r + 1} dep"
+    g.close()
+
+
+@pytest.mark.parametrize("giant", [0, 20])
+def test_rounds_out_of_order_and_fusion_off(orc, giant):
+    """A call that is not the prepared (seed, round + 1) starts over (its bitmap
+    seeds cleared); fusion off gives the same bytes."""
+    rp, col = graphgen.pld_graph(3001, 3, 400, 1.9, 12)
+    order = [(7, 0), (7, 1), (7, 5), (9, 6), (7, 2), (7, 3)]
+    results = []
+    for fuse in (1, 0):
+        g = cb.Graph(rp, col)
+        g.set_option(cb.OPT_GIANT_DEG, giant)
+        g.set_option(cb.OPT_FUSE_NEXT, fuse)
+        ref = col
+        for seed, r in order:
+            g.global_trade(seed, r)
+            ref, _ = orc.global_trade(rp, ref, seed, r)
+            assert np.array_equal(g.download(), ref), f"fuse {fuse} seed {seed} round {r}"
+        results.append(g.download())
+        g.close()
+    assert np.array_equal(results[0], results[1])
+
+
+def test_batch_fusion_off_equals_on(orc):
+    gs = [graphgen.pld_graph(700 + 91 * c, 2, 90, 2.0, 140 + c) for c in range(6)]
+    seeds = [11 * c + 5 for c in range(6)]
+    out = []
+    for fuse in (1, 0):
+        b = cb.Batch(gs, seeds)
+        b.set_option(cb.OPT_FUSE_NEXT, fuse)
+        b.set_option(cb.OPT_GIANT_DEG, 30)
+        b.run(3)
+        b.run(3)
+        out.append([b.download_chain(c) for c in range(6)])
+        b.close()
+    for c, (rp, col) in enumerate(gs):
+        x = col
+        for r in range(6):
+            x, _ = orc.global_trade(rp, x, seeds[c], r)
+        assert np.array_equal(out[0][c], x) and np.array_equal(out[1][c], x), f"chain {c}"
