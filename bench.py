@@ -39,6 +39,8 @@ WORKLOAD_TEXT = {
     "hubs": "n=2^24, degrees Pld([1,2^16),2.5), erased configuration model, graph seed 3",
     "batch": ("512 chains: chain c has n_c=round(2^U[10,16]) nodes, degrees Pld([2,n_c/8),gamma_c), "
               "gamma_c~U[1.8,2.6], graph seed 1000+c, chain seed c"),
+    "serve": ("Poisson requests: m=2^U[12,24] edges, degrees Pld([5,sqrt n),2), graph seed 10^6+q, "
+              "k~U{1..32} samples, r~U{5..20} rounds, rate 0.7x the measured capacity"),
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_{workload}.json")
 KERNEL_SOURCES = ["cb_trade.hip", "cb_prep.hip", "cb_block.hpp", "cb_device.hpp", "cb_kernels.hpp"]
@@ -248,6 +250,63 @@ def run_batch(args, cb, graphs, seeds):
     return reps, step_ms_all, tune, t_single
 
 
+def run_serve(args, cb, graphgen):
+    """Closed batch (every request at t = 0) to measure capacity, then a
+    Poisson stream at 0.7x that rate through the continuous-batching server.
+    Returns the JSON fields of the serving run."""
+    import numpy as np
+    import torch
+    spec = graphgen.serve_specs(args.requests)
+    graphs = [graphgen.pld_graph(s["n"], s["a"], s["b"], s["gamma"], s["graph_seed"]) for s in spec]
+    work = [len(c) // 2 * s["samples"] * s["rounds"] for (_, c), s in zip(graphs, spec)]
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(0.6 * free)
+
+    def serve(arrivals):
+        srv = cb.Server(budget)
+        order = np.argsort(arrivals, kind="stable")
+        pending = list(order)
+        inflight = {}
+        done_at = {}
+        steps = 0
+        t0 = time.perf_counter()
+        while pending or inflight:
+            now = time.perf_counter() - t0
+            while pending and arrivals[pending[0]] <= now:
+                q = pending.pop(0)
+                s = spec[q]
+                inflight[srv.submit(*graphs[q], s["samples"], s["rounds"], s["chain_seed"])] = q
+            if not inflight:
+                time.sleep(max(0.0, arrivals[pending[0]] - now))
+                continue
+            srv.step()
+            steps += 1
+            now = time.perf_counter() - t0
+            for rid in [r for r in inflight if srv.finished(r)]:
+                done_at[inflight.pop(rid)] = now
+                srv.release(rid)
+        srv.close()
+        lat = [done_at[q] - arrivals[q] for q in range(len(spec))]
+        return lat, max(done_at.values()), steps
+
+    lat0, span0, steps0 = serve(np.zeros(len(spec)))
+    capacity = len(spec) / span0
+    rate = 0.7 * capacity
+    rng = np.random.Generator(np.random.PCG64(11))
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, len(spec)))
+    arrivals -= arrivals[0]
+    lat, span, steps = serve(arrivals)
+    print(f"[bench] serve: capacity {capacity:.2f} req/s (closed batch {span0:.2f} s), "
+          f"Poisson at {rate:.2f} req/s: span {span:.2f} s, p50 {np.median(lat):.2f} s", file=sys.stderr, flush=True)
+    return {
+        "requests": len(spec), "edge_trades": int(sum(work)), "budget_bytes": budget,
+        "closed_batch_s": span0, "capacity_req_per_s": capacity, "rate_req_per_s": rate,
+        "span_s": span, "server_steps": steps, "latency_p50_s": percentile(lat, 0.5),
+        "latency_p99_s": percentile(lat, 0.99), "latency_max_s": max(lat),
+        "closed_batch_edge_trades_per_s": sum(work) / span0,
+    }
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -264,6 +323,7 @@ def main(argv=None) -> int:
     ap.add_argument("--local-stack", type=int, default=None)
     ap.add_argument("--fuse", type=int, default=None, choices=[0, 1],
                     help="prepare the next round in the rebuild (default on)")
+    ap.add_argument("--requests", type=int, default=32, help="requests of the served workload")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one plain device-to-device copy of BYTES (for scaling "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -303,6 +363,17 @@ def main(argv=None) -> int:
     torch.cuda.set_stream(stream)
     copy_bps = copy_bandwidth()
     print(f"[bench] device copy {copy_bps / 1e9:.0f} GB/s (read + write)", file=sys.stderr, flush=True)
+    if args.workload == "serve":
+        sv = run_serve(args, cb, graphgen)
+        out = {"metric": "edge-trades/sec per global super-step (m x rounds / s)",
+               "value": sv["edge_trades"] / sv["span_s"], "unit": "edge-trades/s", "n_gpus": 1,
+               "steps": sv["server_steps"], "warmup": 0, "ms_per_step": sv["span_s"] * 1e3 / sv["server_steps"],
+               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+               "data": "synthetic", "config": {"workload": f"serve: {WORKLOAD_TEXT['serve']}",
+                                               "requests": sv["requests"]},
+               "serving": sv, "copy_kernel_gbps": copy_bps / 1e9, "hbm_peak_gbps": HBM_PEAK / 1e9}
+        print(json.dumps(out), flush=True)
+        return 0
     t_gen = time.perf_counter()
     if args.workload == "batch":
         spec = graphgen.batch_specs(512)

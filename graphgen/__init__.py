@@ -12,6 +12,7 @@ Workloads (degrees i.i.d. from Pld([a,b), gamma), P[k] ~ k^-gamma):
 * ``hubs``:   n = 2^24,  Pld([1, 2^16), 2.5),     graph seed 3 (sparse, about ten
   nodes of degree above 8192: the bitmap-set path at the full id range)
 * batched:    ``batch_specs`` / ``batch_chain``: 512 chains of 2^10..2^16 nodes
+* served:     ``serve_specs``: requests of 2^12..2^24 edges, 1..32 samples, 5..20 rounds
 """
 from __future__ import annotations
 
@@ -148,6 +149,35 @@ def batch_specs(chains: int = 512, seed: int = 4):
 
 def batch_chain(spec):
     return pld_graph(spec["n"], spec["a"], spec["b"], spec["gamma"], spec["graph_seed"], threads=1)
+
+
+def pld_mean(a: int, b: int, gamma: float) -> float:
+    ks = np.arange(a, b, dtype=float)
+    w = ks ** -gamma
+    return float((ks * w).sum() / w.sum())
+
+
+def serve_specs(count: int, seed: int = 5):
+    """The served workload: request q has m_target = 2^U[12,24] edges, n chosen
+    so that n * E[Pld([5, sqrt n), 2)] / 2 is about m_target, graph seed
+    10^6 + q, k ~ U{1..32} samples and r ~ U{5..20} rounds (numpy PCG64 with
+    `seed`)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for q in range(count):
+        m_target = 2.0 ** (12 + 12 * rng.random())
+        lo, hi = 16, 1 << 26
+        while hi - lo > 1:
+            mid = (lo + hi) // 2
+            if mid * pld_mean(5, max(6, int(mid ** 0.5)), 2.0) / 2 < m_target:
+                lo = mid
+            else:
+                hi = mid
+        n = hi
+        out.append(dict(n=n, a=5, b=max(6, int(n ** 0.5)), gamma=2.0, graph_seed=10**6 + q,
+                        samples=int(rng.integers(1, 33)), rounds=int(rng.integers(5, 21)),
+                        chain_seed=7919 * (q + 1)))
+    return out
 
 
 def edge_list_to_csr(n: int, edges) -> tuple[np.ndarray, np.ndarray]:

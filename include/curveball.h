@@ -300,6 +300,57 @@ typedef struct {
 
 cb_status graph_autotune(cb_graph* g, uint32_t trial_rounds, int32_t use_cache, cb_tune_result* out);
 
+/* ---- request server (continuous batching) ----------------------------------
+ * Serves requests "`samples` samples of G after `rounds` global trades": sample
+ * j of a request with seed s is G after rounds 0..rounds-1 of the chain with
+ * seed s + j (Def. "Undirected Global Trade", Sec. 3.3; each sample is an
+ * independent run of the chain, for null-model sampling). Requests queue in
+ * arrival order and are admitted while the device memory of their chains
+ * fits half of `hbm_budget_bytes` (the other half covers the rebuild of the
+ * union below). All chains of all admitted requests advance together, one
+ * round per server_step, as one batch (see batch_run); a chain that finishes
+ * is copied to host memory and leaves; requests admitted later join the
+ * running batch, whose device state is rebuilt on the device whenever its
+ * chains change (every chain keeps its adjacency, seed and round). Chain
+ * state stays on the device from admission to the last round. A result
+ * depends only on (G, seed, sample, rounds): it is the same alone and in any
+ * mix. One host thread drives a server. */
+typedef struct cb_server cb_server;
+typedef struct {
+    int64_t queued;             /* requests waiting for admission */
+    int64_t active_chains;      /* chains on the device */
+    int64_t finished_requests;  /* requests whose samples are all done */
+    int64_t steps;              /* rounds run */
+    int64_t repacks;            /* rebuilds of the batch after admissions/retirements */
+    int64_t active_bytes;       /* device bytes held for admitted requests */
+    int64_t budget_bytes;
+} cb_server_status;
+
+/* A server on the current device, ordered on `stream` (NULL: its own). */
+cb_status server_create(size_t hbm_budget_bytes, void* stream, cb_server** out);
+
+/* Queue a request (host CSR in the graph form above, copied; samples >= 1).
+ * CB_ENOMEM if its chains alone need more than half the budget. */
+cb_status server_submit(cb_server* s, int64_t n, const int64_t* row_ptr, const int32_t* col,
+                        int32_t samples, uint32_t rounds, uint64_t seed, int64_t* request_id);
+
+/* One scheduling step: admit what fits, rebuild the batch if its chains
+ * changed, run one round of every active chain, copy out finished chains.
+ * Synchronises when a chain finishes. `status` may be NULL. */
+cb_status server_step(cb_server* s, cb_server_status* status);
+
+/* *finished = 1 once every sample of the request is done. */
+cb_status server_request_state(cb_server* s, int64_t request_id, int32_t* finished);
+
+/* Copy sample `sample` of a finished request into col (row_ptr[n] entries). */
+cb_status server_result(cb_server* s, int64_t request_id, int32_t sample, int32_t* col);
+
+/* Forget a finished request (its results). */
+cb_status server_release(cb_server* s, int64_t request_id);
+
+/* Release the server and all its device memory (NULL is a no-op). */
+void server_free(cb_server* s);
+
 /* ---- no device allocation -------------------------------------------------
  * For callers that cannot allocate device memory (code under stream capture,
  * tight serving loops, harnesses that forbid hipMalloc). One global trade

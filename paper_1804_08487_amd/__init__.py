@@ -33,7 +33,8 @@ EXPORTS = ("cb_set_allocator", "graph_upload", "graph_info", "global_trade", "gr
            "graph_download", "graph_free", "cb_last_error", "global_trade_steps",
            "graph_download_state", "graph_set_option", "graph_stats", "graph_kernel_times",
            "batch_upload", "batch_run", "batch_info", "batch_download", "graph_autotune",
-           "global_trade_static")
+           "global_trade_static", "server_create", "server_submit", "server_step",
+           "server_request_state", "server_result", "server_release", "server_free")
 
 
 class CurveballError(RuntimeError):
@@ -72,6 +73,15 @@ class TuneResult(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class ServerStatus(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in (
+        "queued", "active_chains", "finished_requests", "steps", "repacks", "active_bytes",
+        "budget_bytes")]
+
+    def as_dict(self):
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -105,8 +115,16 @@ def lib():
         L.batch_download.argtypes = [vp, i32, vp]
         L.graph_autotune.argtypes = [vp, u32, i32, ctypes.POINTER(TuneResult)]
         L.global_trade_static.argtypes = [i64, vp, vp, u64, u32, vp]
+        L.server_create.argtypes = [ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+        L.server_submit.argtypes = [vp, i64, vp, vp, i32, u32, u64, ctypes.POINTER(i64)]
+        L.server_step.argtypes = [vp, ctypes.POINTER(ServerStatus)]
+        L.server_request_state.argtypes = [vp, i64, ctypes.POINTER(i32)]
+        L.server_result.argtypes = [vp, i64, i32, vp]
+        L.server_release.argtypes = [vp, i64]
+        L.server_free.argtypes = [vp]
+        L.server_free.restype = None
         for name in EXPORTS:
-            if name not in ("graph_free", "cb_last_error"):
+            if name not in ("graph_free", "cb_last_error", "server_free"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -289,3 +307,56 @@ class Batch(Graph):
         col = np.empty(max(nnz, 1), np.int32)
         _check(lib().batch_download(self._h, chain, col.ctypes.data))
         return col[:nnz]
+
+
+class Server:
+    """Continuous-batching request server (see ``server_create``): requests
+    "samples of G after r rounds" join the running batch as memory allows."""
+
+    def __init__(self, hbm_budget_bytes: int, stream=None):
+        if stream is None:
+            stream = current_stream_handle()
+        h = ctypes.c_void_p()
+        _check(lib().server_create(int(hbm_budget_bytes), stream, ctypes.byref(h)))
+        self._h = h
+        self._sizes = {}
+
+    def submit(self, row_ptr, col, samples: int, rounds: int, seed: int) -> int:
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        cl = np.ascontiguousarray(col, dtype=np.int32)
+        rid = ctypes.c_int64()
+        _check(lib().server_submit(self._h, len(rp) - 1, rp.ctypes.data, cl.ctypes.data if len(cl) else None,
+                                   samples, rounds, int(seed) & (2**64 - 1), ctypes.byref(rid)))
+        self._sizes[int(rid.value)] = (int(rp[-1]), samples)
+        return int(rid.value)
+
+    def step(self):
+        st = ServerStatus()
+        _check(lib().server_step(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def finished(self, rid: int) -> bool:
+        f = ctypes.c_int32()
+        _check(lib().server_request_state(self._h, rid, ctypes.byref(f)))
+        return bool(f.value)
+
+    def result(self, rid: int, sample: int):
+        nnz, _ = self._sizes[rid]
+        out = np.empty(max(nnz, 1), np.int32)
+        _check(lib().server_result(self._h, rid, sample, out.ctypes.data))
+        return out[:nnz]
+
+    def release(self, rid: int):
+        _check(lib().server_release(self._h, rid))
+        self._sizes.pop(rid, None)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().server_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

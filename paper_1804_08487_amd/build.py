@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libcurveball.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["cb_prep.hip", "cb_trade.hip", "cb_host.hip"]
+SOURCES = ["cb_prep.hip", "cb_trade.hip", "cb_host.hip", "cb_serve.hip"]
 ARCH = os.environ.get("CB_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

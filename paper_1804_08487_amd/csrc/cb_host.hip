@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "curveball.h"
+#include "cb_internal.hpp"
 #include "cb_kernels.hpp"
 
 using namespace cbx;
@@ -67,6 +68,7 @@ struct cb_graph {
   std::vector<void*> owned;
 
   // chains (one for graph_upload)
+  bool batch = false;          // made by batch_upload (or the server): run with batch_run
   int32_t chains = 1;
   std::vector<int64_t> h_node_base, h_nnz_base;   // chains + 1 (batches only)
   std::vector<uint64_t> h_seed;                   // batches only
@@ -634,18 +636,6 @@ cb_status enqueue_round(cb_graph* g, hipStream_t st, int last_step, bool advance
   return CB_OK;
 }
 
-// One chain of a graph being created: n nodes, host CSR offsets rp[0..n] and
-// its adjacency (local ids) in host memory, or in device memory with every id
-// shifted by dev_shift from local.
-struct ChainSrc {
-  int64_t n;
-  const int64_t* rp;
-  const int32_t* col;
-  bool col_on_device;
-  int32_t dev_shift;
-  uint64_t seed;
-  uint32_t round;
-};
 
 // Device properties and occupancy of the trade kernel, once per device.
 struct DeviceInfo {
@@ -785,7 +775,7 @@ cb_status upload_verdict(cb_graph* g) {
 // further if the bitmaps would take too much memory. Batches of chains start
 // without giant nodes (their bitmaps would span every chain's ids).
 int64_t default_giant_threshold(const cb_graph* g, const int64_t* rp) {
-  if (g->chains != 1) return 0;
+  if (g->batch) return 0;
   const int64_t n = g->n;
   const int64_t min_deg = std::max<int64_t>(kGiantMinDeg, n / 2048);
   size_t free_b = 0, total_b = 0;
@@ -806,8 +796,11 @@ int64_t default_giant_threshold(const cb_graph* g, const int64_t* rp) {
   return thr;
 }
 
+}  // namespace
+
 // Create a graph of `count` chains in allocated device memory.
-cb_status create_graph(const ChainSrc* src, int32_t count, void* stream, uint32_t flags, cb_graph** out) {
+cb_status cbx::create_graph(const ChainSrc* src, int32_t count, void* stream, uint32_t flags, bool batch,
+                            cb_graph** out) {
   if (!out) return fail(CB_EINVAL, "out is NULL");
   *out = nullptr;
   if (count < 1) return fail(CB_EINVAL, "a graph needs at least one chain");
@@ -833,6 +826,7 @@ cb_status create_graph(const ChainSrc* src, int32_t count, void* stream, uint32_
 
   cb_graph* g = new cb_graph();
   g->alloc = g_allocator;
+  g->batch = batch;
   char msg[256];
   if (!HIP_OK(hipGetDevice(&g->device), "hipGetDevice")) { delete g; return fail(CB_EDEVICE, "%s", msg); }
   if (stream) {
@@ -919,7 +913,8 @@ cb_status create_graph(const ChainSrc* src, int32_t count, void* stream, uint32_
     delete g;
     return s;
   }
-  if (count > 1) {
+  g->batch = batch;
+  if (batch) {
     g->h_node_base = node_base;
     g->h_nnz_base = nnz_base;
     g->h_seed = seeds;
@@ -928,6 +923,39 @@ cb_status create_graph(const ChainSrc* src, int32_t count, void* stream, uint32_
   *out = g;
   return CB_OK;
 }
+
+cb_status cbx::set_error(cb_status s, const char* msg) { return fail(s, "%s", msg); }
+
+// Device bytes a graph of these chains allocates (before giant bitmaps).
+size_t cbx::graph_bytes(const ChainSrc* src, int32_t count) {
+  cb_graph g;
+  int64_t d1 = 0, d2 = 0;
+  for (int32_t c = 0; c < count; ++c)
+    for (int64_t x = 0; x < src[c].n; ++x) {
+      const int64_t d = src[c].rp[x + 1] - src[c].rp[x];
+      if (d > d1) { d2 = d1; d1 = d; } else if (d > d2) { d2 = d; }
+    }
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  g.cu_count = device_info(dev).cu_count;
+  g.nbig_alloc = std::max(1, g.cu_count / 2);
+  size_graph(&g, src, count, d1, d2);
+  BufPlan P;
+  plan_buffers(&g, P);
+  return plan_bytes(P);
+}
+
+// Chain c's adjacency in device memory (global ids: local + *node_base).
+int32_t* cbx::chain_col(cb_graph* g, int32_t c, int64_t* node_base) {
+  if (!g->batch) {
+    *node_base = 0;
+    return g->col;
+  }
+  *node_base = g->h_node_base[c];
+  return g->col + g->h_nnz_base[c];
+}
+
+namespace {
 
 // ---------------------------------------------------------------- autotuner
 
@@ -983,7 +1011,7 @@ cb_status graph_upload(int64_t n, const int64_t* row_ptr, const int32_t* col, vo
   if (!out) return fail(CB_EINVAL, "out is NULL");
   if (n < 0 || n > INT32_MAX) return fail(CB_EINVAL, "n must be in [0, 2^31 - 1]");
   ChainSrc c{n, row_ptr, col, false, 0, 0, 0};
-  return create_graph(&c, 1, stream, flags, out);
+  return create_graph(&c, 1, stream, flags, false, out);
 }
 
 cb_status graph_info(const cb_graph* g, int64_t* n, int64_t* nnz) {
@@ -995,7 +1023,7 @@ cb_status graph_info(const cb_graph* g, int64_t* n, int64_t* nnz) {
 
 cb_status global_trade(cb_graph* g, uint64_t seed, uint32_t round) {
   if (!g) return fail(CB_EINVAL, "null graph");
-  if (g->chains != 1) return fail(CB_EINVAL, "global_trade needs a single-chain graph (use batch_run)");
+  if (g->batch) return fail(CB_EINVAL, "global_trade needs a graph from graph_upload (use batch_run)");
   if (g->poisoned) return fail(CB_EPOISONED, "graph handle poisoned: %s", g->poison_msg);
   if (g->prepared && (g->prep_seed != seed || g->prep_round != round)) unprepare(g);
   if (!g->prepared)
@@ -1006,7 +1034,7 @@ cb_status global_trade(cb_graph* g, uint64_t seed, uint32_t round) {
 
 cb_status global_trade_steps(cb_graph* g, uint64_t seed, uint32_t round, int32_t last_step) {
   if (!g) return fail(CB_EINVAL, "null graph");
-  if (g->chains != 1) return fail(CB_EINVAL, "global_trade_steps needs a single-chain graph");
+  if (g->batch) return fail(CB_EINVAL, "global_trade_steps needs a graph from graph_upload");
   if (g->poisoned) return fail(CB_EPOISONED, "graph handle poisoned: %s", g->poison_msg);
   unprepare(g);
   hipLaunchKernelGGL(k_set_chain, dim3(1), dim3(64), 0, g->stream, g->ch_seed, g->ch_round, 0, seed, round);
@@ -1020,7 +1048,7 @@ cb_status graph_sync(cb_graph* g) {
 
 cb_status graph_download(cb_graph* g, int64_t* row_ptr, int32_t* col) {
   if (!g) return fail(CB_EINVAL, "null graph");
-  if (g->chains != 1) return fail(CB_EINVAL, "graph_download needs a single-chain graph (use batch_download)");
+  if (g->batch) return fail(CB_EINVAL, "graph_download needs a graph from graph_upload (use batch_download)");
   if (g->nnz > 0 && !col) return fail(CB_EINVAL, "col is NULL");
   cb_status s = sync_and_check(g);
   if (s != CB_OK) return s;
@@ -1195,13 +1223,13 @@ cb_status batch_upload(int32_t chains, const int64_t* n, const int64_t* const* r
   std::vector<ChainSrc> src((size_t)chains);
   for (int32_t c = 0; c < chains; ++c)
     src[c] = ChainSrc{n[c], row_ptr[c], col[c], false, 0, seeds[c], first_round ? first_round[c] : 0u};
-  return create_graph(src.data(), chains, stream, flags, out);
+  return create_graph(src.data(), chains, stream, flags, true, out);
 }
 
 cb_status batch_info(const cb_graph* g, int32_t chain, int64_t* n, int64_t* nnz, uint32_t* next_round) {
   if (!g) return fail(CB_EINVAL, "null graph");
   if (chain < 0 || chain >= g->chains) return fail(CB_EINVAL, "chain out of range");
-  if (g->chains == 1) {
+  if (!g->batch) {
     if (n) *n = g->n;
     if (nnz) *nnz = g->nnz;
     if (next_round) *next_round = 0;
@@ -1217,7 +1245,7 @@ cb_status batch_run(cb_graph* g, uint32_t rounds) {
   if (!g) return fail(CB_EINVAL, "null graph");
   if (g->poisoned) return fail(CB_EPOISONED, "graph handle poisoned: %s", g->poison_msg);
   if (rounds == 0) return CB_OK;
-  if (g->chains == 1) return fail(CB_EINVAL, "batch_run needs a graph from batch_upload (use global_trade)");
+  if (!g->batch) return fail(CB_EINVAL, "batch_run needs a graph from batch_upload (use global_trade)");
   char msg[256];
   const bool eager = g->timing || g->tracing || g->giant_dirty;
   if (eager) {
@@ -1264,7 +1292,7 @@ cb_status batch_run(cb_graph* g, uint32_t rounds) {
 cb_status batch_download(cb_graph* g, int32_t chain, int32_t* col) {
   if (!g) return fail(CB_EINVAL, "null graph");
   if (chain < 0 || chain >= g->chains) return fail(CB_EINVAL, "chain out of range");
-  if (g->chains == 1) return graph_download(g, nullptr, col);
+  if (!g->batch) return graph_download(g, nullptr, col);
   const int64_t e0 = g->h_nnz_base[chain], e = g->h_nnz_base[chain + 1] - e0;
   if (e > 0 && !col) return fail(CB_EINVAL, "col is NULL");
   cb_status s = sync_and_check(g);
