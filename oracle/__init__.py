@@ -74,6 +74,11 @@ def _declare(lib):
     lib.orc_global_trade_o2.restype = ctypes.c_int
     lib.orc_check_graph.argtypes = [ctypes.c_int64, _i64p, _i32p]
     lib.orc_check_graph.restype = ctypes.c_int
+    lib.orc_cbu_pair.argtypes = [ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint64, _i32p, _i32p]
+    lib.orc_cbu_pair.restype = None
+    lib.orc_cbu_o1.argtypes = [ctypes.c_int64, _i64p, _i32p, ctypes.c_uint64, ctypes.c_uint64,
+                               ctypes.c_uint64, ctypes.POINTER(Stats)]
+    lib.orc_cbu_o1.restype = ctypes.c_int
     return lib
 
 
@@ -165,6 +170,23 @@ class Oracle:
             raise ValueError(form)
         if rc:
             raise RuntimeError(f"oracle global trade ({form}) failed: {rc}")
+        return out, st.as_dict()
+
+    def cbu_pair(self, n, seed, step):
+        u, v = ctypes.c_int32(), ctypes.c_int32()
+        self.lib.orc_cbu_pair(n, seed, step, ctypes.byref(u), ctypes.byref(v))
+        return int(u.value), int(v.value)
+
+    def cbu(self, row_ptr, col, seed, step0, steps):
+        """Apply uniform single trades step0 .. step0 + steps - 1; returns
+        (new col, stats dict)."""
+        n = len(row_ptr) - 1
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        out = np.array(col, dtype=np.int32, copy=True)
+        st = Stats()
+        rc = self.lib.orc_cbu_o1(n, _ptr64(rp), _ptr32(out), seed, step0, steps, ctypes.byref(st))
+        if rc:
+            raise RuntimeError(f"oracle single trades failed: {rc}")
         return out, st.as_dict()
 
     def check_graph(self, row_ptr, col):

@@ -20,6 +20,9 @@
  *  - IM-CB (Sec. 4.2 and its algorithm in the appendix): each edge is stored
  *    once, at the endpoint traded first; a trade pushes each resulting edge
  *    to the endpoint whose trade comes next.
+ *  - Simple Undirected Curveball (Sec. 3.2, the paragraph after the trade
+ *    figure): a chain of single trades, each of a node pair drawn uniformly
+ *    at random with a uniform split.
  */
 #define _POSIX_C_SOURCE 199309L
 #include <time.h>
@@ -558,4 +561,71 @@ int orc_check_graph(int64_t n, const int64_t* row_ptr, const int32_t* col)
     }
     if (row_ptr[n] % 2) return -7;
     return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Uniform single trades (Simple Undirected Curveball).                */
+/* ------------------------------------------------------------------ */
+
+void orc_cbu_pair(int64_t n, uint64_t seed, uint64_t step, int32_t* u, int32_t* v)
+{
+    uint32_t lo = (uint32_t)step, hi = (uint32_t)(step >> 32);
+    int64_t a = (int64_t)orc_bounded(orc_philox64(seed, lo, hi, 0u, ORC_TAG_U), (uint64_t)n);
+    int64_t b = (int64_t)orc_bounded(orc_philox64(seed, lo, hi, 1u, ORC_TAG_U), (uint64_t)(n - 1));
+    if (b >= a) ++b;
+    *u = (int32_t)a;
+    *v = (int32_t)b;
+}
+
+int orc_cbu_o1(int64_t n, const int64_t* row_ptr, int32_t* col, uint64_t seed,
+               uint64_t step0, uint64_t steps, orc_stats* st)
+{
+    orc_stats s;
+    memset(&s, 0, sizeof(s));
+    s.unmatched = -1;
+    if (n < 2 || steps == 0) { if (st) *st = s; return 0; }
+    if (step0 + steps > ((uint64_t)1 << 32)) return -30;
+    int rc = 0;
+    int64_t dmax = 0;
+    for (int64_t x = 0; x < n; ++x) {
+        int64_t d = row_ptr[x + 1] - row_ptr[x];
+        if (d > dmax) dmax = d;
+    }
+    int64_t cap = 2 * dmax + 2;
+    int32_t* Bu = (int32_t*)malloc((size_t)cap * sizeof(int32_t));
+    int32_t* Bv = (int32_t*)malloc((size_t)cap * sizeof(int32_t));
+    int32_t* mtv = (int32_t*)malloc((size_t)cap * sizeof(int32_t));
+    int32_t* mtu = (int32_t*)malloc((size_t)cap * sizeof(int32_t));
+    if (!Bu || !Bv || !mtv || !mtu) { rc = -100; goto out; }
+    for (uint64_t t = 0; t < steps; ++t) {
+        uint64_t step = step0 + t;
+        int32_t u, v;
+        orc_cbu_pair(n, seed, step, &u, &v);
+        int32_t* Au = col + row_ptr[u];
+        int32_t* Av = col + row_ptr[v];
+        int64_t du = row_ptr[u + 1] - row_ptr[u];
+        int64_t dv = row_ptr[v + 1] - row_ptr[v];
+        int64_t info[6];
+        rc = orc_trade_apply(Au, du, Av, dv, u, v, NULL, seed, ORC_CBU_ROUND, (uint32_t)step,
+                             Bu, Bv, mtv, mtu, info);
+        if (rc) goto out;
+        memcpy(Au, Bu, (size_t)du * sizeof(int32_t));
+        memcpy(Av, Bv, (size_t)dv * sizeof(int32_t));
+        /* the passive rows follow the moved edges */
+        for (int64_t q = 0; q < info[4]; ++q)
+            if (row_replace(col + row_ptr[mtv[q]], row_ptr[mtv[q] + 1] - row_ptr[mtv[q]], u, v)) { rc = -10; goto out; }
+        for (int64_t q = 0; q < info[5]; ++q)
+            if (row_replace(col + row_ptr[mtu[q]], row_ptr[mtu[q] + 1] - row_ptr[mtu[q]], v, u)) { rc = -11; goto out; }
+        s.trades += 1;
+        s.work += du + dv;
+        s.common += info[0];
+        s.disjoint += info[1] + info[2];
+        s.moved += info[4] + info[5];
+        s.uv_edges += info[3];
+        if (du + dv > s.max_s) s.max_s = du + dv;
+    }
+    if (st) *st = s;
+out:
+    free(Bu); free(Bv); free(mtv); free(mtu);
+    return rc;
 }

@@ -31,6 +31,8 @@ extern "C" {
 
 #define ORC_TAG_M 0x4D415443u /* "MATC" */
 #define ORC_TAG_F 0x46595348u /* "FYSH" */
+#define ORC_TAG_U 0x43425550u /* "CBUP": node pair of a uniform single trade */
+#define ORC_CBU_ROUND 0xFFFFFFFFu /* round word of a single trade's split draws */
 #define ORC_UNMATCHED INT32_MAX
 
 typedef struct {
@@ -98,6 +100,22 @@ int orc_global_trade_o2(int64_t n, const int64_t* row_ptr, int32_t* col,
 
 /* 0 if the CSR is simple, rows strictly ascending and symmetric. */
 int orc_check_graph(int64_t n, const int64_t* row_ptr, const int32_t* col);
+
+/* Uniform single-trade chain (Simple Undirected Curveball, Sec. 3.2): step s
+ * draws the node pair u = bounded(philox64(seed; s_lo, s_hi, 0, TAG_U), n),
+ * v' = bounded(philox64(seed; s_lo, s_hi, 1, TAG_U), n - 1), v = v' + (v' >= u)
+ * (a uniform ordered pair of distinct nodes, so a uniform unordered pair),
+ * then trades u and v with the split drawn from philox64(seed; s, CBU_ROUND,
+ * j, TAG_F) (steps below 2^32). */
+void orc_cbu_pair(int64_t n, uint64_t seed, uint64_t step, int32_t* u, int32_t* v);
+
+/* Apply steps step0 .. step0 + steps - 1 to the graph in place, one trade
+ * after the other, as the definition states (both trading rows rewritten,
+ * passive rows relabelled). st->trades counts the steps, st->moved the
+ * disjoint neighbours that changed sides, st->work the sum of deg u + deg v.
+ * Returns 0 or a negative code (n < 2: no step is possible, nothing changes). */
+int orc_cbu_o1(int64_t n, const int64_t* row_ptr, int32_t* col, uint64_t seed,
+               uint64_t step0, uint64_t steps, orc_stats* st);
 
 #ifdef __cplusplus
 }

@@ -103,3 +103,30 @@ def transition_matrix(degrees):
         for t, p in global_trade_row(from_edges(n, s)).items():
             P[i][index[t]] += p
     return states, P
+
+
+def cbu_row(adj):
+    """Exact distribution of canon(state) after one uniform single trade
+    (Simple Undirected Curveball): an ordered pair of distinct nodes drawn
+    uniformly (so a uniform unordered pair), then the trade with a uniform
+    split."""
+    n = len(adj)
+    pairs = [(u, v) for u in range(n) for v in range(n) if u != v]
+    p_pair = Fraction(1, len(pairs))
+    dist = {}
+    for u, v in pairs:
+        for p, t in trade_outcomes(adj, u, v):
+            key = canon(t)
+            dist[key] = dist.get(key, 0) + p_pair * p
+    return dist
+
+
+def cbu_matrix(degrees):
+    states = state_space(degrees)
+    index = {s: i for i, s in enumerate(states)}
+    n = len(degrees)
+    P = [[Fraction(0)] * len(states) for _ in states]
+    for i, s in enumerate(states):
+        for t, p in cbu_row(from_edges(n, s)).items():
+            P[i][index[t]] += p
+    return states, P
