@@ -41,6 +41,8 @@ WORKLOAD_TEXT = {
               "gamma_c~U[1.8,2.6], graph seed 1000+c, chain seed c"),
     "serve": ("Poisson requests: m=2^U[12,24] edges, degrees Pld([5,sqrt n),2), graph seed 10^6+q, "
               "k~U{1..32} samples, r~U{5..20} rounds, rate 0.7x the measured capacity"),
+    "quality": ("mixing study: thinning on n=2000 Pld([5,b),2), b in {25,750}, global trades vs n/2 "
+                "single trades per super-step; swap fractions on 10-regular and Pld([10,n/20),2) graphs"),
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_{workload}.json")
 KERNEL_SOURCES = ["cb_trade.hip", "cb_prep.hip", "cb_block.hpp", "cb_device.hpp", "cb_kernels.hpp"]
@@ -363,6 +365,17 @@ def main(argv=None) -> int:
     torch.cuda.set_stream(stream)
     copy_bps = copy_bandwidth()
     print(f"[bench] device copy {copy_bps / 1e9:.0f} GB/s (read + write)", file=sys.stderr, flush=True)
+    if args.workload == "quality":
+        from paper_1804_08487_amd import quality
+        t0 = time.perf_counter()
+        q = quality.study(supersteps=args.steps if args.steps != 10 else 300)
+        wall = time.perf_counter() - t0
+        out = {"metric": "chain quality (fraction of edges still correlated vs thinning; swap fraction)",
+               "value": None, "unit": "fraction", "n_gpus": 1, "steps": None, "warmup": 0,
+               "higher_is_better": False, "data": "synthetic",
+               "config": {"workload": f"quality: {WORKLOAD_TEXT['quality']}"}, "wall_s": wall, "quality": q}
+        print(json.dumps(out), flush=True)
+        return 0
     if args.workload == "serve":
         sv = run_serve(args, cb, graphgen)
         out = {"metric": "edge-trades/sec per global super-step (m x rounds / s)",

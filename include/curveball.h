@@ -226,6 +226,13 @@ typedef struct {
                                 unlocking later trades */
     double big_release_us;   /* 0: unlocking is part of the write phase */
     double big_max_us;       /* longest single workgroup trade */
+    int64_t moved;           /* disjoint neighbours that changed sides, over the
+                                counted trades (a swap moves two: the paper's
+                                swap fraction is moved / work, appendix on
+                                swaps performed) */
+    int64_t counted_trades;  /* trades whose moves were counted: all except those
+                                whose write phase was shared (CB_OPT_HELP_MIN 0
+                                counts every trade) */
 } cb_round_stats;
 
 cb_status graph_stats(cb_graph* g, cb_round_stats* out);
@@ -299,6 +306,22 @@ typedef struct {
 } cb_tune_result;
 
 cb_status graph_autotune(cb_graph* g, uint32_t trial_rounds, int32_t use_cache, cb_tune_result* out);
+
+/* ---- uniform single trades ------------------------------------------------
+ * Simple Undirected Curveball (Sec. 3.2, the paragraph after the trade
+ * figure): a chain of single trades, each of a node pair drawn uniformly at
+ * random with a uniform split (the comparison chain of the mixing study,
+ * Sec. 6, where n/2 single trades make one super-step). Step s of the chain
+ * with seed `seed` trades u = bounded(philox64(seed; s_lo, s_hi, 0,
+ * 0x43425550), n) and v = bounded(philox64(seed; s_lo, s_hi, 1, 0x43425550),
+ * n - 1), plus one if v >= u; its split draws philox64(seed; s, 0xFFFFFFFF,
+ * j, 0x46595348) with the rule above (u is the first node).
+ * Apply steps step0 .. step0 + steps - 1 (below 2^32) to a graph from
+ * graph_upload, one after the other in effect: runs of steps whose pairs share
+ * no node go through the trade kernel as one partial global trade. Needs
+ * giant nodes off (CB_OPT_GIANT_DEG 0). Synchronises. Round statistics
+ * (graph_stats) then sum over the steps. */
+cb_status cbu_trades(cb_graph* g, uint64_t seed, uint64_t step0, uint64_t steps);
 
 /* ---- request server (continuous batching) ----------------------------------
  * Serves requests "`samples` samples of G after `rounds` global trades": sample

@@ -34,7 +34,7 @@ EXPORTS = ("cb_set_allocator", "graph_upload", "graph_info", "global_trade", "gr
            "graph_download_state", "graph_set_option", "graph_stats", "graph_kernel_times",
            "batch_upload", "batch_run", "batch_info", "batch_download", "graph_autotune",
            "global_trade_static", "server_create", "server_submit", "server_step",
-           "server_request_state", "server_result", "server_release", "server_free")
+           "server_request_state", "server_result", "server_release", "server_free", "cbu_trades")
 
 
 class CurveballError(RuntimeError):
@@ -55,7 +55,8 @@ class RoundStats(ctypes.Structure):
         "forwarded", "emitted", "small_workers", "big_workers")] + [
         (name, ctypes.c_double) for name in (
             "small_busy_us", "big_busy_us", "big_gather_us", "big_split_us", "big_write_us",
-            "big_release_us", "big_max_us")]
+            "big_release_us", "big_max_us")] + [
+        (name, ctypes.c_int64) for name in ("moved", "counted_trades")]
 
     def as_dict(self):
         return {name: (getattr(self, name) if isinstance(getattr(self, name), float)
@@ -121,6 +122,7 @@ def lib():
         L.server_request_state.argtypes = [vp, i64, ctypes.POINTER(i32)]
         L.server_result.argtypes = [vp, i64, i32, vp]
         L.server_release.argtypes = [vp, i64]
+        L.cbu_trades.argtypes = [vp, u64, u64, u64]
         L.server_free.argtypes = [vp]
         L.server_free.restype = None
         for name in EXPORTS:
@@ -233,6 +235,10 @@ class Graph:
         rounds = ctypes.c_int64()
         _check(lib().graph_kernel_times(self._h, ms, 4, ctypes.byref(rounds)))
         return [float(x) for x in ms], int(rounds.value)
+
+    def single_trades(self, seed: int, step0: int, steps: int):
+        """Uniform single trades step0 .. step0 + steps - 1 (see ``cbu_trades``)."""
+        _check(lib().cbu_trades(self._h, seed, step0, steps))
 
     def autotune(self, trial_rounds: int = 2, use_cache: bool = True):
         res = TuneResult()

@@ -450,6 +450,50 @@ int32_t effective_small_max(const cb_graph* g) {
   return g->giant_deg > 0 ? (int32_t)std::min<int64_t>(g->small_max, g->giant_deg - 1) : g->small_max;
 }
 
+// Arguments of the trade kernel for the trades 0..L-1 of the current matching.
+TradeArgs trade_args(const cb_graph* g, int32_t L) {
+  TradeArgs A{};
+  A.rp = g->rp;
+  A.col = g->col;
+  A.col_t = g->col_t;
+  A.tinfo = g->tinfo;
+  A.gs = giant_sets(g);
+  A.perm = g->perm;
+  A.inbox = g->inbox;
+  A.inbox_cur = g->inbox_cur;
+  A.col_out = g->col_out;
+  A.out_cur = g->out_cur;
+  A.own_cur = g->own_cur;
+  A.dep = g->dep;
+  A.src_list = g->src_list;
+  A.tsz = g->tsz;
+  A.jobs = g->jobs;
+  A.trace = g->tracing ? g->trace : nullptr;
+  A.qs = g->qs;
+  A.qb = g->qb;
+  A.ctrl = g->ctrl;
+  A.stats = g->stats;
+  A.slots = g->slots;
+  A.slot_elems = g->slot_elems;
+  A.sbpre = g->sbpre;
+  A.sbpre_stride = g->sbpre_stride;
+  A.smax = g->smax;
+  A.n = g->n;
+  A.L = L;
+  A.small_max = effective_small_max(g);
+  A.help_min = g->help_min;
+  A.help_groups = g->help_groups;
+  A.help_chunk = g->help_chunk;
+  A.idle_backoff = g->idle_backoff;
+  A.big_lds_max = g->big_lds_max;
+  A.nbig = effective_nbig(g);
+  A.stack_cap = g->stack_cap;
+  A.keybits = g->keybits_entry;
+  A.ch = chains_of(g);
+  A.watchdog_ticks = (uint64_t)g->watchdog_ms * g->ticks_per_ms;
+  return A;
+}
+
 // Forget a prepared round (its bitmap seeds are cleared before the next scan).
 void unprepare(cb_graph* g) {
   if (g->prepared && g->ngiant > 0) g->giant_dirty = true;
@@ -520,7 +564,7 @@ cb_status enqueue_round(cb_graph* g, hipStream_t st, int last_step, bool advance
 
   hipLaunchKernelGGL(k_round_reset, dim3(grid_for(std::max<int64_t>({n, (int64_t)g->nb, (int64_t)kCwCount}), 256, 8192)),
                      dim3(256), 0, st, n, g->nb, g->inbox_cur, g->out_cur, g->own_cur, g->bcount,
-                     g->bcur, g->ctrl, g->stats);
+                     g->bcur, g->ctrl, g->stats, 1);
   // 1. matching
   if (!from_prepared) enqueue_matching(g, st);
   if (timed) (void)hipEventRecord(evs.ev[1], st);
@@ -541,49 +585,11 @@ cb_status enqueue_round(cb_graph* g, hipStream_t st, int last_step, bool advance
   if (timed) (void)hipEventRecord(evs.ev[2], st);
   if (last_step >= CB_STEP_TRADE && L > 0) {
     // 3. trades
-    TradeArgs A{};
-    A.rp = g->rp;
-    A.col = g->col;
-    A.col_t = g->col_t;
-    A.tinfo = g->tinfo;
-    A.gs = giant_sets(g);
-    A.perm = g->perm;
-    A.inbox = g->inbox;
-    A.inbox_cur = g->inbox_cur;
-    A.col_out = g->col_out;
-    A.out_cur = g->out_cur;
-    A.own_cur = g->own_cur;
-    A.dep = g->dep;
-    A.src_list = g->src_list;
-    A.tsz = g->tsz;
-    A.jobs = g->jobs;
-    A.trace = g->tracing ? g->trace : nullptr;
     if (g->tracing) {
       if (!HIP_OK(hipMemsetAsync(g->trace, 0xFF, (size_t)L * kTraceFields * sizeof(int64_t), st), "clear trace"))
         return fail(CB_EDEVICE, "%s", msg);
     }
-    A.qs = g->qs;
-    A.qb = g->qb;
-    A.ctrl = g->ctrl;
-    A.stats = g->stats;
-    A.slots = g->slots;
-    A.slot_elems = g->slot_elems;
-    A.sbpre = g->sbpre;
-    A.sbpre_stride = g->sbpre_stride;
-    A.smax = g->smax;
-    A.n = n;
-    A.L = L;
-    A.small_max = effective_small_max(g);
-    A.help_min = g->help_min;
-    A.help_groups = g->help_groups;
-    A.help_chunk = g->help_chunk;
-    A.idle_backoff = g->idle_backoff;
-    A.big_lds_max = g->big_lds_max;
-    A.nbig = effective_nbig(g);
-    A.stack_cap = g->stack_cap;
-    A.keybits = g->keybits_entry;
-    A.ch = ch;
-    A.watchdog_ticks = (uint64_t)g->watchdog_ms * g->ticks_per_ms;
+    const TradeArgs A = trade_args(g, L);
     hipLaunchKernelGGL(k_trade, dim3(trade_grid(g)), dim3(kTradeBlock), 0, st, A);
   }
   if (timed) (void)hipEventRecord(evs.ev[3], st);
@@ -994,6 +1000,28 @@ cb_tune_result current_options(const cb_graph* g) {
   return r;
 }
 
+// Philox4x32-10 on the host (the node pairs of single trades are drawn
+// here); the same convention as the device's philox64.
+uint64_t host_philox64(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3) {
+  uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c0 = n0;
+    c1 = (uint32_t)p1;
+    c2 = n2;
+    c3 = (uint32_t)p0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return ((uint64_t)c1 << 32) | c0;
+}
+uint64_t host_bounded(uint64_t x, uint64_t k) { return (uint64_t)(((unsigned __int128)x * k) >> 64); }
+
+constexpr uint32_t kTagPair = 0x43425550u;   // node pair of a single trade
+constexpr uint32_t kSingleRound = 0xFFFFFFFFu;   // round word of a single trade's split draws
+
 }  // namespace
 
 extern "C" {
@@ -1191,6 +1219,8 @@ cb_status graph_stats(cb_graph* g, cb_round_stats* out) {
   out->big_max_us = (double)st[kStatBigMaxTicks] * us;
   out->small_workers = (int64_t)(trade_grid(g) - effective_nbig(g)) * kWavesPerBlock;
   out->big_workers = effective_nbig(g);
+  out->moved = (int64_t)st[kStatMoved];
+  out->counted_trades = (int64_t)st[kStatCounted];
   return CB_OK;
 }
 
@@ -1499,5 +1529,99 @@ extern "C" cb_status global_trade_static(int64_t n, const int64_t* row_ptr, int3
   g->gwords = ((n + 4095) / 4096) * 64;
   s = enqueue_round(g, st, CB_STEP_REBUILD, false);
   if (s != CB_OK) return s;
+  return sync_and_check(g);
+}
+
+// ---------------------------------------------------------------- single trades
+// Steps step0 .. step0 + steps - 1 of the uniform single-trade chain. Step s
+// trades the pair u = bounded(philox64(seed; s_lo, s_hi, 0, TAG_U), n),
+// v = bounded(philox64(seed; s_lo, s_hi, 1, TAG_U), n - 1) (+1 if >= u), its
+// split drawn from philox64(seed; s, 0xFFFFFFFF, j, TAG_F). Consecutive steps
+// whose pairs share no node form a phase, applied in step order as one
+// partial global trade (the dependency counts order them exactly as the
+// sequential chain does); a step that meets a node of the current phase
+// starts the next phase.
+extern "C" cb_status cbu_trades(cb_graph* g, uint64_t seed, uint64_t step0, uint64_t steps) {
+  if (!g) return fail(CB_EINVAL, "null graph");
+  if (g->batch) return fail(CB_EINVAL, "single trades need a graph from graph_upload");
+  if (g->poisoned) return fail(CB_EPOISONED, "graph handle poisoned: %s", g->poison_msg);
+  if (step0 + steps > ((uint64_t)1 << 32) || step0 + steps < step0)
+    return fail(CB_EINVAL, "single-trade steps must stay below 2^32");
+  if (g->ngiant > 0) return fail(CB_EINVAL, "single trades need giant nodes off (CB_OPT_GIANT_DEG 0)");
+  if (g->n < 2 || steps == 0) return CB_OK;
+  const int64_t n = g->n;
+  char msg[256];
+  // every step's pair, and where each phase starts
+  std::vector<int32_t> pairs((size_t)(2 * steps));
+  std::vector<uint64_t> phase_start;
+  std::vector<uint32_t> stamp((size_t)n, 0);
+  uint32_t phase = 0;
+  for (uint64_t t = 0; t < steps; ++t) {
+    const uint64_t s = step0 + t;
+    const int64_t u = (int64_t)host_bounded(host_philox64(seed, (uint32_t)s, (uint32_t)(s >> 32), 0u, kTagPair), (uint64_t)n);
+    int64_t v = (int64_t)host_bounded(host_philox64(seed, (uint32_t)s, (uint32_t)(s >> 32), 1u, kTagPair), (uint64_t)(n - 1));
+    if (v >= u) ++v;
+    if (phase == 0 || stamp[(size_t)u] == phase || stamp[(size_t)v] == phase) {
+      ++phase;
+      phase_start.push_back(t);
+    }
+    stamp[(size_t)u] = stamp[(size_t)v] = phase;
+    pairs[(size_t)(2 * t)] = (int32_t)u;
+    pairs[(size_t)(2 * t + 1)] = (int32_t)v;
+  }
+  phase_start.push_back(steps);
+  int32_t* dpairs = nullptr;
+  if (!alloc_into(g, &dpairs, (int64_t)pairs.size())) return fail(CB_ENOMEM, "no device memory for the pairs");
+  hipStream_t st = g->stream;
+  unprepare(g);
+  bool ok = HIP_OK(hipMemcpyAsync(dpairs, pairs.data(), pairs.size() * sizeof(int32_t), hipMemcpyHostToDevice, st),
+                   "copy pairs");
+  const Chains ch = chains_of(g);
+  (void)ch;
+  for (size_t p = 0; ok && p + 1 < phase_start.size(); ++p) {
+    const uint64_t t0 = phase_start[p];
+    const int32_t P = (int32_t)(phase_start[p + 1] - t0);
+    hipLaunchKernelGGL(k_round_reset, dim3(grid_for(std::max<int64_t>({n, (int64_t)g->nb, (int64_t)kCwCount}), 256, 8192)),
+                       dim3(256), 0, st, n, g->nb, g->inbox_cur, g->out_cur, g->own_cur, g->bcount, g->bcur, g->ctrl,
+                       g->stats, p == 0 ? 1 : 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, g->trade_of, n, kUnmatched);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, g->tinfo, n, kUnmatched);
+    hipLaunchKernelGGL(k_phase_pairs, dim3(grid_for(P, 256, 1024)), dim3(256), 0, st, dpairs + 2 * t0, P, g->perm,
+                       g->trade_of, g->tinfo, g->dep);
+    hipLaunchKernelGGL(k_set_draws, dim3(1), dim3(64), 0, st, g->ch_seed, g->ch_round, g->ch_draw_base, seed,
+                       kSingleRound, (uint32_t)(step0 + t0));
+    if (g->nnz > 0) {
+      hipLaunchKernelGGL(k_depscan, dim3((unsigned)((g->nnz + kScanChunk - 1) / kScanChunk)), dim3(256), 0, st, n,
+                         g->nnz, g->rp, g->col, g->trade_of, g->tinfo, g->col_t, g->dep, giant_sets(g), g->ctrl);
+      hipLaunchKernelGGL(k_copy_idle_edges, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, n, g->rp, g->col,
+                         g->trade_of, g->col_out, g->out_cur, g->ctrl);
+    }
+    hipLaunchKernelGGL(k_sources, dim3(grid_for(P, 256, 8192)), dim3(256), 0, st, P, g->dep, g->perm, g->rp,
+                       effective_small_max(g), g->tsz, g->src_list, g->qb, g->ctrl, g->stats);
+    const TradeArgs A = trade_args(g, P);
+    hipLaunchKernelGGL(k_trade, dim3(trade_grid(g)), dim3(kTradeBlock), 0, st, A);
+    hipLaunchKernelGGL(k_check_rows, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, n, g->rp, g->out_cur,
+                       g->own_cur, g->ctrl);
+    if (g->nnz > 0) {
+      const NextScan none{};
+      if (g->n_small)
+        hipLaunchKernelGGL(k_segsort_small, dim3(grid_for(g->n_small, 4, 65536)), dim3(256), 0, st, g->rows,
+                           g->n_small, g->rp, g->col_out, g->col, none, g->ctrl);
+      if (g->n_mid)
+        hipLaunchKernelGGL(k_segsort_mid, dim3(grid_for(g->n_mid, 1, 65536)), dim3(256), 0, st,
+                           g->rows + g->n_small, g->n_mid, g->rp, g->col_out, g->col, g->keybits_node, none, g->ctrl);
+      if (g->n_big)
+        hipLaunchKernelGGL(k_segsort_big, dim3(grid_for(g->n_big, 1, 8192)), dim3(256), 0, st,
+                           g->rows + g->n_small + g->n_mid, g->n_big, g->rp, g->col_out, g->col, g->keybits_node,
+                           none, g->ctrl);
+    }
+    ok = HIP_OK(hipGetLastError(), "kernel launch");
+  }
+  // the draw offset goes back to the global-trade convention
+  hipLaunchKernelGGL(k_set_draws, dim3(1), dim3(64), 0, st, g->ch_seed, g->ch_round, g->ch_draw_base, seed, 0u, 0u);
+  const hipError_t se = hipStreamSynchronize(st);
+  dev_free_one(g, dpairs);
+  if (!ok) return poison(g, CB_EDEVICE, msg);
+  if (se != hipSuccess) return poison(g, CB_EDEVICE, hipGetErrorString(se));
   return sync_and_check(g);
 }

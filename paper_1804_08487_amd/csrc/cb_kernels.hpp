@@ -46,6 +46,8 @@ enum Stat : int {
   kStatBigWrite,     // ... writing and forwarding
   kStatBigRelease,   // ... unlocking later trades
   kStatBigMaxTicks,  // longest single large trade
+  kStatMoved,        // disjoint neighbours that changed sides (counted trades only)
+  kStatCounted,      // trades whose moved neighbours were counted (all but shared write phases)
   kStatCount = 16
 };
 
@@ -201,7 +203,13 @@ struct TradeArgs {
 // ---- kernels ---------------------------------------------------------------
 __global__ void k_round_reset(int64_t n, int32_t nb, int32_t* inbox_cur, int32_t* out_cur,
                               int32_t* own_cur, int32_t* bcount, int32_t* bcur, int32_t* ctrl,
-                              unsigned long long* stats);
+                              unsigned long long* stats, int32_t reset_stats);
+__global__ void k_phase_pairs(const int32_t* pairs, int32_t P, int32_t* perm, int32_t* trade_of,
+                              int32_t* tinfo, int32_t* dep);
+__global__ void k_copy_idle_edges(int64_t n, const int64_t* rp, const int32_t* col, const int32_t* trade_of,
+                                  int32_t* col_out, int32_t* out_cur, int32_t* ctrl);
+__global__ void k_set_draws(uint64_t* seed, uint32_t* round, uint32_t* draw_base, uint64_t s, uint32_t r,
+                            uint32_t d);
 __global__ void k_set_chain(uint64_t* seed, uint32_t* round, int32_t c, uint64_t s, uint32_t r);
 __global__ void k_advance_rounds(uint32_t* round, int32_t count, uint32_t by);
 __global__ void k_fill_i32(int32_t* p, int64_t count, int32_t value);

@@ -8,7 +8,7 @@ namespace cbx {
 
 __global__ void k_round_reset(int64_t n, int32_t nb, int32_t* inbox_cur, int32_t* out_cur,
                               int32_t* own_cur, int32_t* bcount, int32_t* bcur, int32_t* ctrl,
-                              unsigned long long* stats) {
+                              unsigned long long* stats, int32_t reset_stats) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t i = t0; i < n; i += stride) {
@@ -24,7 +24,51 @@ __global__ void k_round_reset(int64_t n, int32_t nb, int32_t* inbox_cur, int32_t
   if (t0 < kCwCount && t0 != kCwErr && t0 != kCwAbort && t0 != kCwDbgBits && t0 != kCwDbgA &&
       t0 != kCwDbgB)
     ctrl[cw((int)t0)] = 0;
-  if (t0 < kStatCount) stats[t0] = 0;
+  if (t0 < kStatCount && reset_stats) stats[t0] = 0;
+}
+
+// ---------------------------------------------------------------- single trades
+// One phase of uniform single trades: node-disjoint pairs, applied in step
+// order as the trades 0..P-1 of a partial global trade (every other node
+// sits out). pairs holds u0, v0, u1, v1, ...
+
+__global__ void k_phase_pairs(const int32_t* pairs, int32_t P, int32_t* perm, int32_t* trade_of,
+                              int32_t* tinfo, int32_t* dep) {
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < P; i += gridDim.x * blockDim.x) {
+    const int32_t u = pairs[2 * i], v = pairs[2 * i + 1];
+    perm[2 * i] = u;
+    perm[2 * i + 1] = v;
+    trade_of[u] = trade_of[v] = i;
+    tinfo[u] = tinfo[v] = i;
+    dep[i] = 0;
+  }
+}
+
+// Edges between two nodes that sit out the phase stay where they are: row x
+// of a node without a trade keeps its neighbours without a trade (the other
+// edges are written by the trades).
+__global__ void k_copy_idle_edges(int64_t n, const int64_t* rp, const int32_t* col, const int32_t* trade_of,
+                                  int32_t* col_out, int32_t* out_cur, int32_t* ctrl) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += stride) {
+    if (trade_of[x] != kUnmatched) continue;
+    const int64_t b = rp[x], e = rp[x + 1];
+    for (int64_t i = b; i < e; ++i) {
+      const int32_t y = col[i];
+      if (trade_of[y] != kUnmatched) continue;
+      const int32_t p = atomicAdd(&out_cur[x], 1);
+      if (p < e - b) col_out[b + p] = y; else atomic_or(&ctrl[cw(kCwErr)], kErrOut);
+    }
+  }
+}
+
+__global__ void k_set_draws(uint64_t* seed, uint32_t* round, uint32_t* draw_base, uint64_t s, uint32_t r,
+                            uint32_t d) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    seed[0] = s;
+    round[0] = r;
+    draw_base[0] = d;
+  }
 }
 
 // ---------------------------------------------------------------- chains

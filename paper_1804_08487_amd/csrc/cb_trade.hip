@@ -447,7 +447,7 @@ struct ItemSrc {
 };
 
 struct WriteCounts {   // per lane
-  unsigned long long fwd, emit, push;
+  unsigned long long fwd, emit, push, moved;
 };
 
 // Item o: its entry, with the side bit replaced by the side of its owner
@@ -488,6 +488,9 @@ __device__ __forceinline__ void write_range(const TradeArgs& A, const ItemSrc& S
         tx[r] = ent_node(e);
         ttag[r] = ent_tag(e);
         towner[r] = ent_side(e) ? S.v : S.u;
+        // a disjoint neighbour that changed sides (the published items of a
+        // shared phase no longer carry their old side)
+        if (!kShared && o < S.nD) W.moved += (uint64_t)(ent_side(S.E[S.D[o]]) != (o < S.a ? 0 : 1));
       }
     }
     // members of a giant node's list learn their tag here, one gather each,
@@ -816,7 +819,7 @@ struct WaveState {
   int32_t top;        // local stack depth (uniform)
   int32_t ndone;
   int32_t shard;      // home shard of the small-trade queues
-  unsigned long long n_small, n_push, work, fwd, emit, ticks;
+  unsigned long long n_small, n_push, work, fwd, emit, ticks, moved;
 };
 
 // Drops the dependency counters of later trades reached by trade k's
@@ -918,7 +921,7 @@ __device__ __forceinline__ void small_trade(const TradeArgs& A, int32_t k, int32
   // ---- write: own-row finals, other-row finals, forwards; each chunk's
   // forwards then drop their target trades' counters once the chunk's
   // writes are complete
-  int32_t nfwd = 0, nemit = 0;
+  int32_t nfwd = 0, nemit = 0, nmoved = 0;
 #pragma unroll
   for (int pass = 0; pass < 2; ++pass) {
     const int32_t count = pass ? nD : s;
@@ -942,6 +945,7 @@ __device__ __forceinline__ void small_trade(const TradeArgs& A, int32_t k, int32
           x = ent_node(e);
           tag = ent_tag(e);
           owner = o < a ? u : v;
+          nmoved += ent_side(e) != (o < a ? 0 : 1) ? 1 : 0;
         }
       }
       const bool own = valid && tag <= kTagPartner;
@@ -973,6 +977,7 @@ __device__ __forceinline__ void small_trade(const TradeArgs& A, int32_t k, int32
   S.n_small += 1;
   S.work += (unsigned long long)s;
   S.fwd += (unsigned long long)nfwd;
+  S.moved += (unsigned long long)wave_sum(nmoved);
   S.emit += (unsigned long long)nemit;
 }
 
@@ -985,9 +990,11 @@ __device__ void wave_flush(const TradeArgs& A, WaveState& S) {
     if (S.fwd) atomicAdd(&A.stats[kStatForward], S.fwd);
     if (S.emit) atomicAdd(&A.stats[kStatEmit], S.emit);
     if (S.ticks) atomicAdd(&A.stats[kStatSmallTicks], S.ticks);
+    if (S.moved) atomicAdd(&A.stats[kStatMoved], S.moved);
+    if (S.n_small) atomicAdd(&A.stats[kStatCounted], S.n_small);
   }
   S.ndone = 0;
-  S.n_small = S.n_push = S.work = S.fwd = S.emit = S.ticks = 0;
+  S.n_small = S.n_push = S.work = S.fwd = S.emit = S.ticks = S.moved = 0;
 }
 
 constexpr int32_t kFlushEvery = 32;   // trades between progress flushes
@@ -1036,7 +1043,7 @@ __device__ __forceinline__ void small_worker(const TradeArgs& A, WaveLds& W) {
       }
       if (wave_bcast(stop, 0)) break;
       // an idle wavefront also writes chunks of the large trades' write jobs
-      WriteCounts H{0, 0, 0};
+      WriteCounts H{0, 0, 0, 0};
       if (try_help(A, (int32_t)blockIdx.x, H)) {
         S.fwd += (unsigned long long)wave_sum((int32_t)H.fwd);
         S.emit += (unsigned long long)wave_sum((int32_t)H.emit);
@@ -2153,7 +2160,7 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
   // their back (own_cur), so later trades released here may emit into them
   // from the front at once. Large trades open this phase to idle workgroups
   // through their write job.
-  WriteCounts W{0, 0, 0};
+  WriteCounts W{0, 0, 0, 0};
   const int w = tid >> 6;
   ItemSrc S{E, D, k, u, v, s, nD, a, du, dv, bu, bv, gu, gv};
   if (!share) {
@@ -2241,6 +2248,8 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
   counters[1] += W.fwd;
   counters[2] += W.push;
   counters[3] += W.emit;
+  counters[8] += W.moved;
+  if (tid == 0 && !share) counters[9] += 1;
   __syncthreads();
 }
 
@@ -2249,7 +2258,8 @@ __device__ __forceinline__ void big_worker(const TradeArgs& A, BigLds& B) {
   uint64_t* slot = A.slots + (int64_t)blockIdx.x * A.slot_elems;
   // per-thread partial counters: work, forwarded, pushes, emitted, then
   // (thread 0) ticks of gather, split, write, release
-  unsigned long long counters[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  // ..., then moved neighbours (every thread) and counted trades (thread 0)
+  unsigned long long counters[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   unsigned long long max_ticks = 0;
   unsigned long long n_big = 0;
   Watchdog wd{0, 0};
@@ -2296,7 +2306,7 @@ __device__ __forceinline__ void big_worker(const TradeArgs& A, BigLds& B) {
         backoff = 1;
         continue;
       }
-      WriteCounts H{0, 0, 0};
+      WriteCounts H{0, 0, 0, 0};
       const bool helped = try_help(A, (int32_t)blockIdx.x, H);
       counters[1] += H.fwd;
       counters[2] += H.push;
@@ -2330,6 +2340,8 @@ __device__ __forceinline__ void big_worker(const TradeArgs& A, BigLds& B) {
   if (counters[1]) atomicAdd(&A.stats[kStatForward], counters[1]);
   if (counters[2]) atomicAdd(&A.stats[kStatPush], counters[2]);
   if (counters[3]) atomicAdd(&A.stats[kStatEmit], counters[3]);
+  if (counters[8]) atomicAdd(&A.stats[kStatMoved], counters[8]);
+  if (tid == 0 && counters[9]) atomicAdd(&A.stats[kStatCounted], counters[9]);
   if (tid == 0 && n_big) atomicAdd(&A.stats[kStatBig], n_big);
   if (tid == 0) {
     const unsigned long long busy = counters[4] + counters[5] + counters[6] + counters[7];
