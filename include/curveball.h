@@ -190,6 +190,11 @@ cb_status graph_download_state(cb_graph* g, int32_t which, void* host, int64_t c
                                    between polls of the ready queues, in units of
                                    2048 cycles (1..1024; default 128, about
                                    110 us) */
+#define CB_OPT_CU_POOL      16  /* 1 (default): ready small trades beyond a wavefront's
+                                   local stack go first to a pool in its
+                                   workgroup's LDS, where idle wavefronts of the
+                                   same CU take them; 0: straight to the global
+                                   queues */
 #define CB_OPT_FUSE_NEXT    14  /* 1 (default): a full round also prepares the next
                                    one (its matching, run once this round's trade
                                    kernel is done, and its dependency scan, done
@@ -281,7 +286,8 @@ cb_status batch_info(const cb_graph* g, int32_t chain, int64_t* n, int64_t* nnz,
 cb_status batch_download(cb_graph* g, int32_t chain, int32_t* col);
 
 /* ---- autotuner --------------------------------------------------------------
- * Chooses the idle wavefronts' back-off (CB_OPT_IDLE_BACKOFF), their local
+ * Chooses the workgroup pool (CB_OPT_CU_POOL), the idle wavefronts' back-off
+ * (CB_OPT_IDLE_BACKOFF), their local
  * stack of ready trades (CB_OPT_LOCAL_STACK), the wavefront/workgroup size
  * threshold (CB_OPT_SMALL_MAX), the size from which write phases are shared
  * (CB_OPT_HELP_MIN), their chunk size (CB_OPT_HELP_CHUNK) and the workgroup
@@ -299,6 +305,7 @@ typedef struct {
     int32_t big_workers;
     int32_t local_stack;          /* CB_OPT_LOCAL_STACK */
     int32_t idle_backoff;         /* CB_OPT_IDLE_BACKOFF */
+    int32_t cu_pool;              /* CB_OPT_CU_POOL */
     double ms_per_round;          /* of the chosen options */
     double default_ms_per_round;  /* of the options the tuner started from */
     int32_t evaluated;            /* timed candidates (0 when taken from the cache) */

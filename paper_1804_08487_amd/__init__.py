@@ -25,7 +25,7 @@ STEP_MATCHING, STEP_DEPSCAN, STEP_TRADE, STEP_REBUILD = 1, 2, 3, 4
 STATE_PERM, STATE_TRADE_OF, STATE_DEP, STATE_COL, STATE_OUT_CUR, STATE_INBOX_CUR, STATE_TRACE, STATE_OWN_CUR = range(1, 9)
 (OPT_SMALL_MAX, OPT_BIG_WORKERS, OPT_GRID_BLOCKS, OPT_WATCHDOG_MS, OPT_TIMING, OPT_LOCAL_STACK,
  OPT_BIG_LDS_MAX, OPT_GIANT_DEG, OPT_DEBUG_CHECKS, OPT_TRACE, OPT_HELP_MIN, OPT_HELP_GROUPS,
- OPT_HELP_CHUNK, OPT_FUSE_NEXT, OPT_IDLE_BACKOFF) = range(1, 16)
+ OPT_HELP_CHUNK, OPT_FUSE_NEXT, OPT_IDLE_BACKOFF, OPT_CU_POOL) = range(1, 17)
 UNMATCHED = 2**31 - 1
 
 # Every symbol declared in include/curveball.h.
@@ -67,6 +67,7 @@ class TuneResult(ctypes.Structure):
     _fields_ = [("small_max", ctypes.c_int32), ("help_min", ctypes.c_int32),
                 ("help_chunk", ctypes.c_int32), ("big_workers", ctypes.c_int32),
                 ("local_stack", ctypes.c_int32), ("idle_backoff", ctypes.c_int32),
+                ("cu_pool", ctypes.c_int32),
                 ("ms_per_round", ctypes.c_double), ("default_ms_per_round", ctypes.c_double),
                 ("evaluated", ctypes.c_int32), ("cached", ctypes.c_int32)]
 

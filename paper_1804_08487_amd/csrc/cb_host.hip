@@ -70,7 +70,8 @@ struct cb_graph {
   // chains (one for graph_upload)
   bool batch = false;          // made by batch_upload (or the server): run with batch_run
   int32_t chains = 1;
-  std::vector<int64_t> h_node_base, h_nnz_base;   // chains + 1 (batches only)
+  std::vector<int64_t> h_node_base, h_nnz_base;   // chains + 1 (batches only), in internal order
+  std::vector<int32_t> h_pos;                     // internal position of each caller chain (batches)
   std::vector<uint64_t> h_seed;                   // batches only
   std::vector<uint32_t> h_round;                  // next round of each chain (batches only)
   int64_t* ch_node_base = nullptr;
@@ -141,6 +142,7 @@ struct cb_graph {
   int32_t help_groups = 2;
   int32_t help_chunk = kHelpChunk;
   int32_t idle_backoff = 128;
+  int32_t cu_pool = 1;
   int64_t watchdog_ms = 20000;
   bool timing = false;
   bool debug_checks = false;
@@ -485,6 +487,7 @@ TradeArgs trade_args(const cb_graph* g, int32_t L) {
   A.help_groups = g->help_groups;
   A.help_chunk = g->help_chunk;
   A.idle_backoff = g->idle_backoff;
+  A.cu_pool = g->cu_pool;
   A.big_lds_max = g->big_lds_max;
   A.nbig = effective_nbig(g);
   A.stack_cap = g->stack_cap;
@@ -805,11 +808,23 @@ int64_t default_giant_threshold(const cb_graph* g, const int64_t* rp) {
 }  // namespace
 
 // Create a graph of `count` chains in allocated device memory.
-cb_status cbx::create_graph(const ChainSrc* src, int32_t count, void* stream, uint32_t flags, bool batch,
+cb_status cbx::create_graph(const ChainSrc* src_in, int32_t count, void* stream, uint32_t flags, bool batch,
                             cb_graph** out) {
   if (!out) return fail(CB_EINVAL, "out is NULL");
   *out = nullptr;
   if (count < 1) return fail(CB_EINVAL, "a graph needs at least one chain");
+  // A batch lays its chains out largest first: their sources are handed out
+  // first and their dependency chains, the longest, start earliest. Each
+  // chain's result does not depend on where it sits.
+  std::vector<int32_t> order((size_t)count);
+  for (int32_t c = 0; c < count; ++c) order[c] = c;
+  if (batch)
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+      return src_in[a].rp[src_in[a].n] > src_in[b].rp[src_in[b].n];
+    });
+  std::vector<ChainSrc> sorted_src((size_t)count);
+  for (int32_t i = 0; i < count; ++i) sorted_src[i] = src_in[order[i]];
+  const ChainSrc* src = sorted_src.data();
   int64_t d1 = 0, d2 = 0, n_total = 0, nnz_total = 0;
   for (int32_t c = 0; c < count; ++c) {
     cb_status s = check_chain_host(src[c], &d1, &d2);
@@ -827,7 +842,7 @@ cb_status cbx::create_graph(const ChainSrc* src, int32_t count, void* stream, ui
       const int64_t e = src[c].rp[src[c].n];
       for (int64_t i = 0; i < e; ++i)
         if (src[c].col[i] < 0 || src[c].col[i] >= src[c].n)
-          return fail(CB_ENOTSIMPLE, "chain %d: a neighbour id is outside [0, n)", (int)c);
+          return fail(CB_ENOTSIMPLE, "chain %d: a neighbour id is outside [0, n)", (int)order[c]);
     }
 
   cb_graph* g = new cb_graph();
@@ -925,6 +940,8 @@ cb_status cbx::create_graph(const ChainSrc* src, int32_t count, void* stream, ui
     g->h_nnz_base = nnz_base;
     g->h_seed = seeds;
     g->h_round = rounds;
+    g->h_pos.assign((size_t)count, 0);
+    for (int32_t i = 0; i < count; ++i) g->h_pos[order[i]] = i;
   }
   *out = g;
   return CB_OK;
@@ -957,8 +974,9 @@ int32_t* cbx::chain_col(cb_graph* g, int32_t c, int64_t* node_base) {
     *node_base = 0;
     return g->col;
   }
-  *node_base = g->h_node_base[c];
-  return g->col + g->h_nnz_base[c];
+  const int32_t i = g->h_pos[c];
+  *node_base = g->h_node_base[i];
+  return g->col + g->h_nnz_base[i];
 }
 
 namespace {
@@ -986,6 +1004,7 @@ void apply_tuned(cb_graph* g, const cb_tune_result& r) {
   g->nbig = r.big_workers;
   g->stack_cap = r.local_stack;
   g->idle_backoff = r.idle_backoff;
+  g->cu_pool = r.cu_pool;
   g->opt_version++;
 }
 
@@ -997,6 +1016,7 @@ cb_tune_result current_options(const cb_graph* g) {
   r.big_workers = effective_nbig(g);
   r.local_stack = g->stack_cap;
   r.idle_backoff = g->idle_backoff;
+  r.cu_pool = g->cu_pool;
   return r;
 }
 
@@ -1176,6 +1196,10 @@ cb_status graph_set_option(cb_graph* g, int32_t option, int64_t value) {
         return fail(CB_EINVAL, "help chunk must be a multiple of 64 in [64, 4096]");
       g->help_chunk = (int32_t)value;
       return CB_OK;
+    case CB_OPT_CU_POOL:
+      if (value != 0 && value != 1) return fail(CB_EINVAL, "pool must be 0 or 1");
+      g->cu_pool = (int32_t)value;
+      return CB_OK;
     case CB_OPT_IDLE_BACKOFF:
       if (value < 1 || value > 1024) return fail(CB_EINVAL, "idle back-off must be in [1, 1024]");
       g->idle_backoff = (int32_t)value;
@@ -1265,9 +1289,10 @@ cb_status batch_info(const cb_graph* g, int32_t chain, int64_t* n, int64_t* nnz,
     if (next_round) *next_round = 0;
     return CB_OK;
   }
-  if (n) *n = g->h_node_base[chain + 1] - g->h_node_base[chain];
-  if (nnz) *nnz = g->h_nnz_base[chain + 1] - g->h_nnz_base[chain];
-  if (next_round) *next_round = g->h_round[chain];
+  const int32_t i = g->h_pos[chain];
+  if (n) *n = g->h_node_base[i + 1] - g->h_node_base[i];
+  if (nnz) *nnz = g->h_nnz_base[i + 1] - g->h_nnz_base[i];
+  if (next_round) *next_round = g->h_round[i];
   return CB_OK;
 }
 
@@ -1323,14 +1348,15 @@ cb_status batch_download(cb_graph* g, int32_t chain, int32_t* col) {
   if (!g) return fail(CB_EINVAL, "null graph");
   if (chain < 0 || chain >= g->chains) return fail(CB_EINVAL, "chain out of range");
   if (!g->batch) return graph_download(g, nullptr, col);
-  const int64_t e0 = g->h_nnz_base[chain], e = g->h_nnz_base[chain + 1] - e0;
+  const int32_t ci = g->h_pos[chain];
+  const int64_t e0 = g->h_nnz_base[ci], e = g->h_nnz_base[ci + 1] - e0;
   if (e > 0 && !col) return fail(CB_EINVAL, "col is NULL");
   cb_status s = sync_and_check(g);
   if (s != CB_OK) return s;
   char msg[256];
   if (e > 0 && !HIP_OK(hipMemcpy(col, g->col + e0, (size_t)e * sizeof(int32_t), hipMemcpyDeviceToHost), "download col"))
     return fail(CB_EDEVICE, "%s", msg);
-  const int32_t shift = (int32_t)g->h_node_base[chain];
+  const int32_t shift = (int32_t)g->h_node_base[ci];
   if (shift)
     for (int64_t i = 0; i < e; ++i) col[i] -= shift;
   return CB_OK;
@@ -1408,6 +1434,7 @@ cb_status graph_autotune(cb_graph* g, uint32_t trial_rounds, int32_t use_cache, 
     int count;
   };
   const Param params[] = {
+      {&cb_tune_result::cu_pool, {0, 1}, 2},
       {&cb_tune_result::idle_backoff, {2, 8, 32, 128}, 4},
       {&cb_tune_result::local_stack, {0, 1, 2, 4, 8, 16}, 6},
       {&cb_tune_result::small_max, {128, 256, 384, 512}, 4},

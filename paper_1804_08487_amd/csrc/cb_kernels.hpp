@@ -192,6 +192,7 @@ struct TradeArgs {
   int32_t help_groups;      // workgroup b helps owners j with j % help_groups == b % help_groups
   int32_t help_chunk;       // items per claimed chunk of a shared write phase (a multiple of 64)
   int32_t idle_backoff;     // longest sleep of an idle wavefront worker, in units of 2048 cycles
+  int32_t cu_pool;          // 1: ready small trades beyond the local stack go to the workgroup's LDS pool
   int32_t big_lds_max;
   int32_t nbig;
   int32_t stack_cap;

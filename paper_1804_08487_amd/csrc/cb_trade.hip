@@ -92,8 +92,17 @@ struct BigLds {
 static_assert(offsetof(BigLds, sbcnt) == offsetof(BigLds, sboff) + kTradeBlock * sizeof(int32_t),
               "split buffer spans sboff and sbcnt");
 
-union TradeLds {
+// Ready small trades shared by the wavefronts of one workgroup (slot -1:
+// empty): a wavefront that makes more trades ready than it keeps leaves the
+// rest here, where the workgroup's idle wavefronts find them at LDS cost.
+constexpr int kPoolSlots = kWave;
+struct SmallLds {
   WaveLds wave[kWavesPerBlock];
+  int32_t pool[kPoolSlots];
+};
+
+union TradeLds {
+  SmallLds small;
   BigLds big;
 };
 
@@ -447,7 +456,8 @@ struct ItemSrc {
 };
 
 struct WriteCounts {   // per lane
-  unsigned long long fwd, emit, push, moved;
+  unsigned long long fwd, emit, push;
+  uint32_t moved;
 };
 
 // Item o: its entry, with the side bit replaced by the side of its owner
@@ -490,7 +500,7 @@ __device__ __forceinline__ void write_range(const TradeArgs& A, const ItemSrc& S
         towner[r] = ent_side(e) ? S.v : S.u;
         // a disjoint neighbour that changed sides (the published items of a
         // shared phase no longer carry their old side)
-        if (!kShared && o < S.nD) W.moved += (uint64_t)(ent_side(S.E[S.D[o]]) != (o < S.a ? 0 : 1));
+        if (!kShared && o < S.nD) W.moved += (uint32_t)(ent_side(S.E[S.D[o]]) != (o < S.a ? 0 : 1));
       }
     }
     // members of a giant node's list learn their tag here, one gather each,
@@ -819,8 +829,35 @@ struct WaveState {
   int32_t top;        // local stack depth (uniform)
   int32_t ndone;
   int32_t shard;      // home shard of the small-trade queues
+  int32_t* pool;      // the workgroup's pool of ready trades (LDS; null: none)
   unsigned long long n_small, n_push, work, fwd, emit, ticks, moved;
 };
+
+// Put trade t into a free pool slot (wave-wide, t uniform): false if the pool
+// stays full after a few tries.
+__device__ __forceinline__ bool pool_put(int32_t* pool, int32_t t) {
+  for (int tries = 0; tries < 4; ++tries) {
+    const uint64_t freem = ballot(pool[lane_id()] < 0);
+    if (!freem) return false;
+    int32_t ok = 0;
+    if (lane_id() == 0) ok = atomicCAS(&pool[__builtin_ctzll(freem)], -1, t) == -1;
+    if (wave_bcast(ok, 0)) return true;
+  }
+  return false;
+}
+
+// Take a trade from the pool (wave-wide): -1 if it is empty.
+__device__ __forceinline__ int32_t pool_take(int32_t* pool) {
+  for (int tries = 0; tries < 4; ++tries) {
+    const uint64_t full = ballot(pool[lane_id()] >= 0);
+    if (!full) return -1;
+    int32_t k = -1;
+    if (lane_id() == 0) k = atomicExch(&pool[__builtin_ctzll(full)], -1);
+    k = wave_bcast(k, 0);
+    if (k >= 0) return k;
+  }
+  return -1;
+}
 
 // Drops the dependency counters of later trades reached by trade k's
 // output; a ready small trade goes to the local stack or the global queue,
@@ -849,10 +886,21 @@ __device__ __forceinline__ void wave_release_item(const TradeArgs& A, WaveLds& W
   const int cnt = popc64(m);
   const int room = A.stack_cap - S.top;
   const int r = rank_below(m);
-  const uint64_t spill = ballot((keep && r >= room) || big);
+  // beyond the local stack: the workgroup's pool, else the global queues
+  uint64_t rest = ballot(keep && r >= room);
+  if (rest && S.pool) {
+    uint64_t pooled = 0;
+    for (uint64_t left = rest; left; left &= left - 1) {
+      const int ln = __builtin_ctzll(left);
+      if (pool_put(S.pool, wave_bcast(t, ln))) pooled |= 1ull << ln;
+      else break;
+    }
+    rest &= ~pooled;
+  }
+  const uint64_t spill = rest | ballot(big);
   if (spill) publish_wait();
   if (keep && r < room) W.stack[S.top + r] = t;
-  else if (keep) queue_push(A, A.qs, kCwQsTail0, S.shard, t);
+  else if (keep && ((rest >> lane_id()) & 1ull)) queue_push(A, A.qs, kCwQsTail0, S.shard, t);
   else if (big) queue_push(A, A.qb, kCwQbTail0, S.shard % kQbShards, t);
   wave_sync();
   S.top += cnt < room ? cnt : (room > 0 ? room : 0);
@@ -1006,11 +1054,12 @@ constexpr int32_t kFlushEvery = 32;   // trades between progress flushes
 // would wait for a sleeping poller, want a short back-off.
 constexpr int kQsScan = 1;
 
-__device__ __forceinline__ void small_worker(const TradeArgs& A, WaveLds& W) {
+__device__ __forceinline__ void small_worker(const TradeArgs& A, WaveLds& W, int32_t* pool) {
   const int l = lane_id();
   const int32_t wid = (int32_t)(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6));
   WaveState S{};
   S.shard = wid % kQsShards;
+  S.pool = A.cu_pool ? pool : nullptr;
   Watchdog wd{0, 0};
   int32_t backoff = 1;
   bool sources_left = true;   // no trade becomes a source during the kernel
@@ -1020,6 +1069,8 @@ __device__ __forceinline__ void small_worker(const TradeArgs& A, WaveLds& W) {
     if (S.top > 0) {
       S.top -= 1;
       k = W.stack[S.top];
+    } else if (S.pool && (k = pool_take(S.pool)) >= 0) {
+      // a ready trade left by a wavefront of this workgroup
     } else {
       if (l == 0) {
         if (sources_left) {
@@ -1051,7 +1102,11 @@ __device__ __forceinline__ void small_worker(const TradeArgs& A, WaveLds& W) {
         backoff = 1;
         continue;
       }
-      idle_backoff(backoff);
+      // sleep, but look at the workgroup's pool between short naps
+      for (int32_t i = 0; i < backoff; ++i) {
+        __builtin_amdgcn_s_sleep(32);
+        if (S.pool && ballot(S.pool[l] >= 0)) break;
+      }
       backoff = backoff < A.idle_backoff ? backoff * 2 : A.idle_backoff;
       continue;
     }
@@ -2248,8 +2303,9 @@ __device__ __forceinline__ void big_trade(const TradeArgs& A, int32_t k, BigLds&
   counters[1] += W.fwd;
   counters[2] += W.push;
   counters[3] += W.emit;
-  counters[8] += W.moved;
-  if (tid == 0 && !share) counters[9] += 1;
+  const int32_t moved = wave_sum((int32_t)W.moved);
+  if (lane_id() == 0 && moved) atomicAdd(&A.stats[kStatMoved], (unsigned long long)moved);
+  if (tid == 0 && !share) atomicAdd(&A.stats[kStatCounted], 1ull);
   __syncthreads();
 }
 
@@ -2258,8 +2314,7 @@ __device__ __forceinline__ void big_worker(const TradeArgs& A, BigLds& B) {
   uint64_t* slot = A.slots + (int64_t)blockIdx.x * A.slot_elems;
   // per-thread partial counters: work, forwarded, pushes, emitted, then
   // (thread 0) ticks of gather, split, write, release
-  // ..., then moved neighbours (every thread) and counted trades (thread 0)
-  unsigned long long counters[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  unsigned long long counters[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   unsigned long long max_ticks = 0;
   unsigned long long n_big = 0;
   Watchdog wd{0, 0};
@@ -2340,8 +2395,6 @@ __device__ __forceinline__ void big_worker(const TradeArgs& A, BigLds& B) {
   if (counters[1]) atomicAdd(&A.stats[kStatForward], counters[1]);
   if (counters[2]) atomicAdd(&A.stats[kStatPush], counters[2]);
   if (counters[3]) atomicAdd(&A.stats[kStatEmit], counters[3]);
-  if (counters[8]) atomicAdd(&A.stats[kStatMoved], counters[8]);
-  if (tid == 0 && counters[9]) atomicAdd(&A.stats[kStatCounted], counters[9]);
   if (tid == 0 && n_big) atomicAdd(&A.stats[kStatBig], n_big);
   if (tid == 0) {
     const unsigned long long busy = counters[4] + counters[5] + counters[6] + counters[7];
@@ -2360,7 +2413,9 @@ __global__ void __launch_bounds__(kTradeBlock) k_trade(TradeArgs A) {
   if ((int32_t)blockIdx.x < A.nbig) {
     big_worker(A, lds.big);
   } else {
-    small_worker(A, lds.wave[threadIdx.x >> 6]);
+    for (int i = threadIdx.x; i < kPoolSlots; i += blockDim.x) lds.small.pool[i] = -1;
+    __syncthreads();
+    small_worker(A, lds.small.wave[threadIdx.x >> 6], lds.small.pool);
   }
 }
 
