@@ -120,7 +120,9 @@ struct cb_graph {
   int32_t* sbpre = nullptr;
   int64_t sbpre_stride = 1;
   int32_t* rows = nullptr;      // rebuild size classes: small, then mid, then big rows
+  int64_t* big_off = nullptr;   // entries of the big rows laid end to end (n_big + 1)
   int64_t n_small = 0, n_mid = 0, n_big = 0;
+  int64_t big_entries = 0;      // entries in the big rows
 
   int32_t nb = 1;               // matching buckets of all chains
   int keybits_node = 1, keybits_entry = 1;
@@ -280,6 +282,7 @@ void plan_buffers(cb_graph* g, BufPlan& P, bool with_col = true) {
   P.add(&g->slots, (int64_t)g->nbig_alloc * g->slot_elems);
   P.add(&g->sbpre, (int64_t)g->nbig_alloc * g->sbpre_stride);
   P.add(&g->rows, n);
+  P.add(&g->big_off, g->n_big + 1);
   P.add(&g->ch_node_base, C + 1);
   P.add(&g->ch_trade_base, C + 1);
   P.add(&g->ch_bucket_base, C + 1);
@@ -628,9 +631,14 @@ cb_status enqueue_round(cb_graph* g, hipStream_t st, int last_step, bool advance
     if (g->n_mid)
       hipLaunchKernelGGL(k_segsort_mid, dim3(grid_for(g->n_mid, 1, 65536)), dim3(256), 0, st,
                          rm, g->n_mid, g->rp, g->col_out, g->col, g->keybits_node, N, g->ctrl);
-    if (g->n_big)
+    if (g->n_big) {
       hipLaunchKernelGGL(k_segsort_big, dim3(grid_for(g->n_big, 1, 8192)), dim3(256), 0, st,
-                         rb, g->n_big, g->rp, g->col_out, g->col, g->keybits_node, N, g->ctrl);
+                         rb, g->n_big, g->rp, g->col_out, g->col, g->keybits_node, NextScan{}, g->ctrl);
+      if (lookahead) {
+        hipLaunchKernelGGL(k_scan_big_rows, dim3((unsigned)std::max<int64_t>(1, (g->big_entries + kScanChunk - 1) / kScanChunk)),
+                           dim3(256), 0, st, rb, g->n_big, g->big_off, g->rp, g->col, N, g->ctrl);
+      }
+    }
   }
   if (lookahead) {
     g->prepared = true;
@@ -720,13 +728,14 @@ void size_graph(cb_graph* g, const ChainSrc* src, int32_t count, int64_t d1, int
 // Rows per rebuild size class.
 void count_classes(cb_graph* g, const ChainSrc* src, int32_t count) {
   g->n_small = g->n_mid = g->n_big = 0;
+  g->big_entries = 0;
   for (int32_t c = 0; c < count; ++c)
     for (int64_t x = 0; x < src[c].n; ++x) {
       const int64_t d = src[c].rp[x + 1] - src[c].rp[x];
       if (d == 0) continue;
       if (d <= kSegSmallMax) ++g->n_small;
       else if (d <= kSegMidMax) ++g->n_mid;
-      else ++g->n_big;
+      else { ++g->n_big; g->big_entries += d; }
     }
 }
 
@@ -747,6 +756,9 @@ bool init_device_state(cb_graph* g, bool validate, char* msg, size_t cap) {
   if (g->n > 0)
     hipLaunchKernelGGL(k_classify_rows, dim3(grid_for(g->n, 256, 8192)), dim3(256), 0, st, g->n, g->rp, g->rows,
                        g->n_small, g->n_small + g->n_mid, g->row_cur);
+  if (g->n_big > 0)
+    hipLaunchKernelGGL(k_big_offsets, dim3(1), dim3(1024), 0, st, g->rows + g->n_small + g->n_mid, g->n_big, g->rp,
+                       g->big_off);
   if (validate && g->nnz > 0)
     hipLaunchKernelGGL(k_validate, dim3((unsigned)((g->nnz + kScanChunk - 1) / kScanChunk)), dim3(256), 0, st,
                        g->n, g->nnz, g->rp, g->col, g->ctrl);

@@ -254,6 +254,9 @@ __global__ void k_segsort_mid(const int32_t* rows, int64_t nrows, const int64_t*
                               const int32_t* ctrl);
 __global__ void k_segsort_big(const int32_t* rows, int64_t nrows, const int64_t* rp,
                               int32_t* src, int32_t* dst, int keybits, NextScan N, const int32_t* ctrl);
+__global__ void k_big_offsets(const int32_t* rows, int64_t nrows, const int64_t* rp, int64_t* boff);
+__global__ void k_scan_big_rows(const int32_t* rows, int64_t nrows, const int64_t* boff, const int64_t* rp,
+                                const int32_t* col, NextScan N, const int32_t* ctrl);
 __global__ void k_classify_rows(int64_t n, const int64_t* rp, int32_t* rows, int64_t base1,
                                 int64_t base2, unsigned long long* cur);
 __global__ void k_copy_shift(int32_t* dst, const int32_t* src, int64_t count, int32_t delta);

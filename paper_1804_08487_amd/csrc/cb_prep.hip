@@ -591,6 +591,58 @@ __global__ void k_copy_shift(int32_t* dst, const int32_t* src, int64_t count, in
     dst[i] = src[i] + delta;
 }
 
+// Offsets of the big rows' entries laid end to end: boff[i] = sum of the
+// sizes of rows[0..i) (one workgroup; the big rows are few).
+__global__ void k_big_offsets(const int32_t* rows, int64_t nrows, const int64_t* rp, int64_t* boff) {
+  __shared__ int32_t scratch[17];
+  __shared__ int64_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int64_t base = 0; base < nrows; base += blockDim.x) {
+    const int64_t i = base + threadIdx.x;
+    const int32_t d = i < nrows ? (int32_t)(rp[rows[i] + 1] - rp[rows[i]]) : 0;
+    int32_t total;
+    const int32_t ex = block_excl_scan(d, scratch, &total);
+    if (i < nrows) boff[i] = carry + ex;
+    __syncthreads();
+    if (threadIdx.x == 0) carry += total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) boff[nrows] = carry;
+}
+
+// The next round's scan of the big rows (more than kSegMidMax entries),
+// done after their rebuild with their entries split evenly over workgroups
+// (a hub row would hold up one workgroup for long otherwise). A chunk of
+// kScanChunk entries meets at most two big rows.
+__global__ void __launch_bounds__(256)
+k_scan_big_rows(const int32_t* rows, int64_t nrows, const int64_t* boff, const int64_t* rp,
+                const int32_t* col, NextScan N, const int32_t* ctrl) {
+  if (ctrl[cw(kCwErr)]) return;
+  const int64_t total = boff[nrows];
+  const int64_t v0 = (int64_t)blockIdx.x * kScanChunk;
+  if (v0 >= total) return;
+  const int64_t v1 = v0 + kScanChunk < total ? v0 + kScanChunk : total;
+  const int64_t i0 = row_of_entry(boff, 0, nrows - 1, v0);
+  const int64_t i1 = row_of_entry(boff, i0, nrows - 1, v1 - 1);
+  const int32_t x0 = rows[i0], x1 = rows[i1];
+  const RowScan r0 = row_scan(N, x0), r1 = row_scan(N, x1);
+  const int64_t split = boff[i0 + 1];
+  const int64_t e0 = rp[x0] - boff[i0], e1 = rp[x1] - boff[i1];
+  int32_t c0 = 0, c1 = 0;
+  for (int64_t v = v0 + threadIdx.x; v < v1; v += blockDim.x) {
+    if (v < split) {
+      const int64_t e = e0 + v;
+      c0 += scan_entry(N, r0, e, col[e]);
+    } else {
+      const int64_t e = e1 + v;
+      c1 += scan_entry(N, r1, e, col[e]);
+    }
+  }
+  add_dep(N, r0, c0);
+  add_dep(N, r1, c1);
+}
+
 // ---------------------------------------------------------------- validate
 // Every entry: id in range, not the row's own id, strictly above its left
 // neighbour in the row, and present in the neighbour's row (symmetry).

@@ -236,12 +236,13 @@ def test_upload_validation_rejects(name):
 
 # ---- the next round prepared by the rebuild (cross-round fusion)
 
-@pytest.mark.parametrize("giant", [0, 20])
-def test_prepared_round_state_equals_oracle(orc, giant):
+@pytest.mark.parametrize("giant,graph", [(0, "pld"), (20, "pld"), (0, "hub"), (6144, "hub")])
+def test_prepared_round_state_equals_oracle(orc, giant, graph):
     """After a full round the next round's matching and dependency counts
-    (computed by the lookahead matching and the rebuild's scan) equal the
-    oracle's for (seed, round + 1) on the new graph."""
-    rp, col = graphgen.pld_graph(3000, 2, 300, 2.0, 11)
+    (computed by the lookahead matching, the rebuild's scan of rows up to 4096
+    entries and the split scan of bigger rows) equal the oracle's for
+    (seed, round + 1) on the new graph."""
+    rp, col = graphgen.pld_graph(3000, 2, 300, 2.0, 11) if graph == "pld" else _hub_graph()
     n = len(rp) - 1
     g = cb.Graph(rp, col)
     g.set_option(cb.OPT_GIANT_DEG, giant)
