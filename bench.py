@@ -2,7 +2,8 @@
 """Throughput of the global Curveball super-step on one MI355X.
 
 One step = one global trade (matching, dependency scan, trade kernel,
-per-row rebuild) of the whole graph, inputs resident in HBM. Default
+per-row rebuild) of the whole graph, inputs resident in HBM; the schedule
+options come from the library's autotuner, run before the timed rounds. Default
 workload: n = 2^24 nodes, degrees i.i.d. Pld([20, 2^20), gamma = 2.2), erased
 configuration model (graph seed 1), chain seed 1: W warm-up rounds, then K
 timed rounds, repeated R times from a fresh upload; value = m * K / (wall
@@ -188,11 +189,16 @@ def run_single(args, cb, row_ptr, col):
     step_ms_all = []
     kernel_ms = None
     st = None
+    tune = None
     for rep in range(args.reps):
         t_up = time.perf_counter()
         g = cb.Graph(row_ptr, col, validate=False)
         torch.cuda.synchronize()
         t_up = time.perf_counter() - t_up
+        if args.tune:
+            # the library's autotuner (cached per process by the graph's shape),
+            # before the timed rounds
+            tune = g.autotune(trial_rounds=1 if n >= (1 << 22) else 2, use_cache=True)
         for opt, val in ((cb.OPT_SMALL_MAX, args.small_max), (cb.OPT_BIG_WORKERS, args.big_workers),
                          (cb.OPT_GRID_BLOCKS, args.grid_blocks), (cb.OPT_LOCAL_STACK, args.local_stack),
                          (cb.OPT_FUSE_NEXT, args.fuse)):
@@ -214,7 +220,7 @@ def run_single(args, cb, row_ptr, col):
         print(f"[bench] repetition {rep}: {args.steps} rounds in {wall:.3f} s (upload {t_up:.2f} s); "
               f"kernel ms {[round(x, 2) for x in km]}", file=sys.stderr, flush=True)
     kernel_ms = [x / args.reps for x in kernel_ms]
-    return reps, step_ms_all, kernel_ms, st, t_up
+    return reps, step_ms_all, kernel_ms, st, t_up, tune
 
 
 def run_batch(args, cb, graphs, seeds):
@@ -323,6 +329,8 @@ def main(argv=None) -> int:
     ap.add_argument("--big-workers", type=int, default=None)
     ap.add_argument("--grid-blocks", type=int, default=None)
     ap.add_argument("--local-stack", type=int, default=None)
+    ap.add_argument("--tune", type=int, default=1, choices=[0, 1],
+                    help="single chain: options from the library's autotuner (default on)")
     ap.add_argument("--fuse", type=int, default=None, choices=[0, 1],
                     help="prepare the next round in the rebuild (default on)")
     ap.add_argument("--requests", type=int, default=32, help="requests of the served workload")
@@ -403,7 +411,7 @@ def main(argv=None) -> int:
     if args.workload == "batch":
         reps, step_ms, tune, t_single = run_batch(args, cb, graphs, seeds)
     else:
-        reps, step_ms, kernel_ms, st, t_up = run_single(args, cb, row_ptr, col)
+        reps, step_ms, kernel_ms, st, t_up, tune = run_single(args, cb, row_ptr, col)
     wall = statistics.median(reps)
     ms_per_step = wall * 1e3 / args.steps
     value = m * args.steps / wall
@@ -465,6 +473,7 @@ def main(argv=None) -> int:
             out["superstep_hbm_frac"] = traffic["step_bytes"] / (ms_per_step / 1e3) / HBM_PEAK
             out["superstep_traffic_bytes"] = traffic["step_bytes"]
         out["round_stats"] = st
+        out["autotune"] = tune
         out["upload_s_pcie_inclusive"] = t_up
         if args.cpu_trades > 0:
             print("[bench] timing the oracle sample on the host", file=sys.stderr, flush=True)
