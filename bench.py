@@ -198,7 +198,7 @@ def run_single(args, cb, row_ptr, col):
         if args.tune:
             # the library's autotuner (cached per process by the graph's shape),
             # before the timed rounds
-            tune = g.autotune(trial_rounds=1 if n >= (1 << 22) else 2, use_cache=True)
+            tune = g.autotune(trial_rounds=2, use_cache=True)
         for opt, val in ((cb.OPT_SMALL_MAX, args.small_max), (cb.OPT_BIG_WORKERS, args.big_workers),
                          (cb.OPT_GRID_BLOCKS, args.grid_blocks), (cb.OPT_LOCAL_STACK, args.local_stack),
                          (cb.OPT_FUSE_NEXT, args.fuse)):

@@ -293,7 +293,8 @@ cb_status batch_download(cb_graph* g, int32_t chain, int32_t* col);
  * (CB_OPT_HELP_MIN), their chunk size (CB_OPT_HELP_CHUNK) and the workgroup
  * workers (CB_OPT_BIG_WORKERS) by
  * timing `trial_rounds` rounds per candidate from the graph's current state
- * (coordinate descent from the current options), then restores that state and
+ * (coordinate descent from the current options; a candidate replaces the
+ * best only when it is more than 1% faster), then restores that state and
  * keeps the fastest options. The schedule never changes a result. Results are
  * cached for the process by the shape of the graph (log2 of chains, nodes,
  * entries and largest degree); with use_cache != 0 a cached choice is applied

@@ -1467,7 +1467,8 @@ cb_status graph_autotune(cb_graph* g, uint32_t trial_rounds, int32_t use_cache, 
       double ms = 0;
       s = trial(&ms);
       best.evaluated++;
-      if (s == CB_OK && ms < best.ms_per_round) {
+      // a candidate must beat the best by more than round-to-round noise
+      if (s == CB_OK && ms < 0.99 * best.ms_per_round) {
         const int ev = best.evaluated;
         best = cand;
         best.ms_per_round = ms;
