@@ -75,24 +75,36 @@ cb_status cb_set_allocator(const cb_allocator* allocator);
 
 /* Copy a host CSR (row_ptr: n+1 int64, col: row_ptr[n] int32; the caller
  * keeps ownership) to the current HIP device and create a handle that owns
- * all device state of one chain. stream: a hipStream_t on which every later
- * call of this handle is ordered (NULL: the handle creates its own).
- * Synchronises the stream before returning. */
+ * all device state of one chain. The graph is the paper's simple undirected
+ * graph on nodes 0..n-1 (Sec. 2, Preliminaries and Notation): no loops, no
+ * multi-edges, each edge {x, y} stored in both rows, as the trade's
+ * neighbourhoods A_x (Def. "Simple Undirected Trade", Sec. 3.2). With
+ * CB_VALIDATE the device checks that form (CB_ENOTSIMPLE otherwise).
+ * stream: a hipStream_t on which every later call of this handle is ordered
+ * (NULL: the handle creates its own). Synchronises the stream before
+ * returning. Errors: CB_EINVAL (sizes, NULL pointers, offsets),
+ * CB_ENOTSIMPLE, CB_ENOMEM (nothing is kept), CB_EDEVICE. */
 cb_status graph_upload(int64_t n, const int64_t* row_ptr, const int32_t* col,
                        void* stream, uint32_t flags, cb_graph** out);
 
-/* Sizes for download buffers: n and nnz = 2m. */
+/* Sizes for download buffers: n and nnz = 2m (each undirected edge of the
+ * graph, Sec. 2, counts once in each of its two rows). */
 cb_status graph_info(const cb_graph* g, int64_t* n, int64_t* nnz);
 
-/* Apply one global trade with the given chain seed and round number.
- * Asynchronous: enqueued on the handle's stream, returns before it runs. */
+/* Apply one global trade (Def. "Undirected Global Trade", Sec. 3.3) with
+ * the given chain seed and round number, under the random-number convention
+ * above. Asynchronous: enqueued on the handle's stream, returns before it
+ * runs; device-side faults surface at the next synchronising call. For a
+ * graph from batch_upload: CB_EINVAL (use batch_run). */
 cb_status global_trade(cb_graph* g, uint64_t seed, uint32_t round);
 
 /* Wait for all enqueued work; report device-side faults. */
 cb_status graph_sync(cb_graph* g);
 
 /* Synchronise and copy the current graph into caller buffers of n+1 and
- * nnz entries (row_ptr may be NULL: it equals the uploaded one). */
+ * nnz entries (row_ptr may be NULL: it equals the uploaded one, because a
+ * trade preserves every degree, Sec. 3.2). Rows come back strictly
+ * ascending. Reports device-side faults (then the handle is poisoned). */
 cb_status graph_download(cb_graph* g, int64_t* row_ptr, int32_t* col);
 
 /* Release all device memory of the handle (NULL is a no-op). */
@@ -319,7 +331,7 @@ cb_status graph_autotune(cb_graph* g, uint32_t trial_rounds, int32_t use_cache, 
  * Simple Undirected Curveball (Sec. 3.2, the paragraph after the trade
  * figure): a chain of single trades, each of a node pair drawn uniformly at
  * random with a uniform split (the comparison chain of the mixing study,
- * Sec. 6, where n/2 single trades make one super-step). Step s of the chain
+ * Sec. 5.1, where n/2 single trades make one super-step). Step s of the chain
  * with seed `seed` trades u = bounded(philox64(seed; s_lo, s_hi, 0,
  * 0x43425550), n) and v = bounded(philox64(seed; s_lo, s_hi, 1, 0x43425550),
  * n - 1), plus one if v >= u; its split draws philox64(seed; s, 0xFFFFFFFF,

@@ -1,5 +1,5 @@
 """Chain-quality measurements on the GPU chains (the paper's mixing study,
-Sec. 6 "Mixing of Edge-Switching, Curveball and Global Curveball", and its
+Sec. 5.1 "Mixing of Edge-Switching, Curveball and Global Curveball", and its
 appendix on swaps performed by Curveball and Global Curveball).
 
 The chains run in the HIP library through the C ABI (global trades, or n/2
