@@ -507,11 +507,16 @@ __device__ __forceinline__ void write_range(const TradeArgs& A, const ItemSrc& S
     // and their bitmap words are cleared for the next round (every member of
     // a giant's set is an item of this trade; nothing reads the set again
     // this round)
+    // the target rows' offsets are loaded with the tags (one round trip)
     int32_t tinf[kBatch];
+    int64_t rxa[kBatch];
+    int32_t dxa[kBatch];
 #pragma unroll
     for (int r = 0; r < kBatch; ++r) {
       const bool unk = tx[r] >= 0 && ttag[r] == kTagUnknown;
       tinf[r] = unk ? A.tinfo[tx[r]] : 0;
+      rxa[r] = tx[r] >= 0 ? A.rp[tx[r]] : 0;
+      dxa[r] = tx[r] >= 0 ? (int32_t)(A.rp[tx[r] + 1] - rxa[r]) : 0;
       if (unk) {
         if (S.gu >= 0) A.gs.bm[(int64_t)S.gu * A.gs.gwords + (tx[r] >> 6)] = 0ull;
         if (S.gv >= 0) A.gs.bm[(int64_t)S.gv * A.gs.gwords + (tx[r] >> 6)] = 0ull;
@@ -554,8 +559,8 @@ __device__ __forceinline__ void write_range(const TradeArgs& A, const ItemSrc& S
       pu += popc64(mu[r]);
       pv += popc64(mv[r]);
       if (tx[r] < 0 || ttag[r] == kTagPartner) continue;
-      const int64_t rx = A.rp[tx[r]];
-      const int32_t dx = (int32_t)(A.rp[tx[r] + 1] - rx);
+      const int64_t rx = rxa[r];
+      const int32_t dx = dxa[r];
       if (tp[r] >= dx) { raise_error(A, ttag[r] == kTagEmit ? kErrOut : kErrInbox, S.k, tx[r]); continue; }
       if (ttag[r] == kTagEmit) {
         A.col_out[rx + tp[r]] = towner[r];
@@ -862,16 +867,8 @@ __device__ __forceinline__ int32_t pool_take(int32_t* pool) {
 // Drops the dependency counters of later trades reached by trade k's
 // output; a ready small trade goes to the local stack or the global queue,
 // a ready large one to the workgroup queues.
-__device__ __forceinline__ void wave_release_item(const TradeArgs& A, WaveLds& W, WaveState& S,
-                                                  bool fwd, uint32_t tag, int32_t k) {
-  bool ready = false;
-  int32_t t = -1;
-  if (fwd) {
-    t = tag_trade(tag);
-    const int32_t old = atomic_add(&A.dep[t], -1);
-    if (old <= 0) raise_error(A, kErrDep, t, -1 - old);
-    ready = old == 1;
-  }
+__device__ __forceinline__ void wave_release_ready(const TradeArgs& A, WaveLds& W, WaveState& S,
+                                                   bool ready, int32_t t, int32_t k) {
   if (ballot(ready) == 0) return;
   bool big = false;
   if (ready) {
@@ -916,34 +913,53 @@ __device__ __forceinline__ void small_trade(const TradeArgs& A, int32_t k, int32
   const int32_t niu = load_agent(&A.inbox_cur[u]);
   const int32_t niv = load_agent(&A.inbox_cur[v]);
 
-  // ---- gather both lists into E (u's at [0, du), v's at [du, s))
-  int32_t nf[2] = {0, 0};
+  // ---- gather both lists into E (u's at [0, du), v's at [du, s)): row
+  // entries of later nodes from the front of each side's range, arrivals
+  // from its back. A row's inbox has as many slots as the row, so slot e is
+  // read with row entry e (kept if e is below the arrival count): every
+  // load of both rows in one round trip.
+  constexpr int kGatherIt = kSmallCap / kWave;
+  int32_t gx[kGatherIt], gt[kGatherIt], gy[kGatherIt];
 #pragma unroll
-  for (int side = 0; side < 2; ++side) {
-    const int64_t b = side ? bv : bu;
-    const int32_t d = side ? dv : du;
-    const int32_t off = side ? du : 0;
-    int32_t cnt = 0;
-    for (int32_t c = 0; c < d; c += kWave) {
-      const int32_t e = c + l;
-      int32_t x = 0, t = -1;
-      if (e < d) { x = A.col[b + e]; t = A.col_t[b + e]; }
-      const bool fresh = e < d && tinfo_trade(t) >= k;
-      const uint64_t m = ballot(fresh);
-      if (fresh) W.E[off + cnt + rank_below(m)] = make_entry(x, side, tag_of(t, k));
-      cnt += popc64(m);
+  for (int it = 0; it < kGatherIt; ++it) {
+    const int32_t i = it * kWave + l;
+    gx[it] = 0;
+    gt[it] = -1;
+    gy[it] = 0;
+    if (i < s) {
+      const int64_t at = i < du ? bu + i : bv + (i - du);
+      gx[it] = A.col[at];
+      gt[it] = A.col_t[at];
+      gy[it] = load_agent(&A.inbox[at]);
     }
-    nf[side] = cnt;
-    const int32_t ni = side ? niv : niu;
-    if (cnt + ni != d) { raise_error(A, kErrGather, k, (cnt + ni) - d); return; }
-    for (int32_t j = l; j < ni; j += kWave)
-      W.E[off + cnt + j] = make_entry(load_agent(&A.inbox[b + j]), side, kTagEmit);
   }
+  int32_t cnt0 = 0, cnt1 = 0;
+#pragma unroll
+  for (int it = 0; it < kGatherIt; ++it) {
+    if (it * kWave >= s) break;   // uniform across the wavefront
+    const int32_t i = it * kWave + l;
+    const int side = i < du ? 0 : 1;
+    const bool fresh = i < s && tinfo_trade(gt[it]) >= k;
+    const uint64_t m0 = ballot(fresh && side == 0);
+    const uint64_t m1 = ballot(fresh && side == 1);
+    if (fresh)
+      W.E[side ? du + cnt1 + rank_below(m1) : cnt0 + rank_below(m0)] = make_entry(gx[it], side, tag_of(gt[it], k));
+    cnt0 += popc64(m0);
+    cnt1 += popc64(m1);
+    if (i < du) {
+      if (i < niu && niu <= du) W.E[du - 1 - i] = make_entry(gy[it], 0, kTagEmit);
+    } else if (i < s) {
+      if (i - du < niv && niv <= dv) W.E[s - 1 - (i - du)] = make_entry(gy[it], 1, kTagEmit);
+    }
+  }
+  if (cnt0 + niu != du) { raise_error(A, kErrGather, k, (cnt0 + niu) - du); return; }
+  if (cnt1 + niv != dv) { raise_error(A, kErrGather, k, (cnt1 + niv) - dv); return; }
   wave_sync();
   wave_bitonic_sort(W.E, (uint32_t)s);
 
-  // ---- classify: shared (C), partner (P), disjoint (D, kept ascending)
-  int32_t nD = 0, a = 0;
+  // ---- classify: shared (C), partner (P), disjoint (D[0..nD), ascending);
+  // the kept ones (C, P) fill D[nD..s) from the back
+  int32_t nD = 0, a = 0, nk = 0;
   for (int32_t c = 0; c < s; c += kWave) {
     const int32_t i = c + l;
     bool isD = false;
@@ -961,66 +977,108 @@ __device__ __forceinline__ void small_trade(const TradeArgs& A, int32_t k, int32
     if (isD) W.D[nD + rank_below(m)] = i;
     nD += popc64(m);
     a += popc64(ballot(isD && side == 0));
+    const uint64_t mk = ballot(i < s && !isD);
+    if (i < s && !isD) W.D[s - 1 - (nk + rank_below(mk))] = i;
+    nk += popc64(mk);
   }
   wave_sync();
   const DrawKey dk = draw_key(A, k);
   wave_split(W.D, nD, a, dk.seed, dk.round, dk.idx, W.R);
 
-  // ---- write: own-row finals, other-row finals, forwards; each chunk's
-  // forwards then drop their target trades' counters once the chunk's
-  // writes are complete
-  int32_t nfwd = 0, nemit = 0, nmoved = 0;
+  // ---- write: kWriteIt * 64 items at a time (all of most trades). Item o is
+  // entry E[D[o]]; a disjoint one (o < nD) goes to u below position a, a
+  // kept one stays with its side. Own-row finals take their positions with
+  // one out_cur atomic per row; other-row finals and forwards reserve a slot
+  // of their target row; once this wavefront's writes are complete, every
+  // forward drops its target trade's counter (one round trip for all).
+  constexpr int kWriteIt = 8;
+  int32_t nmoved = 0, nfwd = 0, nemit = 0;
+  for (int32_t o0 = 0; o0 < s; o0 += kWriteIt * kWave) {
+  int32_t ix[kWriteIt], ip[kWriteIt], isd[kWriteIt];
+  uint32_t itag[kWriteIt];
+  int64_t irx[kWriteIt];
+  int32_t idd[kWriteIt];
+  int32_t nu = 0, nv = 0;
 #pragma unroll
-  for (int pass = 0; pass < 2; ++pass) {
-    const int32_t count = pass ? nD : s;
-    for (int32_t c = 0; c < count; c += kWave) {
-      const int32_t o = c + l;
-      bool valid = o < count;
-      int32_t owner = u, x = 0;
-      uint32_t tag = 0;
-      if (valid) {
-        if (pass == 0) {
-          const uint64_t e = W.E[o];
-          x = ent_node(e);
-          tag = ent_tag(e);
-          const bool isP = tag == kTagPartner;
-          const bool isC = !isP && ((o > 0 && ent_node(W.E[o - 1]) == x) ||
-                                    (o + 1 < s && ent_node(W.E[o + 1]) == x));
-          valid = isP || isC;
-          owner = ent_side(e) ? v : u;
-        } else {
-          const uint64_t e = W.E[W.D[o]];
-          x = ent_node(e);
-          tag = ent_tag(e);
-          owner = o < a ? u : v;
-          nmoved += ent_side(e) != (o < a ? 0 : 1) ? 1 : 0;
-        }
-      }
-      const bool own = valid && tag <= kTagPartner;
-      const uint64_t mu = ballot(own && owner == u);
-      const uint64_t mv = ballot(own && owner == v);
-      int32_t baseu = 0, basev = 0;
-      if (l == 0) {
-        if (mu) baseu = atomic_add(&A.out_cur[u], popc64(mu));
-        if (mv) basev = atomic_add(&A.out_cur[v], popc64(mv));
-      }
-      baseu = wave_bcast(baseu, 0);
-      basev = wave_bcast(basev, 0);
-      if (own) {
-        const int32_t p = owner == u ? baseu + rank_below(mu) : basev + rank_below(mv);
-        const int32_t dd = owner == u ? du : dv;
-        if (p < dd) A.col_out[(owner == u ? bu : bv) + p] = x; else raise_error(A, kErrOut, k, -2 - owner);
-      }
-      if (valid) route_edge(A, owner, x, tag, k);
-      const bool fwd = valid && tag >= 2u;
-      const uint64_t mf = ballot(fwd);
-      nfwd += popc64(mf);
-      nemit += popc64(ballot(valid && tag == kTagEmit));
-      if (mf) {
-        publish_wait();
-        wave_release_item(A, W, S, fwd, tag, k);
+  for (int it = 0; it < kWriteIt; ++it) {
+    const int32_t o = o0 + it * kWave + l;
+    ix[it] = -1;
+    itag[it] = kTagPartner;
+    isd[it] = 0;
+    ip[it] = 0;
+    irx[it] = 0;
+    idd[it] = 0;
+    if (o < s) {
+      const uint64_t e = W.E[W.D[o]];
+      ix[it] = ent_node(e);
+      itag[it] = ent_tag(e);
+      isd[it] = o < nD ? (o < a ? 0 : 1) : ent_side(e);
+      if (o < nD) nmoved += ent_side(e) != isd[it] ? 1 : 0;
+      if (itag[it] != kTagPartner) {
+        irx[it] = A.rp[ix[it]];
+        idd[it] = (int32_t)(A.rp[ix[it] + 1] - irx[it]);
+        ip[it] = atomic_add(itag[it] == kTagEmit ? &A.out_cur[ix[it]] : &A.inbox_cur[ix[it]], 1);
       }
     }
+    const bool own = ix[it] >= 0 && itag[it] <= kTagPartner;
+    nu += popc64(ballot(own && isd[it] == 0));
+    nv += popc64(ballot(own && isd[it] == 1));
+  }
+  int32_t baseu = 0, basev = 0;
+  if (l == 0) {
+    if (nu) baseu = atomic_add(&A.out_cur[u], nu);
+    if (nv) basev = atomic_add(&A.out_cur[v], nv);
+  }
+  baseu = wave_bcast(baseu, 0);
+  basev = wave_bcast(basev, 0);
+  int32_t cfwd = 0, cemit = 0;
+  bool fwd[kWriteIt];
+#pragma unroll
+  for (int it = 0; it < kWriteIt; ++it) {
+    const bool own = ix[it] >= 0 && itag[it] <= kTagPartner;
+    const uint64_t mu = ballot(own && isd[it] == 0);
+    const uint64_t mv = ballot(own && isd[it] == 1);
+    const int32_t owner = isd[it] ? v : u;
+    if (own) {
+      const int32_t p = isd[it] ? basev + rank_below(mv) : baseu + rank_below(mu);
+      const int32_t dd = isd[it] ? dv : du;
+      if (p < dd) A.col_out[(isd[it] ? bv : bu) + p] = ix[it]; else raise_error(A, kErrOut, k, -2 - owner);
+    }
+    baseu += popc64(mu);
+    basev += popc64(mv);
+    fwd[it] = false;
+    if (ix[it] >= 0 && itag[it] != kTagPartner) {
+      if (ip[it] >= idd[it]) {
+        raise_error(A, itag[it] == kTagEmit ? kErrOut : kErrInbox, k, ix[it]);
+      } else if (itag[it] == kTagEmit) {
+        A.col_out[irx[it] + ip[it]] = owner;
+        cemit += 1;
+      } else {
+        if (itag[it] & kTagGiant) giant_insert(A.gs, A.gs.giant_id[ix[it]], owner);
+        else store_agent(&A.inbox[irx[it] + ip[it]], owner);
+        fwd[it] = true;
+        cfwd += 1;
+      }
+    }
+  }
+  cfwd = wave_sum(cfwd);
+  nfwd += cfwd;
+  nemit += wave_sum(cemit);
+  if (cfwd) {
+    // the inbox entries and bitmap bits are written before the counters
+    // they unlock
+    publish_wait();
+    int32_t old[kWriteIt];
+#pragma unroll
+    for (int it = 0; it < kWriteIt; ++it) old[it] = fwd[it] ? atomic_add(&A.dep[tag_trade(itag[it])], -1) : 2;
+#pragma unroll
+    for (int it = 0; it < kWriteIt; ++it) {
+      if (o0 + it * kWave >= s) break;   // uniform across the wavefront
+      const int32_t t = fwd[it] ? tag_trade(itag[it]) : -1;
+      if (fwd[it] && old[it] <= 0) raise_error(A, kErrDep, t, -1 - old[it]);
+      wave_release_ready(A, W, S, fwd[it] && old[it] == 1, t, k);
+    }
+  }
   }
   S.n_small += 1;
   S.work += (unsigned long long)s;
@@ -1029,7 +1087,7 @@ __device__ __forceinline__ void small_trade(const TradeArgs& A, int32_t k, int32
   S.emit += (unsigned long long)nemit;
 }
 
-__device__ void wave_flush(const TradeArgs& A, WaveState& S) {
+__device__ __forceinline__ void wave_flush(const TradeArgs& A, WaveState& S) {
   if (lane_id() == 0) {
     if (S.ndone) atomic_add(&A.ctrl[cw(kCwDone)], S.ndone);
     if (S.n_small) atomicAdd(&A.stats[kStatSmall], S.n_small);
@@ -1156,16 +1214,19 @@ __device__ __forceinline__ bool gather_list(const TradeArgs& A, int32_t k, int64
   __syncthreads();
   // one LDS counter update per wavefront and chunk (trip count is uniform
   // across a wavefront: the bound is rounded up to whole wavefronts)
-  // kGatherBatch strides of loads are issued before the first is used.
+  // kGatherBatch strides of loads are issued before the first is used. The
+  // row's inbox slot e is read with row entry e and kept if e < ni; arrivals
+  // fill out[] from the back (the j-th at d-1-j).
   const int32_t dr = (d + kWave - 1) / kWave * kWave;
   const int32_t nt = blockDim.x;
   for (int32_t e0 = tid; e0 < dr; e0 += kGatherBatch * nt) {
-    int32_t t[kGatherBatch], x[kGatherBatch];
+    int32_t t[kGatherBatch], x[kGatherBatch], y[kGatherBatch];
 #pragma unroll
     for (int r = 0; r < kGatherBatch; ++r) {
       const int32_t e = e0 + r * nt;
       t[r] = e < d ? A.col_t[b + e] : 0;
       x[r] = e < d ? A.col[b + e] : 0;
+      y[r] = e < d ? load_agent(&A.inbox[b + e]) : 0;
     }
 #pragma unroll
     for (int r = 0; r < kGatherBatch; ++r) {
@@ -1177,6 +1238,7 @@ __device__ __forceinline__ bool gather_list(const TradeArgs& A, int32_t k, int64
       if (lane_id() == 0 && m) base = atomicAdd(&B.cnt[0], popc64(m));
       base = wave_bcast(base, 0);
       if (fresh) out[base + rank_below(m)] = make_entry(x[r], side, tag_of(t[r], k));
+      if (e < ni && ni <= d) out[d - 1 - e] = make_entry(y[r], side, kTagEmit);
     }
   }
   __syncthreads();
@@ -1186,20 +1248,6 @@ __device__ __forceinline__ bool gather_list(const TradeArgs& A, int32_t k, int64
     if (tid == 0) raise_error(A, kErrGather, k, 1000000 + nf + ni - d);
     return false;
   }
-  for (int32_t j0 = tid; j0 < ni; j0 += kGatherBatch * nt) {
-    int32_t x[kGatherBatch];
-#pragma unroll
-    for (int r = 0; r < kGatherBatch; ++r) {
-      const int32_t j = j0 + r * nt;
-      x[r] = j < ni ? load_agent(&A.inbox[b + j]) : 0;
-    }
-#pragma unroll
-    for (int r = 0; r < kGatherBatch; ++r) {
-      const int32_t j = j0 + r * nt;
-      if (j < ni) out[nf + j] = make_entry(x[r], side, kTagEmit);
-    }
-  }
-  __syncthreads();
   return true;
 }
 
@@ -1215,14 +1263,19 @@ __device__ __forceinline__ bool gather_both(const TradeArgs& A, int32_t k, int64
   __syncthreads();
   const int32_t s = du + dv;
   const int32_t sr = (s + kWave - 1) / kWave * kWave;
+  // A row's inbox has as many slots as the row; slot e is read with row
+  // entry e (one round trip for both) and kept if e is below the row's
+  // arrival count. Arrivals fill out[] from the back: u's j-th at s-1-j, v's
+  // at s-1-niu-j; row entries of later nodes fill it from the front.
   for (int32_t e0 = tid; e0 < sr; e0 += kGatherBatch * nt) {
-    int32_t t[kGatherBatch], x[kGatherBatch];
+    int32_t t[kGatherBatch], x[kGatherBatch], y[kGatherBatch];
 #pragma unroll
     for (int r = 0; r < kGatherBatch; ++r) {
       const int32_t e = e0 + r * nt;
       const int64_t at = e < du ? bu + e : bv + (e - du);
       t[r] = e < s ? A.col_t[at] : 0;
       x[r] = e < s ? A.col[at] : 0;
+      y[r] = e < s ? load_agent(&A.inbox[at]) : 0;
     }
 #pragma unroll
     for (int r = 0; r < kGatherBatch; ++r) {
@@ -1239,6 +1292,11 @@ __device__ __forceinline__ bool gather_both(const TradeArgs& A, int32_t k, int64
       }
       base = wave_bcast(base, 0);
       if (fresh) out[base + rank_below(m)] = make_entry(x[r], side, tag_of(t[r], k));
+      if (e < du) {
+        if (e < niu && niu <= du) out[s - 1 - e] = make_entry(y[r], 0, kTagEmit);
+      } else if (e < s) {
+        if (e - du < niv && niv <= dv) out[s - 1 - niu - (e - du)] = make_entry(y[r], 1, kTagEmit);
+      }
     }
   }
   __syncthreads();
@@ -1249,21 +1307,6 @@ __device__ __forceinline__ bool gather_both(const TradeArgs& A, int32_t k, int64
     if (tid == 0) raise_error(A, kErrGather, k, 1000000 + nf + niu + niv - s);
     return false;
   }
-  const int32_t ni = niu + niv;
-  for (int32_t j0 = tid; j0 < ni; j0 += kGatherBatch * nt) {
-    int32_t x[kGatherBatch];
-#pragma unroll
-    for (int r = 0; r < kGatherBatch; ++r) {
-      const int32_t j = j0 + r * nt;
-      x[r] = j < ni ? load_agent(&A.inbox[j < niu ? bu + j : bv + (j - niu)]) : 0;
-    }
-#pragma unroll
-    for (int r = 0; r < kGatherBatch; ++r) {
-      const int32_t j = j0 + r * nt;
-      if (j < ni) out[nf + j] = make_entry(x[r], j < niu ? 0 : 1, kTagEmit);
-    }
-  }
-  __syncthreads();
   return true;
 }
 
@@ -1744,14 +1787,41 @@ __device__ __forceinline__ bool giant_fused(const TradeArgs& A, int32_t k, int32
   for (int i = 0; i < kSbRegs; ++i) cv[i] = inreg && j0s + i < j1s ? load_agent(&sc[j0s + i]) : 0;
   if (tid == 0) { B.cnt[0] = 0; B.cnt[1] = 0; B.cnt[2] = 0; }
   __syncthreads();
-  // O entries: shared neighbour (bit set in the giant's set) or partner
-  for (int32_t j = tid; j < d_o; j += nt) {
-    const int32_t x = ent_node(O[j]);
-    const bool common = (load_agent_u64(&bm[x >> 6]) >> (x & 63)) & 1ull;
-    const bool partner = x == h;
-    kc[j] = common ? 2 : (partner ? 1 : 0);
-    if (common) atomicAdd(&B.cnt[0], 1);
-    if (partner) B.cnt[1] = 1;
+  // O entries, from the words of their superblock up to their own (8 lanes,
+  // 8 words each; these loads overlap those of the counts above): the
+  // giant's members below them (posO, the prefix of the superblock is added
+  // below) and whether they are shared neighbours (their bit set in the
+  // giant's set) or the partner
+  for (int32_t j0 = w * 8; j0 < d_o; j0 += (nt >> 6) * 8) {
+    const int32_t j = j0 + (l >> 3);
+    int32_t c = 0, mem = 0;
+    if (j < d_o) {
+      const int32_t x = ent_node(O[j]);
+      const int64_t wb = (int64_t)(x >> 12) * 64 + (l & 7) * 8;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int64_t wi = wb + i;
+        const int32_t below = x - (int32_t)(wi * 64);   // bits of word wi below x
+        if (below >= 0) {
+          const uint64_t word = load_agent_u64(&bm[wi]);
+          c += below >= 64 ? popc64(word) : popc64(word & ((1ull << below) - 1ull));
+          if (below < 64) mem = (int32_t)((word >> below) & 1ull);
+        }
+      }
+    }
+    c += __shfl_xor(c, 1, kWave);
+    c += __shfl_xor(c, 2, kWave);
+    c += __shfl_xor(c, 4, kWave);
+    mem |= __shfl_xor(mem, 1, kWave);
+    mem |= __shfl_xor(mem, 2, kWave);
+    mem |= __shfl_xor(mem, 4, kWave);
+    if (j < d_o && (l & 7) == 0) {
+      const bool partner = ent_node(O[j]) == h;
+      posO[j] = c;
+      kc[j] = mem ? 2 : (partner ? 1 : 0);
+      if (mem) atomicAdd(&B.cnt[0], 1);
+      if (partner) B.cnt[1] = 1;
+    }
   }
   __syncthreads();
   int32_t nK1 = 0;
@@ -1809,30 +1879,11 @@ __device__ __forceinline__ bool giant_fused(const TradeArgs& A, int32_t k, int32
   }
   __syncthreads();
   // ranks of O's nodes among the giant's members: the prefix of their
-  // superblock plus the members below them in it (8 lanes, 8 words each)
-  for (int32_t j0 = w * 8; j0 < d_o; j0 += (nt >> 6) * 8) {
-    const int32_t j = j0 + (l >> 3);
-    int32_t c = 0;
-    int32_t x = 0;
-    if (j < d_o) {
-      x = ent_node(O[j]);
-      const int64_t wb = (int64_t)(x >> 12) * 64 + (l & 7) * 8;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int64_t wi = wb + i;
-        const int32_t below = x - (int32_t)(wi * 64);   // bits of word wi below x
-        if (below > 0) {
-          const uint64_t word = load_agent_u64(&bm[wi]);
-          c += below >= 64 ? popc64(word) : popc64(word & ((1ull << below) - 1ull));
-        }
-      }
-    }
-    c += __shfl_xor(c, 1, kWave);
-    c += __shfl_xor(c, 2, kWave);
-    c += __shfl_xor(c, 4, kWave);
-    if (j < d_o && (l & 7) == 0)
-      posO[j] = j + (pre_lds ? preL[x >> 12] : load_agent(&pre[x >> 12])) + c +
-                ((kc[j] == 2 && sh < so) ? 1 : 0);
+  // superblock plus the members below them in it (counted above)
+  for (int32_t j = tid; j < d_o; j += nt) {
+    const int32_t x = ent_node(O[j]);
+    posO[j] = j + (pre_lds ? preL[x >> 12] : load_agent(&pre[x >> 12])) + posO[j] +
+              ((kc[j] == 2 && sh < so) ? 1 : 0);
   }
   __syncthreads();   // posO is read by other wavefronts below
   const int32_t n_common = B.cnt[0];
