@@ -171,7 +171,9 @@ cb_status graph_download_state(cb_graph* g, int32_t which, void* host, int64_t c
                                    wavefront (0..512); larger ones on a whole
                                    workgroup. Default 512. */
 #define CB_OPT_BIG_WORKERS   2  /* workgroups reserved for large trades (>= 1) */
-#define CB_OPT_GRID_BLOCKS   3  /* workgroups of the trade kernel (0 = auto) */
+#define CB_OPT_GRID_BLOCKS   3  /* workgroups of the trade kernel (0 = auto: one per
+                                   CU; for a graph with giant nodes, the
+                                   workgroup workers plus a quarter of the CUs) */
 #define CB_OPT_WATCHDOG_MS   4  /* idle time after which the trade kernel gives up */
 #define CB_OPT_TIMING        5  /* 1: time every kernel with HIP events */
 #define CB_OPT_LOCAL_STACK   6  /* ready trades a wavefront keeps for itself (0..16) */
@@ -298,7 +300,8 @@ cb_status batch_info(const cb_graph* g, int32_t chain, int64_t* n, int64_t* nnz,
 cb_status batch_download(cb_graph* g, int32_t chain, int32_t* col);
 
 /* ---- autotuner --------------------------------------------------------------
- * Chooses the workgroup pool (CB_OPT_CU_POOL), the idle wavefronts' back-off
+ * Chooses the trade kernel's workgroups (CB_OPT_GRID_BLOCKS), the workgroup
+ * pool (CB_OPT_CU_POOL), the idle wavefronts' back-off
  * (CB_OPT_IDLE_BACKOFF), their local
  * stack of ready trades (CB_OPT_LOCAL_STACK), the wavefront/workgroup size
  * threshold (CB_OPT_SMALL_MAX), the size from which write phases are shared
@@ -319,6 +322,7 @@ typedef struct {
     int32_t local_stack;          /* CB_OPT_LOCAL_STACK */
     int32_t idle_backoff;         /* CB_OPT_IDLE_BACKOFF */
     int32_t cu_pool;              /* CB_OPT_CU_POOL */
+    int32_t grid_blocks;          /* CB_OPT_GRID_BLOCKS */
     double ms_per_round;          /* of the chosen options */
     double default_ms_per_round;  /* of the options the tuner started from */
     int32_t evaluated;            /* timed candidates (0 when taken from the cache) */

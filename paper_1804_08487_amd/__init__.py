@@ -67,7 +67,7 @@ class TuneResult(ctypes.Structure):
     _fields_ = [("small_max", ctypes.c_int32), ("help_min", ctypes.c_int32),
                 ("help_chunk", ctypes.c_int32), ("big_workers", ctypes.c_int32),
                 ("local_stack", ctypes.c_int32), ("idle_backoff", ctypes.c_int32),
-                ("cu_pool", ctypes.c_int32),
+                ("cu_pool", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
                 ("ms_per_round", ctypes.c_double), ("default_ms_per_round", ctypes.c_double),
                 ("evaluated", ctypes.c_int32), ("cached", ctypes.c_int32)]
 

@@ -444,8 +444,17 @@ int32_t effective_nbig(const cb_graph* g) {
   return std::min(v, g->nbig_alloc);
 }
 
+// Workgroups of the trade kernel. Automatic: one per CU; with giant nodes,
+// the workgroup workers plus a quarter of the CUs. A chain of giant trades is
+// bound by the round trips of its scattered accesses, and wavefront workers
+// on every CU add enough traffic to lengthen them: at n = 2^24 the trade
+// kernel took 733 ms on 256 workgroups, 615 ms on 128 (64 + 64) and 636 ms
+// on 112, while a batch of 512 small chains, which needs the wavefront
+// workers' throughput, took 80 ms on 256 and 113 ms on 128.
 int32_t trade_grid(const cb_graph* g) {
-  int32_t blocks = g->grid_blocks > 0 ? g->grid_blocks : g->cu_count * g->occupancy_blocks;
+  int32_t blocks = g->grid_blocks;
+  if (blocks <= 0)
+    blocks = g->ngiant > 0 ? effective_nbig(g) + std::max(1, g->cu_count / 4) : g->cu_count * g->occupancy_blocks;
   return std::max(blocks, effective_nbig(g) + 1);
 }
 
@@ -1017,6 +1026,7 @@ void apply_tuned(cb_graph* g, const cb_tune_result& r) {
   g->stack_cap = r.local_stack;
   g->idle_backoff = r.idle_backoff;
   g->cu_pool = r.cu_pool;
+  g->grid_blocks = r.grid_blocks;
   g->opt_version++;
 }
 
@@ -1029,6 +1039,7 @@ cb_tune_result current_options(const cb_graph* g) {
   r.local_stack = g->stack_cap;
   r.idle_backoff = g->idle_backoff;
   r.cu_pool = g->cu_pool;
+  r.grid_blocks = g->grid_blocks;
   return r;
 }
 
@@ -1437,15 +1448,19 @@ cb_status graph_autotune(cb_graph* g, uint32_t trial_rounds, int32_t use_cache, 
     best.ms_per_round = best.default_ms_per_round = ms;
     best.evaluated = 2;
   }
-  // coordinate descent over the idle wavefronts' back-off, their local stack
-  // of ready trades, the wavefront/workgroup threshold, the size from which
-  // write phases are shared, their chunk size and the workgroup workers
+  // coordinate descent over the kernel's workgroups (a grid below the
+  // workgroup workers plus one is raised to that), the workgroup pool, the
+  // idle wavefronts' back-off, their local stack of ready trades, the
+  // wavefront/workgroup threshold, the size from which write phases are
+  // shared, their chunk size and the workgroup workers
   struct Param {
     int32_t cb_tune_result::*field;
     int32_t values[6];
     int count;
   };
+  const int32_t cu = g->cu_count;
   const Param params[] = {
+      {&cb_tune_result::grid_blocks, {0, cu, cu * 3 / 4, cu * 5 / 8, cu / 2}, 5},
       {&cb_tune_result::cu_pool, {0, 1}, 2},
       {&cb_tune_result::idle_backoff, {2, 8, 32, 128}, 4},
       {&cb_tune_result::local_stack, {0, 1, 2, 4, 8, 16}, 6},
