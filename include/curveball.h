@@ -172,8 +172,9 @@ cb_status graph_download_state(cb_graph* g, int32_t which, void* host, int64_t c
                                    workgroup. Default 512. */
 #define CB_OPT_BIG_WORKERS   2  /* workgroups reserved for large trades (>= 1) */
 #define CB_OPT_GRID_BLOCKS   3  /* workgroups of the trade kernel (0 = auto: one per
-                                   CU; for a graph with giant nodes, the
-                                   workgroup workers plus a quarter of the CUs) */
+                                   CU; for a graph with giant nodes and average
+                                   degree at least 32, the workgroup workers
+                                   plus a quarter of the CUs) */
 #define CB_OPT_WATCHDOG_MS   4  /* idle time after which the trade kernel gives up */
 #define CB_OPT_TIMING        5  /* 1: time every kernel with HIP events */
 #define CB_OPT_LOCAL_STACK   6  /* ready trades a wavefront keeps for itself (0..16) */

@@ -444,17 +444,22 @@ int32_t effective_nbig(const cb_graph* g) {
   return std::min(v, g->nbig_alloc);
 }
 
-// Workgroups of the trade kernel. Automatic: one per CU; with giant nodes,
-// the workgroup workers plus a quarter of the CUs. A chain of giant trades is
-// bound by the round trips of its scattered accesses, and wavefront workers
-// on every CU add enough traffic to lengthen them: at n = 2^24 the trade
-// kernel took 733 ms on 256 workgroups, 615 ms on 128 (64 + 64) and 636 ms
-// on 112, while a batch of 512 small chains, which needs the wavefront
-// workers' throughput, took 80 ms on 256 and 113 ms on 128.
+// Workgroups of the trade kernel. Automatic: one per CU; for a dense graph
+// (average degree at least 32) with giant nodes, the workgroup workers plus a
+// quarter of the CUs. There a chain of giant trades is bound by the round
+// trips of its scattered accesses, and wavefront workers on every CU add
+// enough traffic to lengthen them: at n = 2^24, average degree 100, the trade
+// kernel took 733 ms on 256 workgroups, 615 ms on 128 (64 + 64) and 636 ms on
+// 112. Sparse graphs are mostly wavefront trades and need every worker (a
+// sparse 2^24-node graph with a few giants: 129 ms per round on 256
+// workgroups, 184 ms on 128), as does a batch of 512 small chains (80 ms on
+// 256, 113 ms on 128).
 int32_t trade_grid(const cb_graph* g) {
   int32_t blocks = g->grid_blocks;
-  if (blocks <= 0)
-    blocks = g->ngiant > 0 ? effective_nbig(g) + std::max(1, g->cu_count / 4) : g->cu_count * g->occupancy_blocks;
+  if (blocks <= 0) {
+    const bool dense_giants = g->ngiant > 0 && g->nnz >= 32 * g->n;
+    blocks = dense_giants ? effective_nbig(g) + std::max(1, g->cu_count / 4) : g->cu_count * g->occupancy_blocks;
+  }
   return std::max(blocks, effective_nbig(g) + 1);
 }
 
