@@ -646,6 +646,8 @@ cb_status enqueue_round(cb_graph* g, hipStream_t st, int last_step, bool advance
       hipLaunchKernelGGL(k_segsort_mid, dim3(grid_for(g->n_mid, 1, 65536)), dim3(256), 0, st,
                          rm, g->n_mid, g->rp, g->col_out, g->col, g->keybits_node, N, g->ctrl);
     if (g->n_big) {
+      hipLaunchKernelGGL(k_segsort_wide, dim3(grid_for(g->n_big, 1, 4096)), dim3(kSegWideThreads), 0, st,
+                         rb, g->n_big, g->rp, g->col_out, g->col, g->keybits_node, g->ctrl);
       hipLaunchKernelGGL(k_segsort_big, dim3(grid_for(g->n_big, 1, 8192)), dim3(256), 0, st,
                          rb, g->n_big, g->rp, g->col_out, g->col, g->keybits_node, NextScan{}, g->ctrl);
       if (lookahead) {
@@ -1670,10 +1672,14 @@ extern "C" cb_status cbu_trades(cb_graph* g, uint64_t seed, uint64_t step0, uint
       if (g->n_mid)
         hipLaunchKernelGGL(k_segsort_mid, dim3(grid_for(g->n_mid, 1, 65536)), dim3(256), 0, st,
                            g->rows + g->n_small, g->n_mid, g->rp, g->col_out, g->col, g->keybits_node, none, g->ctrl);
-      if (g->n_big)
+      if (g->n_big) {
+        hipLaunchKernelGGL(k_segsort_wide, dim3(grid_for(g->n_big, 1, 4096)), dim3(kSegWideThreads), 0, st,
+                           g->rows + g->n_small + g->n_mid, g->n_big, g->rp, g->col_out, g->col, g->keybits_node,
+                           g->ctrl);
         hipLaunchKernelGGL(k_segsort_big, dim3(grid_for(g->n_big, 1, 8192)), dim3(256), 0, st,
                            g->rows + g->n_small + g->n_mid, g->n_big, g->rp, g->col_out, g->col, g->keybits_node,
                            none, g->ctrl);
+      }
     }
     ok = HIP_OK(hipGetLastError(), "kernel launch");
   }

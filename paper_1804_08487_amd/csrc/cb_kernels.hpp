@@ -96,6 +96,8 @@ constexpr int kMatchCap = 2048;       // bucket size sorted in LDS by k_match_so
 constexpr int kMatchBlock = 256;
 constexpr int kScanChunk = 2048;      // CSR entries per workgroup in k_depscan/k_validate
 constexpr int kSegMidMax = 4096;      // rows sorted in LDS by one workgroup
+constexpr int kSegWideMax = 32768;    // bigger rows up to this are sorted in LDS by one wide workgroup
+constexpr int kSegWideThreads = 1024;
 constexpr int kSegSmallMax = 64;      // rows sorted in registers by one wavefront
 
 // Trade information of a node as stored per CSR entry (col_t) and per node
@@ -254,6 +256,8 @@ __global__ void k_segsort_mid(const int32_t* rows, int64_t nrows, const int64_t*
                               const int32_t* ctrl);
 __global__ void k_segsort_big(const int32_t* rows, int64_t nrows, const int64_t* rp,
                               int32_t* src, int32_t* dst, int keybits, NextScan N, const int32_t* ctrl);
+__global__ void k_segsort_wide(const int32_t* rows, int64_t nrows, const int64_t* rp, const int32_t* src,
+                               int32_t* dst, int keybits, const int32_t* ctrl);
 __global__ void k_big_offsets(const int32_t* rows, int64_t nrows, const int64_t* rp, int64_t* boff);
 __global__ void k_scan_big_rows(const int32_t* rows, int64_t nrows, const int64_t* boff, const int64_t* rp,
                                 const int32_t* col, NextScan N, const int32_t* ctrl);

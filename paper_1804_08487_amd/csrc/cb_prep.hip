@@ -535,6 +535,89 @@ k_segsort_mid(const int32_t* rows, int64_t nrows, const int64_t* rp, const int32
   }
 }
 
+// Rows of kSegMidMax < d <= kSegWideMax entries (from the list of big rows;
+// larger ones are left to k_segsort_big), one per workgroup of
+// kSegWideThreads, sorted in LDS as k_segsort_mid does it: ids bucketed by
+// their top bits (about 16 per bucket), each then placed by its rank within
+// its bucket; a bucket of more than kSegBucketMax ids (ids bunched together)
+// sends the row to the bitonic network. The row's scan for the next round is
+// done by k_scan_big_rows.
+__global__ void __launch_bounds__(kSegWideThreads)
+k_segsort_wide(const int32_t* rows, int64_t nrows, const int64_t* rp, const int32_t* src, int32_t* dst,
+               int keybits, const int32_t* ctrl) {
+  constexpr int kPer = kSegWideMax / kSegWideThreads;
+  __shared__ int32_t buf[kSegWideMax];
+  __shared__ int32_t cnt[kSegWideMax / 16];
+  __shared__ int32_t scan[kSegWideThreads / 64 + 1];
+  __shared__ int32_t full;
+  if (ctrl[cw(kCwErr)]) return;
+  const int tid = threadIdx.x;
+  for (int64_t r = blockIdx.x; r < nrows; r += gridDim.x) {
+    const int32_t x = rows[r];
+    const int64_t b = rp[x];
+    const int32_t d = (int32_t)(rp[x + 1] - b);
+    if (d > kSegWideMax) continue;   // uniform: left to k_segsort_big
+    int lb = 0;
+    while ((16 << lb) < d && lb < keybits) ++lb;
+    const int32_t nb = 1 << lb;   // at most kSegWideMax / 16
+    const int sh = keybits - lb;
+    auto bucket = [&](int32_t v) -> int32_t {
+      const uint32_t q = (uint32_t)v >> sh;
+      return q < (uint32_t)nb ? (int32_t)q : nb - 1;
+    };
+    int32_t v[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int32_t i = tid + q * kSegWideThreads;
+      v[q] = i < d ? src[b + i] : 0;
+    }
+    for (int32_t q = tid; q < nb; q += kSegWideThreads) cnt[q] = 0;
+    if (tid == 0) full = 0;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPer; ++q)
+      if (tid + q * kSegWideThreads < d) atomicAdd(&cnt[bucket(v[q])], 1);
+    __syncthreads();
+    // two buckets per thread (nb <= 2 * kSegWideThreads)
+    const int32_t c0 = 2 * tid < nb ? cnt[2 * tid] : 0;
+    const int32_t c1 = 2 * tid + 1 < nb ? cnt[2 * tid + 1] : 0;
+    if (c0 > kSegBucketMax || c1 > kSegBucketMax) full = 1;
+    int32_t tot;
+    const int32_t start = block_excl_scan(c0 + c1, scan, &tot);   // its barriers publish `full`
+    if (full) {
+#pragma unroll
+      for (int q = 0; q < kPer; ++q)
+        if (tid + q * kSegWideThreads < d) buf[tid + q * kSegWideThreads] = v[q];
+      __syncthreads();
+      block_bitonic_sort(buf, (uint32_t)d);
+      for (int32_t i = tid; i < d; i += kSegWideThreads) dst[b + i] = buf[i];
+      __syncthreads();
+      continue;
+    }
+    if (2 * tid < nb) cnt[2 * tid] = start;
+    if (2 * tid + 1 < nb) cnt[2 * tid + 1] = start + c0;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPer; ++q)
+      if (tid + q * kSegWideThreads < d) buf[atomicAdd(&cnt[bucket(v[q])], 1)] = v[q];
+    __syncthreads();
+    // cnt[q] is now the end of bucket q and the start of bucket q + 1
+    for (int32_t i = tid; i < d; i += kSegWideThreads) {
+      const int32_t e = buf[i];
+      const int32_t q = bucket(e);
+      const int32_t lo = q ? cnt[q - 1] : 0;
+      const int32_t hi = cnt[q];
+      int32_t rk = lo;
+      for (int32_t j = lo; j < hi; ++j) {
+        const int32_t y = buf[j];
+        rk += (y < e || (y == e && j < i)) ? 1 : 0;
+      }
+      dst[b + rk] = e;
+    }
+    __syncthreads();
+  }
+}
+
 __global__ void __launch_bounds__(256)
 k_segsort_big(const int32_t* rows, int64_t nrows, const int64_t* rp, int32_t* src,
               int32_t* dst, int keybits, NextScan N, const int32_t* ctrl) {
@@ -544,6 +627,7 @@ k_segsort_big(const int32_t* rows, int64_t nrows, const int64_t* rp, int32_t* sr
     const int32_t x = rows[r];
     const int64_t b = rp[x];
     const int64_t d = rp[x + 1] - b;
+    if (d <= kSegWideMax) continue;   // sorted in LDS by k_segsort_wide
     int32_t* out = block_radix_sort<int32_t>(src + b, dst + b, d, keybits, R);
     if (out != dst + b) {
       for (int64_t i = threadIdx.x; i < d; i += blockDim.x) dst[b + i] = out[i];

@@ -296,3 +296,30 @@ def test_batch_fusion_off_equals_on(orc):
         for r in range(6):
             x, _ = orc.global_trade(rp, x, seeds[c], r)
         assert np.array_equal(out[0][c], x) and np.array_equal(out[1][c], x), f"chain {c}"
+
+
+def _wide_rows_graph():
+    """Rows sorted in LDS by the wide rebuild kernel (4096 < d <= 32768):
+    node 0 has 9000 consecutive neighbour ids (a bucket too full: the
+    bitonic fallback), node 1 has 20000 spread-out ones; node 2 has 40000
+    (left to the radix sort), plus a sparse random graph."""
+    rng = np.random.default_rng(123)
+    n = 70000
+    edges = {(0, i) for i in range(5, 9005)}
+    edges |= {(1, int(i)) for i in rng.choice(np.arange(5, n), 20000, replace=False)}
+    edges |= {(2, int(i)) for i in rng.choice(np.arange(5, n), 40000, replace=False)}
+    for _ in range(80000):
+        x, y = sorted(int(t) for t in rng.integers(3, n, 2))
+        if x != y:
+            edges.add((x, y))
+    return graphgen.edge_list_to_csr(n, sorted(edges))
+
+
+@pytest.mark.parametrize("tier", ["default", "no_giant", "all_global"])
+def test_wide_rows_rebuilt_in_lds(orc, tier):
+    _say(f"wide rows graph tier {tier}")
+    rp, col = _wide_rows_graph()
+    deg = np.diff(rp)
+    assert deg[0] == 9000 and deg[1] == 20000 and deg[2] == 40000
+    opts = {cb.OPT_GIANT_DEG: 0} if tier == "no_giant" else TIERS[tier]
+    _run_and_compare(orc, rp, col, seed=6, rounds=3, options=opts)
