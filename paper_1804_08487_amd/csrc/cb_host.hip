@@ -648,8 +648,8 @@ cb_status enqueue_round(cb_graph* g, hipStream_t st, int last_step, bool advance
     if (g->n_big) {
       hipLaunchKernelGGL(k_segsort_wide, dim3(grid_for(g->n_big, 1, 4096)), dim3(kSegWideThreads), 0, st,
                          rb, g->n_big, g->rp, g->col_out, g->col, g->keybits_node, g->ctrl);
-      hipLaunchKernelGGL(k_segsort_big, dim3(grid_for(g->n_big, 1, 8192)), dim3(256), 0, st,
-                         rb, g->n_big, g->rp, g->col_out, g->col, g->keybits_node, NextScan{}, g->ctrl);
+      hipLaunchKernelGGL(k_segsort_huge, dim3(grid_for(g->n_big, 1, 4096)), dim3(kSegWideThreads), 0, st,
+                         rb, g->n_big, g->rp, g->col_out, g->col, g->keybits_node, g->ctrl);
       if (lookahead) {
         hipLaunchKernelGGL(k_scan_big_rows, dim3((unsigned)std::max<int64_t>(1, (g->big_entries + kScanChunk - 1) / kScanChunk)),
                            dim3(256), 0, st, rb, g->n_big, g->big_off, g->rp, g->col, N, g->ctrl);
@@ -1676,9 +1676,9 @@ extern "C" cb_status cbu_trades(cb_graph* g, uint64_t seed, uint64_t step0, uint
         hipLaunchKernelGGL(k_segsort_wide, dim3(grid_for(g->n_big, 1, 4096)), dim3(kSegWideThreads), 0, st,
                            g->rows + g->n_small + g->n_mid, g->n_big, g->rp, g->col_out, g->col, g->keybits_node,
                            g->ctrl);
-        hipLaunchKernelGGL(k_segsort_big, dim3(grid_for(g->n_big, 1, 8192)), dim3(256), 0, st,
+        hipLaunchKernelGGL(k_segsort_huge, dim3(grid_for(g->n_big, 1, 4096)), dim3(kSegWideThreads), 0, st,
                            g->rows + g->n_small + g->n_mid, g->n_big, g->rp, g->col_out, g->col, g->keybits_node,
-                           none, g->ctrl);
+                           g->ctrl);
       }
     }
     ok = HIP_OK(hipGetLastError(), "kernel launch");

@@ -254,9 +254,9 @@ __global__ void k_segsort_small(const int32_t* rows, int64_t nrows, const int64_
 __global__ void k_segsort_mid(const int32_t* rows, int64_t nrows, const int64_t* rp,
                               const int32_t* src, int32_t* dst, int keybits, NextScan N,
                               const int32_t* ctrl);
-__global__ void k_segsort_big(const int32_t* rows, int64_t nrows, const int64_t* rp,
-                              int32_t* src, int32_t* dst, int keybits, NextScan N, const int32_t* ctrl);
 __global__ void k_segsort_wide(const int32_t* rows, int64_t nrows, const int64_t* rp, const int32_t* src,
+                               int32_t* dst, int keybits, const int32_t* ctrl);
+__global__ void k_segsort_huge(const int32_t* rows, int64_t nrows, const int64_t* rp, const int32_t* src,
                                int32_t* dst, int keybits, const int32_t* ctrl);
 __global__ void k_big_offsets(const int32_t* rows, int64_t nrows, const int64_t* rp, int64_t* boff);
 __global__ void k_scan_big_rows(const int32_t* rows, int64_t nrows, const int64_t* boff, const int64_t* rp,

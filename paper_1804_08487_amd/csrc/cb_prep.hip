@@ -536,7 +536,7 @@ k_segsort_mid(const int32_t* rows, int64_t nrows, const int64_t* rp, const int32
 }
 
 // Rows of kSegMidMax < d <= kSegWideMax entries (from the list of big rows;
-// larger ones are left to k_segsort_big), one per workgroup of
+// larger ones are left to k_segsort_huge), one per workgroup of
 // kSegWideThreads, sorted in LDS as k_segsort_mid does it: ids bucketed by
 // their top bits (about 16 per bucket), each then placed by its rank within
 // its bucket; a bucket of more than kSegBucketMax ids (ids bunched together)
@@ -556,7 +556,7 @@ k_segsort_wide(const int32_t* rows, int64_t nrows, const int64_t* rp, const int3
     const int32_t x = rows[r];
     const int64_t b = rp[x];
     const int32_t d = (int32_t)(rp[x + 1] - b);
-    if (d > kSegWideMax) continue;   // uniform: left to k_segsort_big
+    if (d > kSegWideMax) continue;   // uniform: left to k_segsort_huge
     int lb = 0;
     while ((16 << lb) < d && lb < keybits) ++lb;
     const int32_t nb = 1 << lb;   // at most kSegWideMax / 16
@@ -618,29 +618,142 @@ k_segsort_wide(const int32_t* rows, int64_t nrows, const int64_t* rp, const int3
   }
 }
 
-__global__ void __launch_bounds__(256)
-k_segsort_big(const int32_t* rows, int64_t nrows, const int64_t* rp, int32_t* src,
-              int32_t* dst, int keybits, NextScan N, const int32_t* ctrl) {
-  __shared__ RadixLds R;
+// Sort dst[0, d) in place (d <= kSegWideMax) on the whole workgroup of
+// kSegWideThreads, by the low `lo_bits` bits of its ids (the higher ones are
+// equal within the run): the bucket-and-rank sort of k_segsort_wide, or the
+// bitonic network when a bucket is too full.
+__device__ __forceinline__ void lds_sort_run(int32_t* dst, int32_t d, int lo_bits, int32_t* buf, int32_t* cnt,
+                                             int32_t* scan, int32_t* full) {
+  constexpr int kPer = kSegWideMax / kSegWideThreads;
+  const int tid = threadIdx.x;
+  int lb = 0;
+  while ((16 << lb) < d && lb < lo_bits) ++lb;
+  const int32_t nb = 1 << lb;
+  const int sh = lo_bits - lb;
+  auto bucket = [&](int32_t v) -> int32_t { return (int32_t)(((uint32_t)v >> sh) & (uint32_t)(nb - 1)); };
+  int32_t v[kPer];
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int32_t i = tid + q * kSegWideThreads;
+    v[q] = i < d ? dst[i] : 0;
+  }
+  for (int32_t q = tid; q < nb; q += kSegWideThreads) cnt[q] = 0;
+  if (tid == 0) *full = 0;
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kPer; ++q)
+    if (tid + q * kSegWideThreads < d) atomicAdd(&cnt[bucket(v[q])], 1);
+  __syncthreads();
+  const int32_t c0 = 2 * tid < nb ? cnt[2 * tid] : 0;
+  const int32_t c1 = 2 * tid + 1 < nb ? cnt[2 * tid + 1] : 0;
+  if (c0 > kSegBucketMax || c1 > kSegBucketMax) *full = 1;
+  int32_t tot;
+  const int32_t start = block_excl_scan(c0 + c1, scan, &tot);   // its barriers publish `full`
+  if (*full) {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q)
+      if (tid + q * kSegWideThreads < d) buf[tid + q * kSegWideThreads] = v[q];
+    __syncthreads();
+    block_bitonic_sort(buf, (uint32_t)d);
+    for (int32_t i = tid; i < d; i += kSegWideThreads) dst[i] = buf[i];
+    __syncthreads();
+    return;
+  }
+  if (2 * tid < nb) cnt[2 * tid] = start;
+  if (2 * tid + 1 < nb) cnt[2 * tid + 1] = start + c0;
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kPer; ++q)
+    if (tid + q * kSegWideThreads < d) buf[atomicAdd(&cnt[bucket(v[q])], 1)] = v[q];
+  __syncthreads();
+  for (int32_t i = tid; i < d; i += kSegWideThreads) {
+    const int32_t e = buf[i];
+    const int32_t q = bucket(e);
+    const int32_t lo = q ? cnt[q - 1] : 0;
+    const int32_t hi = cnt[q];
+    int32_t rk = lo;
+    for (int32_t j = lo; j < hi; ++j) {
+      const int32_t y = buf[j];
+      rk += (y < e || (y == e && j < i)) ? 1 : 0;
+    }
+    dst[rk] = e;
+  }
+  __syncthreads();
+}
+
+// Rows of more than kSegWideMax entries, one per workgroup of
+// kSegWideThreads: the row is split by the top bits of its ids into runs of
+// about kSegWideMax / 2 entries (a count pass and a scatter pass into dst,
+// with the runs' cursors in LDS), then each run is sorted in place by
+// lds_sort_run (a run above kSegWideMax, ids crowded into one range, by the
+// bitonic network in global memory).
+__global__ void __launch_bounds__(kSegWideThreads)
+k_segsort_huge(const int32_t* rows, int64_t nrows, const int64_t* rp, const int32_t* src, int32_t* dst,
+               int keybits, const int32_t* ctrl) {
+  constexpr int kPer = kSegWideMax / kSegWideThreads;
+  constexpr int32_t kRuns = kSegWideMax / 16;
+  __shared__ int32_t buf[kSegWideMax];
+  __shared__ int32_t cnt[kSegWideMax / 16];
+  __shared__ int32_t run_start[kRuns + 1];
+  __shared__ int32_t scan[kSegWideThreads / 64 + 1];
+  __shared__ int32_t full;
   if (ctrl[cw(kCwErr)]) return;
+  const int tid = threadIdx.x;
   for (int64_t r = blockIdx.x; r < nrows; r += gridDim.x) {
     const int32_t x = rows[r];
     const int64_t b = rp[x];
     const int64_t d = rp[x + 1] - b;
-    if (d <= kSegWideMax) continue;   // sorted in LDS by k_segsort_wide
-    int32_t* out = block_radix_sort<int32_t>(src + b, dst + b, d, keybits, R);
-    if (out != dst + b) {
-      for (int64_t i = threadIdx.x; i < d; i += blockDim.x) dst[b + i] = out[i];
+    if (d <= kSegWideMax) continue;   // uniform: sorted by k_segsort_wide
+    int lp = 0;
+    while ((d >> lp) > kSegWideMax / 2 && lp < keybits && (2 << lp) <= kRuns) ++lp;
+    const int32_t np = 1 << lp;
+    const int shp = keybits - lp;
+    auto part = [&](int32_t v) -> int32_t {
+      const uint32_t q = (uint32_t)v >> shp;
+      return q < (uint32_t)np ? (int32_t)q : np - 1;
+    };
+    for (int32_t q = tid; q < np; q += kSegWideThreads) cnt[q] = 0;
+    __syncthreads();
+    for (int64_t c0 = 0; c0 < d; c0 += kSegWideMax) {
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) {
+        const int64_t i = c0 + tid + q * kSegWideThreads;
+        if (i < d) atomicAdd(&cnt[part(src[b + i])], 1);
+      }
     }
-    if (N.tinfo) {
-      const RowScan rs = row_scan(N, x);
-      int32_t cnt = 0;
-      for (int64_t i = threadIdx.x; i < d; i += blockDim.x) cnt += scan_entry(N, rs, b + i, out[i]);
-      add_dep(N, rs, cnt);
+    __syncthreads();
+    const int32_t c0 = 2 * tid < np ? cnt[2 * tid] : 0;
+    const int32_t c1 = 2 * tid + 1 < np ? cnt[2 * tid + 1] : 0;
+    int32_t tot;
+    const int32_t start = block_excl_scan(c0 + c1, scan, &tot);
+    if (2 * tid < np) { cnt[2 * tid] = start; run_start[2 * tid] = start; }
+    if (2 * tid + 1 < np) { cnt[2 * tid + 1] = start + c0; run_start[2 * tid + 1] = start + c0; }
+    if (tid == 0) run_start[np] = (int32_t)d;
+    __syncthreads();
+    for (int64_t c = 0; c < d; c += kSegWideMax) {
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) {
+        const int64_t i = c + tid + q * kSegWideThreads;
+        if (i < d) {
+          const int32_t v = src[b + i];
+          dst[b + atomicAdd(&cnt[part(v)], 1)] = v;
+        }
+      }
+    }
+    __syncthreads();   // the runs in dst are complete and visible to the workgroup
+    for (int32_t p = 0; p < np; ++p) {
+      const int32_t lo = run_start[p], len = run_start[p + 1] - lo;
+      if (len <= 1) continue;
+      if (len <= kSegWideMax) {
+        lds_sort_run(dst + b + lo, len, shp, buf, cnt, scan, &full);
+      } else {
+        block_bitonic_sort(dst + b + lo, (uint32_t)len);
+      }
     }
     __syncthreads();
   }
 }
+
 
 // Rows of each rebuild size class, listed once at upload (degrees never
 // change): rows of 1..64 entries from rows[0], of 65..4096 from rows[base[1]],

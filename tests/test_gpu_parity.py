@@ -301,15 +301,19 @@ def test_batch_fusion_off_equals_on(orc):
 def _wide_rows_graph():
     """Rows sorted in LDS by the wide rebuild kernel (4096 < d <= 32768):
     node 0 has 9000 consecutive neighbour ids (a bucket too full: the
-    bitonic fallback), node 1 has 20000 spread-out ones; node 2 has 40000
-    (left to the radix sort), plus a sparse random graph."""
+    bitonic fallback), node 1 has 20000 spread-out ones. Rows split into
+    runs first (d > 32768): node 2 has 40000 spread-out ids, node 3 has
+    36000 consecutive ones (one crowded run: the bitonic network in global
+    memory: with 2^19 ids a run spans 2^17 of them). Plus a sparse random
+    graph."""
     rng = np.random.default_rng(123)
-    n = 70000
+    n = 300000
     edges = {(0, i) for i in range(5, 9005)}
     edges |= {(1, int(i)) for i in rng.choice(np.arange(5, n), 20000, replace=False)}
     edges |= {(2, int(i)) for i in rng.choice(np.arange(5, n), 40000, replace=False)}
+    edges |= {(3, i) for i in range(20000, 56000)}
     for _ in range(80000):
-        x, y = sorted(int(t) for t in rng.integers(3, n, 2))
+        x, y = sorted(int(t) for t in rng.integers(4, n, 2))
         if x != y:
             edges.add((x, y))
     return graphgen.edge_list_to_csr(n, sorted(edges))
@@ -320,6 +324,6 @@ def test_wide_rows_rebuilt_in_lds(orc, tier):
     _say(f"wide rows graph tier {tier}")
     rp, col = _wide_rows_graph()
     deg = np.diff(rp)
-    assert deg[0] == 9000 and deg[1] == 20000 and deg[2] == 40000
+    assert deg[0] == 9000 and deg[1] == 20000 and deg[2] == 40000 and deg[3] == 36000
     opts = {cb.OPT_GIANT_DEG: 0} if tier == "no_giant" else TIERS[tier]
     _run_and_compare(orc, rp, col, seed=6, rounds=3, options=opts)
