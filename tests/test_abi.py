@@ -68,3 +68,46 @@ def test_allocator_requires_both_callbacks():
     a = cb._Allocator()
     assert cb.lib().cb_set_allocator(ctypes.byref(a)) == cb.CB_EINVAL
     assert cb.lib().cb_set_allocator(None) == cb.CB_OK
+
+
+_CTYPES = {"int32_t": ctypes.c_int32, "int64_t": ctypes.c_int64, "double": ctypes.c_double,
+           "uint32_t": ctypes.c_uint32, "uint64_t": ctypes.c_uint64}
+
+
+def _header_struct(name):
+    """(field, C type) of `typedef struct { ... } name;` in the header, in order."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    m = re.search(r"typedef struct \{([^{}]*)\}\s*" + name + r"\s*;", text)
+    assert m, name
+    fields = []
+    for decl in m.group(1).split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        typ, names = decl.split(None, 1)
+        fields += [(n.strip(), typ) for n in names.split(",")]
+    return fields
+
+
+@pytest.mark.parametrize("cname,pystruct", [("cb_round_stats", cb.RoundStats),
+                                            ("cb_tune_result", cb.TuneResult),
+                                            ("cb_server_status", cb.ServerStatus)])
+def test_binding_structs_mirror_the_header(cname, pystruct):
+    """The ctypes mirrors list the header's fields in the same order with the
+    same C types, so their layouts (offsets, padding, size) agree."""
+    header = _header_struct(cname)
+    mirror = [(n, t) for n, t in pystruct._fields_]
+    assert [n for n, _ in header] == [n for n, _ in mirror]
+    for (n, ctype), (_, pytype) in zip(header, mirror):
+        assert _CTYPES[ctype] is pytype, n
+
+
+def test_binding_constants_match_the_header():
+    text = open(HEADER).read()
+    defines = dict((k, int(v)) for k, v in re.findall(r"#define\s+(CB_\w+)\s+(\d+)u?\b", text))
+    for name, value in defines.items():
+        short = name[3:]
+        if hasattr(cb, short):
+            assert getattr(cb, short) == value, name
+    opts = [k for k in defines if k.startswith("CB_OPT_")]
+    assert opts and all(hasattr(cb, k[3:]) for k in opts)
