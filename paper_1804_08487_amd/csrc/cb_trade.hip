@@ -1131,13 +1131,13 @@ __device__ __forceinline__ void small_worker(const TradeArgs& A, WaveLds& W, int
       // a ready trade left by a wavefront of this workgroup
     } else {
       if (l == 0) {
-        if (sources_left) {
+        // released trades before sources: a released trade may be on the
+        // round's critical path, a source has waited for nothing
+        k = queue_pop(A, A.qs, kQsScan, kCwQsHead0, kCwQsTail0, scan, kQsShards);
+        scan = (scan + kQsScan) % kQsShards;
+        if (k < 0 && sources_left) {
           k = source_pop(A);
           sources_left = k >= 0;
-        }
-        if (k < 0) {
-          k = queue_pop(A, A.qs, kQsScan, kCwQsHead0, kCwQsTail0, scan, kQsShards);
-          scan = (scan + kQsScan) % kQsShards;
         }
       }
       k = wave_bcast(k, 0);
