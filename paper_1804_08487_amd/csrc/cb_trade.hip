@@ -831,7 +831,8 @@ __device__ __forceinline__ bool try_help(const TradeArgs& A, int32_t b, WriteCou
 // ============================================================ small trades
 
 struct WaveState {
-  int32_t top;        // local stack depth (uniform)
+  int32_t top;        // ready trades kept locally (uniform)
+  int32_t head;       // ... the oldest of them, in a ring of kStackCap slots
   int32_t ndone;
   int32_t shard;      // home shard of the small-trade queues
   int32_t* pool;      // the workgroup's pool of ready trades (LDS; null: none)
@@ -896,7 +897,7 @@ __device__ __forceinline__ void wave_release_ready(const TradeArgs& A, WaveLds& 
   }
   const uint64_t spill = rest | ballot(big);
   if (spill) publish_wait();
-  if (keep && r < room) W.stack[S.top + r] = t;
+  if (keep && r < room) W.stack[(S.head + S.top + r) & (kStackCap - 1)] = t;
   else if (keep && ((rest >> lane_id()) & 1ull)) queue_push(A, A.qs, kCwQsTail0, S.shard, t);
   else if (big) queue_push(A, A.qb, kCwQbTail0, S.shard % kQbShards, t);
   wave_sync();
@@ -1125,8 +1126,11 @@ __device__ __forceinline__ void small_worker(const TradeArgs& A, WaveLds& W, int
   for (;;) {
     int32_t k = -1;
     if (S.top > 0) {
+      // oldest first: a trade that waits here may be on the critical path,
+      // and newer ones would keep it at the bottom of a stack
       S.top -= 1;
-      k = W.stack[S.top];
+      k = W.stack[S.head];
+      S.head = (S.head + 1) & (kStackCap - 1);
     } else if (S.pool && (k = pool_take(S.pool)) >= 0) {
       // a ready trade left by a wavefront of this workgroup
     } else {
