@@ -1112,6 +1112,7 @@ constexpr int32_t kFlushEvery = 32;   // trades between progress flushes
 // crowding the memory side on large graphs; small graphs, where ready trades
 // would wait for a sleeping poller, want a short back-off.
 constexpr int kQsScan = 1;
+constexpr int32_t kLocalRun = 4;   // local trades between two polls of a queue shard
 
 __device__ __forceinline__ void small_worker(const TradeArgs& A, WaveLds& W, int32_t* pool) {
   const int l = lane_id();
@@ -1123,15 +1124,31 @@ __device__ __forceinline__ void small_worker(const TradeArgs& A, WaveLds& W, int
   int32_t backoff = 1;
   bool sources_left = true;   // no trade becomes a source during the kernel
   int32_t scan = S.shard;
+  int32_t local_run = 0;   // trades taken from the ring and pool since the last queue poll
   for (;;) {
     int32_t k = -1;
-    if (S.top > 0) {
+    // every kLocalRun local trades, one poll of a queue shard first: trades
+    // released by workgroup trades (and overflow) wait there, and wavefronts
+    // that keep finding local work would leave them waiting
+    if (local_run >= kLocalRun) {
+      local_run = 0;
+      if (l == 0) {
+        k = queue_pop(A, A.qs, kQsScan, kCwQsHead0, kCwQsTail0, scan, kQsShards);
+        scan = (scan + kQsScan) % kQsShards;
+      }
+      k = wave_bcast(k, 0);
+    }
+    if (k >= 0) {
+      // taken from a queue shard
+    } else if (S.top > 0) {
       // oldest first: a trade that waits here may be on the critical path,
       // and newer ones would keep it at the bottom of a stack
       S.top -= 1;
       k = W.stack[S.head];
       S.head = (S.head + 1) & (kStackCap - 1);
+      ++local_run;
     } else if (S.pool && (k = pool_take(S.pool)) >= 0) {
+      ++local_run;
       // a ready trade left by a wavefront of this workgroup
     } else {
       if (l == 0) {
