@@ -105,6 +105,7 @@ struct cb_graph {
   uint64_t* mkey = nullptr;
   int32_t* dep = nullptr;
   int32_t* src_list = nullptr;
+  int32_t* src_b = nullptr;       // per bucket of relative position: source counts, starts, cursors
   int32_t* tsz = nullptr;
   HelpJob* jobs = nullptr;
   int64_t* trace = nullptr;     // allocated when tracing is first switched on
@@ -269,6 +270,7 @@ void plan_buffers(cb_graph* g, BufPlan& P, bool with_col = true) {
   P.add(&g->mkey, n);
   P.add(&g->dep, g->L);
   P.add(&g->src_list, g->L);
+  P.add(&g->src_b, 3 * kSrcBuckets);
   P.add(&g->tsz, g->L);
   P.add(&g->jobs, 2 * kMaxJobs);
   P.add(&g->qs, (int64_t)kQsShards * L1);
@@ -597,10 +599,15 @@ cb_status enqueue_round(cb_graph* g, hipStream_t st, int last_step, bool advance
       hipLaunchKernelGGL(k_depscan, dim3((unsigned)((g->nnz + kScanChunk - 1) / kScanChunk)), dim3(256),
                          0, st, n, g->nnz, g->rp, g->col, g->trade_of, g->tinfo, g->col_t, g->dep,
                          giant_sets(g), g->ctrl);
-    if (L > 0)
-      hipLaunchKernelGGL(k_sources, dim3(grid_for(L, 256, 8192)), dim3(256), 0, st, L, g->dep,
-                         g->perm, g->rp, effective_small_max(g), g->tsz, g->src_list, g->qb,
-                         g->ctrl, g->stats);
+    if (L > 0) {
+      for (int pass = 0; pass < 2; ++pass) {
+        hipLaunchKernelGGL(k_sources, dim3(grid_for(L, 256, 8192)), dim3(256), 0, st, L, g->dep,
+                           g->perm, g->rp, effective_small_max(g), g->tsz, g->src_list, g->qb,
+                           g->ctrl, g->stats, ch, g->src_b, pass);
+        if (pass == 0)
+          hipLaunchKernelGGL(k_sources_scan, dim3(1), dim3(kSrcBuckets), 0, st, g->src_b, g->ctrl);
+      }
+    }
   }
   if (timed) (void)hipEventRecord(evs.ev[2], st);
   if (last_step >= CB_STEP_TRADE && L > 0) {
@@ -761,6 +768,7 @@ bool init_device_state(cb_graph* g, bool validate, char* msg, size_t cap) {
   hipStream_t st = g->stream;
   const int64_t L1 = std::max<int64_t>(g->L, 1);
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, st, g->ctrl, (int64_t)kCtrlInts, 0);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, st, g->src_b, (int64_t)(3 * kSrcBuckets), 0);
   hipLaunchKernelGGL(k_fill_i32, dim3(grid_for((int64_t)(2 * kMaxJobs * sizeof(HelpJob) / 4), 256, 64)), dim3(256), 0, st,
                      reinterpret_cast<int32_t*>(g->jobs), (int64_t)(2 * kMaxJobs * sizeof(HelpJob) / 4), 0);
   hipLaunchKernelGGL(k_fill_i32, dim3(grid_for((int64_t)kQsShards * L1, 256, 8192)), dim3(256), 0, st, g->qs,
@@ -1658,8 +1666,13 @@ extern "C" cb_status cbu_trades(cb_graph* g, uint64_t seed, uint64_t step0, uint
       hipLaunchKernelGGL(k_copy_idle_edges, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, n, g->rp, g->col,
                          g->trade_of, g->col_out, g->out_cur, g->ctrl);
     }
-    hipLaunchKernelGGL(k_sources, dim3(grid_for(P, 256, 8192)), dim3(256), 0, st, P, g->dep, g->perm, g->rp,
-                       effective_small_max(g), g->tsz, g->src_list, g->qb, g->ctrl, g->stats);
+    for (int pass = 0; pass < 2; ++pass) {
+      hipLaunchKernelGGL(k_sources, dim3(grid_for(P, 256, 8192)), dim3(256), 0, st, P, g->dep, g->perm, g->rp,
+                         effective_small_max(g), g->tsz, g->src_list, g->qb, g->ctrl, g->stats, chains_of(g),
+                         g->src_b, pass);
+      if (pass == 0)
+        hipLaunchKernelGGL(k_sources_scan, dim3(1), dim3(kSrcBuckets), 0, st, g->src_b, g->ctrl);
+    }
     const TradeArgs A = trade_args(g, P);
     hipLaunchKernelGGL(k_trade, dim3(trade_grid(g)), dim3(kTradeBlock), 0, st, A);
     hipLaunchKernelGGL(k_check_rows, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, n, g->rp, g->out_cur,

@@ -95,6 +95,7 @@ struct HelpJob {
 constexpr int kMatchCap = 2048;       // bucket size sorted in LDS by k_match_sort
 constexpr int kMatchBlock = 256;
 constexpr int kScanChunk = 2048;      // CSR entries per workgroup in k_depscan/k_validate
+constexpr int kSrcBuckets = 256;     // buckets of relative position that order a round's sources
 constexpr int kSegMidMax = 4096;      // rows sorted in LDS by one workgroup
 constexpr int kSegWideMax = 32768;    // bigger rows up to this are sorted in LDS by one wide workgroup
 constexpr int kSegWideThreads = 1024;
@@ -232,7 +233,8 @@ __global__ void k_depscan(int64_t n, int64_t nnz, const int64_t* rp, const int32
                           int32_t* dep, GiantSets gs, const int32_t* ctrl);
 __global__ void k_sources(int32_t L, const int32_t* dep, const int32_t* perm, const int64_t* rp,
                           int32_t small_max, int32_t* tsz, int32_t* src_list, int32_t* qb,
-                          int32_t* ctrl, unsigned long long* stats);
+                          int32_t* ctrl, unsigned long long* stats, Chains ch, int32_t* sb, int pass);
+__global__ void k_sources_scan(int32_t* sb, int32_t* ctrl);
 __global__ void k_trade(TradeArgs A);
 __global__ void k_check_giants_empty(int64_t total_sb, const int32_t* sc, int32_t* ctrl);
 __global__ void k_check_rows(int64_t n, const int64_t* rp, const int32_t* out_cur,

@@ -337,10 +337,29 @@ __global__ void k_check_giants_empty(int64_t total_sb, const int32_t* sc, int32_
 // Per trade: its size deg u + deg v, and whether it is a source (no
 // dependency). Small sources go to the source list of the wavefront workers;
 // large ones straight into the workgroup queues.
+// Sources of a round, in two passes around k_sources_scan. Pass 0 records
+// every trade's size, queues the large sources, and counts the small ones
+// per bucket of the trades that follow them in their chain (most first: a
+// source with more later trades can head a longer dependency chain; the
+// largest chain's count is the scale, chains being laid out largest first).
+// Pass 1 places the small sources in the source list bucket by bucket, and
+// they are handed out in that order. A single chain keeps trade order.
+__device__ __forceinline__ int32_t source_bucket(const Chains& ch, int32_t k) {
+  const int32_t c = chain_of_trade(ch, k);
+  const int64_t lmax = ch.trade_base[1] - ch.trade_base[0];
+  int64_t rem = ch.trade_base[c + 1] - k;   // this trade and the ones after it
+  if (rem > lmax) rem = lmax;
+  const int64_t q = lmax > 0 ? ((lmax - rem) * kSrcBuckets) / lmax : 0;
+  return q < kSrcBuckets ? (int32_t)q : kSrcBuckets - 1;
+}
+
 __global__ void k_sources(int32_t L, const int32_t* dep, const int32_t* perm, const int64_t* rp,
                           int32_t small_max, int32_t* tsz, int32_t* src_list, int32_t* qb,
-                          int32_t* ctrl, unsigned long long* stats) {
+                          int32_t* ctrl, unsigned long long* stats, Chains ch, int32_t* sb, int pass) {
   if (ctrl[cw(kCwErr)]) return;
+  int32_t* cnt = sb;                    // per bucket: small sources (pass 0)
+  const int32_t* start = sb + kSrcBuckets;
+  int32_t* cur = sb + 2 * kSrcBuckets;  // per bucket: placed so far (pass 1)
   const int32_t stride = gridDim.x * blockDim.x;
   // trip count is uniform across a wavefront (ballots below)
   for (int32_t base = blockIdx.x * blockDim.x; base < L; base += stride) {
@@ -348,27 +367,63 @@ __global__ void k_sources(int32_t L, const int32_t* dep, const int32_t* perm, co
     int32_t s = 0;
     bool src = false;
     if (k < L) {
-      const int32_t u = perm[2 * k], v = perm[2 * k + 1];
-      s = (int32_t)((rp[u + 1] - rp[u]) + (rp[v + 1] - rp[v]));
-      tsz[k] = s;
+      if (pass == 0) {
+        const int32_t u = perm[2 * k], v = perm[2 * k + 1];
+        s = (int32_t)((rp[u + 1] - rp[u]) + (rp[v + 1] - rp[v]));
+        tsz[k] = s;
+      } else {
+        s = tsz[k];
+      }
       src = dep[k] == 0;
     }
     const bool big = src && s > small_max;
-    const uint64_t ms = ballot(src && !big);
-    const uint64_t mb = ballot(big);
-    if ((ms | mb) == 0) continue;
-    int32_t pos = 0, posb = 0;
-    const int shard = (int)((uint32_t)base / 64u) % kQbShards;
-    if (lane_id() == 0) {
-      if (ms) pos = atomic_add(&ctrl[cw(kCwSrcCount)], popc64(ms));
-      if (mb) posb = atomic_add(&ctrl[cw(kCwQbTail0 + shard)], popc64(mb));
-      atomicAdd(&stats[kStatSources], (unsigned long long)popc64(ms | mb));
+    const bool small = src && !big;
+    const int32_t b = small ? source_bucket(ch, k) : -1;
+    // one atomic per wavefront when its small sources share a bucket
+    const uint64_t ms = ballot(small);
+    const int32_t b0 = wave_bcast(b, ms ? __builtin_ctzll(ms) : 0);
+    const bool uniform = ballot(small && b != b0) == 0;
+    if (pass == 0) {
+      const uint64_t mb = ballot(big);
+      if ((ms | mb) == 0) continue;
+      int32_t posb = 0;
+      const int shard = (int)((uint32_t)base / 64u) % kQbShards;
+      if (lane_id() == 0) {
+        if (mb) posb = atomic_add(&ctrl[cw(kCwQbTail0 + shard)], popc64(mb));
+        atomicAdd(&stats[kStatSources], (unsigned long long)popc64(ms | mb));
+        if (ms && uniform) atomicAdd(&cnt[b0], popc64(ms));
+      }
+      if (small && !uniform) atomicAdd(&cnt[b], 1);
+      posb = wave_bcast(posb, 0);
+      if (big) qb[(int64_t)shard * L + posb + rank_below(mb)] = k;
+    } else {
+      if (ms == 0) continue;
+      if (uniform) {
+        int32_t pos = 0;
+        if (lane_id() == 0) pos = start[b0] + atomicAdd(&cur[b0], popc64(ms));
+        pos = wave_bcast(pos, 0);
+        if (small) src_list[pos + rank_below(ms)] = k;
+      } else if (small) {
+        src_list[start[b] + atomicAdd(&cur[b], 1)] = k;
+      }
     }
-    pos = wave_bcast(pos, 0);
-    posb = wave_bcast(posb, 0);
-    if (src && !big) src_list[pos + rank_below(ms)] = k;
-    if (big) qb[(int64_t)shard * L + posb + rank_below(mb)] = k;
   }
+}
+
+// Exclusive scan of the per-bucket source counts (one workgroup of
+// kSrcBuckets threads); the counts and cursors are left zero for the next
+// round, the total goes to the source count.
+__global__ void k_sources_scan(int32_t* sb, int32_t* ctrl) {
+  if (ctrl[cw(kCwErr)]) return;
+  __shared__ int32_t scan[kSrcBuckets / 64 + 1];
+  const int t = threadIdx.x;
+  const int32_t c = sb[t];
+  int32_t tot;
+  const int32_t at = block_excl_scan(c, scan, &tot);
+  sb[kSrcBuckets + t] = at;
+  sb[t] = 0;
+  sb[2 * kSrcBuckets + t] = 0;
+  if (t == 0) store_agent(&ctrl[cw(kCwSrcCount)], tot);
 }
 
 // Every row received exactly its degree: entries from its front plus the
