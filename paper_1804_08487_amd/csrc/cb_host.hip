@@ -107,6 +107,7 @@ struct cb_graph {
   int32_t* src_list = nullptr;
   int32_t* src_b = nullptr;       // per bucket of relative position: source counts, starts, cursors
   int32_t* tsz = nullptr;
+  uint4* ninfo = nullptr;       // per node: row offset, degree, trade information of the round
   HelpJob* jobs = nullptr;
   int64_t* trace = nullptr;     // allocated when tracing is first switched on
   int32_t* qs = nullptr;
@@ -272,6 +273,7 @@ void plan_buffers(cb_graph* g, BufPlan& P, bool with_col = true) {
   P.add(&g->src_list, g->L);
   P.add(&g->src_b, 3 * kSrcBuckets);
   P.add(&g->tsz, g->L);
+  P.add(&g->ninfo, n);
   P.add(&g->jobs, 2 * kMaxJobs);
   P.add(&g->qs, (int64_t)kQsShards * L1);
   P.add(&g->qb, (int64_t)kQbShards * L1);
@@ -488,6 +490,7 @@ TradeArgs trade_args(const cb_graph* g, int32_t L) {
   A.dep = g->dep;
   A.src_list = g->src_list;
   A.tsz = g->tsz;
+  A.ninfo = g->ninfo;
   A.jobs = g->jobs;
   A.trace = g->tracing ? g->trace : nullptr;
   A.qs = g->qs;
@@ -616,6 +619,7 @@ cb_status enqueue_round(cb_graph* g, hipStream_t st, int last_step, bool advance
       if (!HIP_OK(hipMemsetAsync(g->trace, 0xFF, (size_t)L * kTraceFields * sizeof(int64_t), st), "clear trace"))
         return fail(CB_EDEVICE, "%s", msg);
     }
+    hipLaunchKernelGGL(k_node_info, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, n, g->rp, g->tinfo, g->ninfo);
     const TradeArgs A = trade_args(g, L);
     hipLaunchKernelGGL(k_trade, dim3(trade_grid(g)), dim3(kTradeBlock), 0, st, A);
   }
@@ -1673,6 +1677,7 @@ extern "C" cb_status cbu_trades(cb_graph* g, uint64_t seed, uint64_t step0, uint
       if (pass == 0)
         hipLaunchKernelGGL(k_sources_scan, dim3(1), dim3(kSrcBuckets), 0, st, g->src_b, g->ctrl);
     }
+    hipLaunchKernelGGL(k_node_info, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, n, g->rp, g->tinfo, g->ninfo);
     const TradeArgs A = trade_args(g, P);
     hipLaunchKernelGGL(k_trade, dim3(trade_grid(g)), dim3(kTradeBlock), 0, st, A);
     hipLaunchKernelGGL(k_check_rows, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, n, g->rp, g->out_cur,

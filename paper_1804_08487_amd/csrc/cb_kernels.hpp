@@ -176,6 +176,7 @@ struct TradeArgs {
   int32_t* dep;
   const int32_t* src_list;
   const int32_t* tsz;       // deg u + deg v per trade, from k_sources
+  const uint4* ninfo;       // per node: row offset, degree, trade information (one load)
   int64_t* trace;           // optional: per trade ready, start, end tick and releasing trade
   HelpJob* jobs;            // kMaxJobs write jobs
   int32_t* qs;              // kQsShards ready queues of L slots (-1 = empty)
@@ -237,6 +238,7 @@ __global__ void k_sources(int32_t L, const int32_t* dep, const int32_t* perm, co
 __global__ void k_sources_scan(int32_t* sb, int32_t* ctrl);
 __global__ void k_trade(TradeArgs A);
 __global__ void k_check_giants_empty(int64_t total_sb, const int32_t* sc, int32_t* ctrl);
+__global__ void k_node_info(int64_t n, const int64_t* rp, const int32_t* tinfo, uint4* ninfo);
 __global__ void k_check_rows(int64_t n, const int64_t* rp, const int32_t* out_cur,
                              const int32_t* own_cur, int32_t* ctrl);
 // The next round's dependency scan, done by the rebuild as it writes each

@@ -426,6 +426,18 @@ __global__ void k_sources_scan(int32_t* sb, int32_t* ctrl) {
   if (t == 0) store_agent(&ctrl[cw(kCwSrcCount)], tot);
 }
 
+// Row offset, degree and trade information of every node side by side, so
+// that a write in the trade kernel finds all three with one 16-byte load
+// (offsets fit 32 bits: fewer than 2^31 entries). Rebuilt before every trade
+// kernel, after the round's trade information is final.
+__global__ void k_node_info(int64_t n, const int64_t* rp, const int32_t* tinfo, uint4* ninfo) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const int64_t b = rp[i];
+    ninfo[i] = make_uint4((uint32_t)b, (uint32_t)(rp[i + 1] - b), (uint32_t)tinfo[i], 0u);
+  }
+}
+
 // Every row received exactly its degree: entries from its front plus the
 // own-row entries a workgroup trade wrote from its back.
 __global__ void k_check_rows(int64_t n, const int64_t* rp, const int32_t* out_cur,

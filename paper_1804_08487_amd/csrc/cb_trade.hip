@@ -426,8 +426,9 @@ struct Watchdog {
 __device__ __forceinline__ void route_edge(const TradeArgs& A, int32_t owner, int32_t x,
                                            uint32_t tag, int32_t k) {
   if (tag == kTagPartner) return;  // own row only (handled by the caller)
-  const int64_t rx = A.rp[x];
-  const int32_t dx = (int32_t)(A.rp[x + 1] - rx);
+  const uint4 ni = A.ninfo[x];
+  const int64_t rx = ni.x;
+  const int32_t dx = (int32_t)ni.y;
   if (tag == kTagEmit) {
     const int32_t p = atomic_add(&A.out_cur[x], 1);
     if (p < dx) A.col_out[rx + p] = owner; else raise_error(A, kErrOut, k, x);
@@ -507,16 +508,17 @@ __device__ __forceinline__ void write_range(const TradeArgs& A, const ItemSrc& S
     // and their bitmap words are cleared for the next round (every member of
     // a giant's set is an item of this trade; nothing reads the set again
     // this round)
-    // the target rows' offsets are loaded with the tags (one round trip)
+    // the target rows' offsets and degrees come with the tags (one load)
     int32_t tinf[kBatch];
     int64_t rxa[kBatch];
     int32_t dxa[kBatch];
 #pragma unroll
     for (int r = 0; r < kBatch; ++r) {
       const bool unk = tx[r] >= 0 && ttag[r] == kTagUnknown;
-      tinf[r] = unk ? A.tinfo[tx[r]] : 0;
-      rxa[r] = tx[r] >= 0 ? A.rp[tx[r]] : 0;
-      dxa[r] = tx[r] >= 0 ? (int32_t)(A.rp[tx[r] + 1] - rxa[r]) : 0;
+      const uint4 ni = tx[r] >= 0 ? A.ninfo[tx[r]] : make_uint4(0u, 0u, 0u, 0u);
+      tinf[r] = unk ? (int32_t)ni.z : 0;
+      rxa[r] = ni.x;
+      dxa[r] = (int32_t)ni.y;
       if (unk) {
         if (S.gu >= 0) A.gs.bm[(int64_t)S.gu * A.gs.gwords + (tx[r] >> 6)] = 0ull;
         if (S.gv >= 0) A.gs.bm[(int64_t)S.gv * A.gs.gwords + (tx[r] >> 6)] = 0ull;
@@ -1016,8 +1018,9 @@ __device__ __forceinline__ void small_trade(const TradeArgs& A, int32_t k, int32
       isd[it] = o < nD ? (o < a ? 0 : 1) : ent_side(e);
       if (o < nD) nmoved += ent_side(e) != isd[it] ? 1 : 0;
       if (itag[it] != kTagPartner) {
-        irx[it] = A.rp[ix[it]];
-        idd[it] = (int32_t)(A.rp[ix[it] + 1] - irx[it]);
+        const uint4 ni = A.ninfo[ix[it]];
+        irx[it] = ni.x;
+        idd[it] = (int32_t)ni.y;
         ip[it] = atomic_add(itag[it] == kTagEmit ? &A.out_cur[ix[it]] : &A.inbox_cur[ix[it]], 1);
       }
     }
