@@ -57,6 +57,15 @@ def kernel_source_digest() -> str:
     return h.hexdigest()
 
 
+def kernel_bytes(rec, name: str):
+    """Scaled HBM bytes of one kernel in a traffic record, whose kernel names
+    carry their namespace (cbx::k_trade), or None."""
+    for key, value in rec["kernels"].items():
+        if key == name or key.endswith("::" + name):
+            return value
+    return None
+
+
 def measured_traffic(workload: str):
     """HBM bytes per step (per kernel) from the committed rocprofv3 counter
     runs, or None when the kernel sources changed since they were taken."""
@@ -466,7 +475,7 @@ def main(argv=None) -> int:
         achieved = trade_bytes / trade_s if trade_s > 0 else 0.0
         out["roofline"] = {"bound": "hbm", "kernel": "k_trade", "achieved": achieved / 1e9,
                            "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": achieved / HBM_PEAK,
-                           "traffic": traffic["kernels"].get("k_trade") if traffic else None,
+                           "traffic": kernel_bytes(traffic, "k_trade") if traffic else None,
                            "algorithmic_bytes_per_launch": trade_bytes, "avg_launch_ms": kernel_ms[2]}
         out["step_ms"] = dict(zip(names, kernel_ms))
         if traffic:
