@@ -27,8 +27,9 @@ def test_traffic_record_commands_run_committed_files():
     rec = _record()
     assert rec["commands"], "the record names the commands that made it"
     for cmd in rec["commands"]:
-        assert "_work" not in cmd and "gpurun" not in cmd
-        assert "rocprofv3" in cmd and "bench.py" in cmd
+        assert cmd.startswith("rocprofv3 ") and "_work/" not in cmd
+        # the profiled program comes right after "--" and is the committed bench
+        assert cmd.split(" -- ", 1)[1].split()[:2] == ["python3", "bench.py"]
 
 
 def test_stale_record_is_not_used(tmp_path, monkeypatch):
