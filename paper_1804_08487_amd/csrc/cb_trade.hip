@@ -610,11 +610,12 @@ __device__ __forceinline__ int32_t ticket_next(unsigned long long t) { return (i
 // Claim a chunk of a job (single lane): the chunk index, or -1 when the job
 // has none left. A job whose chunks are all taken is not incremented again
 // except by claims racing with the last one.
-__device__ __forceinline__ int32_t claim_chunk(HelpJob* J) {
+__device__ __forceinline__ int32_t claim_chunk(HelpJob* J, uint32_t* gen = nullptr) {
   const unsigned long long seen = load_agent_u64(&J->t.ticket);
   if (ticket_next(seen) >= ticket_chunks(seen)) return -1;
   const unsigned long long t =
       __hip_atomic_fetch_add(&J->t.ticket, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (gen) *gen = ticket_gen(t);
   return ticket_next(t) < ticket_chunks(t) ? ticket_next(t) : -1;
 }
 
@@ -774,11 +775,14 @@ __device__ __forceinline__ uint64_t help_group_mask(int32_t b, int32_t groups) {
   return m;
 }
 
-// An idle wavefront of workgroup b writes one chunk of an open write job of
-// its group, if there is one.
-__device__ __forceinline__ bool try_help(const TradeArgs& A, int32_t b, WriteCounts& W) {
+// An idle wavefront of workgroup b writes chunks of an open write job of its
+// group, if there is one: up to `runs` chunks of that job in a row, so the
+// fields are read once per generation, not once per chunk.
+constexpr int kHelpRun = 8;   // chunks in a row for a wavefront worker (a workgroup worker takes one)
+__device__ __forceinline__ bool try_help(const TradeArgs& A, int32_t b, WriteCounts& W, int runs) {
   const int l = lane_id();
   int32_t j = -1, c = -1;
+  uint32_t gen = 0;
   if (l == 0) {
     const uint64_t group = help_group_mask(b, A.help_groups);
     const uint64_t m = ((uint64_t)(uint32_t)load_agent(&A.ctrl[cw(kCwJobMask0)]) |
@@ -788,45 +792,59 @@ __device__ __forceinline__ bool try_help(const TradeArgs& A, int32_t b, WriteCou
       const int rot = (int)((threadIdx.x >> 6) * A.help_groups) & 63;
       const uint64_t rm = rot ? ((m >> rot) | (m << (64 - rot))) : m;
       j = (int32_t)((__builtin_ctzll(rm) + rot) & 63);
-      c = claim_chunk(A.jobs + j);
+      c = claim_chunk(A.jobs + j, &gen);
     }
   }
   c = wave_bcast(c, 0);
   if (c < 0) return false;
   j = wave_bcast(j, 0);
-  consume_order();
   HelpJob* J = A.jobs + j;
-  // the fields of the claimed generation stay put until this chunk is reported
   const uint64_t* slot = A.slots + (int64_t)j * A.slot_elems;
-  if (load_agent(&J->f.phase) == 1) {
-    extract_chunk(A, load_agent(&J->f.k), load_agent(&J->f.gi), load_agent(&J->f.side),
-                  (int32_t)(A.gs.gwords >> 6), A.sbpre + (int64_t)j * A.sbpre_stride,
-                  reinterpret_cast<unsigned long long*>(const_cast<uint64_t*>(slot) + load_agent64(&J->f.e_off)),
-                  c);
+  ItemSrc S;
+  uint32_t have = 0;   // generation whose fields S holds (0: none yet)
+  int32_t phase = 0;
+  for (int run = 0;;) {
+    consume_order();
+    // the fields of the claimed generation stay put until this chunk is reported
+    gen = (uint32_t)wave_bcast((int32_t)gen, 0) | 0x10000u;
+    if (have != gen) phase = load_agent(&J->f.phase);
+    if (phase == 1) {
+      extract_chunk(A, load_agent(&J->f.k), load_agent(&J->f.gi), load_agent(&J->f.side),
+                    (int32_t)(A.gs.gwords >> 6), A.sbpre + (int64_t)j * A.sbpre_stride,
+                    reinterpret_cast<unsigned long long*>(const_cast<uint64_t*>(slot) + load_agent64(&J->f.e_off)),
+                    c);
+      have = gen;
+    } else {
+      if (have != gen) {
+        S.E = slot + load_agent64(&J->f.e_off);
+        S.D = nullptr;
+        S.k = load_agent(&J->f.k);
+        S.u = load_agent(&J->f.u);
+        S.v = load_agent(&J->f.v);
+        S.s = load_agent(&J->f.s);
+        S.nD = load_agent(&J->f.nD);
+        S.a = load_agent(&J->f.a);
+        S.du = load_agent(&J->f.du);
+        S.dv = load_agent(&J->f.dv);
+        S.bu = load_agent64(&J->f.bu);
+        S.bv = load_agent64(&J->f.bv);
+        S.gu = load_agent(&J->f.gu);
+        S.gv = load_agent(&J->f.gv);
+        have = gen;
+      }
+      const int32_t first = c * A.help_chunk;
+      const int32_t end = first + A.help_chunk < S.s ? first + A.help_chunk : S.s;
+      write_range<true>(A, S, first, end, kWave * kBatch, J->c.own, W);
+    }
     publish_wait();
     if (l == 0) atomic_add(&J->c.done, 1);
-    return true;
+    if (++run >= runs) break;
+    // the next chunk of the same job; a new generation brings new fields
+    c = -1;
+    if (l == 0) c = claim_chunk(J, &gen);
+    c = wave_bcast(c, 0);
+    if (c < 0) break;
   }
-  ItemSrc S;
-  S.E = slot + load_agent64(&J->f.e_off);
-  S.D = nullptr;
-  S.k = load_agent(&J->f.k);
-  S.u = load_agent(&J->f.u);
-  S.v = load_agent(&J->f.v);
-  S.s = load_agent(&J->f.s);
-  S.nD = load_agent(&J->f.nD);
-  S.a = load_agent(&J->f.a);
-  S.du = load_agent(&J->f.du);
-  S.dv = load_agent(&J->f.dv);
-  S.bu = load_agent64(&J->f.bu);
-  S.bv = load_agent64(&J->f.bv);
-  S.gu = load_agent(&J->f.gu);
-  S.gv = load_agent(&J->f.gv);
-  const int32_t first = c * A.help_chunk;
-  const int32_t end = first + A.help_chunk < S.s ? first + A.help_chunk : S.s;
-  write_range<true>(A, S, first, end, kWave * kBatch, J->c.own, W);
-  publish_wait();
-  if (l == 0) atomic_add(&J->c.done, 1);
   return true;
 }
 
@@ -1177,7 +1195,7 @@ __device__ __forceinline__ void small_worker(const TradeArgs& A, WaveLds& W, int
       if (wave_bcast(stop, 0)) break;
       // an idle wavefront also writes chunks of the large trades' write jobs
       WriteCounts H{0, 0, 0, 0};
-      if (try_help(A, (int32_t)blockIdx.x, H)) {
+      if (try_help(A, (int32_t)blockIdx.x, H, kHelpRun)) {
         S.fwd += (unsigned long long)wave_sum((int32_t)H.fwd);
         S.emit += (unsigned long long)wave_sum((int32_t)H.emit);
         S.n_push += (unsigned long long)wave_sum((int32_t)H.push);
@@ -2437,7 +2455,7 @@ __device__ __forceinline__ void big_worker(const TradeArgs& A, BigLds& B) {
         continue;
       }
       WriteCounts H{0, 0, 0, 0};
-      const bool helped = try_help(A, (int32_t)blockIdx.x, H);
+      const bool helped = try_help(A, (int32_t)blockIdx.x, H, 1);
       counters[1] += H.fwd;
       counters[2] += H.push;
       counters[3] += H.emit;
