@@ -15,8 +15,8 @@ launched as a captured graph, options from the autotuner; value = the sum
 of the chains' edges * K / wall seconds. The same chains run one by one on
 the single-chain path give the comparison figure.
 
-Prints one JSON line. --gpus above 1 is refused: this build runs on one GPU
-(independent chains would shard one per GPU with no exchange).
+Prints one JSON line. --gpus above 1 is refused: the library runs on one
+GPU (independent chains would shard one per GPU with no exchange).
 """
 from __future__ import annotations
 
@@ -366,7 +366,7 @@ def main(argv=None) -> int:
         return 0
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU; multi-GPU runs are not part of this build "
+        print("bench.py runs on one GPU; runs on several GPUs are not supported "
               "(independent chains shard one per GPU with no exchange).", file=sys.stderr)
         return 2
 

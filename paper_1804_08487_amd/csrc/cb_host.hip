@@ -803,7 +803,7 @@ bool init_device_state(cb_graph* g, bool validate, char* msg, size_t cap) {
 }
 
 // Read the error word after upload validation: CB_OK or CB_ENOTSIMPLE.
-cb_status upload_verdict(cb_graph* g) {
+cb_status upload_check_status(cb_graph* g) {
   int32_t err = 0;
   char msg[256];
   if (!HIP_OK(hipMemcpy(&err, g->ctrl + cw(kCwErr), sizeof(int32_t), hipMemcpyDeviceToHost), "read error word"))
@@ -967,7 +967,7 @@ cb_status cbx::create_graph(const ChainSrc* src_in, int32_t count, void* stream,
     delete g;
     return fail(CB_EDEVICE, "%s", msg);
   }
-  cb_status s = upload_verdict(g);
+  cb_status s = upload_check_status(g);
   if (s == CB_OK) s = setup_giants(g, default_giant_threshold(g, rp_host), rp_host);
   if (s != CB_OK) {
     release_all(g);
