@@ -7,6 +7,9 @@
 // then its mask bit), claims chunks itself, clears the mask bit and waits
 // until every chunk is reported done. Helpers look at the mask, claim, read
 // the fields of the generation they hold a chunk of, work, and report done.
+// A helper may take a run of chunks of one job in a row: it keeps the fields
+// it read while the tickets it claims show the same generation, and reads
+// them again when a claim shows a new one.
 //
 // Every thread yields at random points. The model checks that each chunk of
 // each generation is worked exactly once, with that generation's fields, that
@@ -44,11 +47,12 @@ static void jitter() {
   else if (r == 9) std::this_thread::sleep_for(std::chrono::microseconds(rng() % 50));
 }
 
-static int32_t claim_chunk(Job& J) {
+static int32_t claim_chunk(Job& J, uint32_t* gen = nullptr) {
   const uint64_t seen = J.ticket.load(std::memory_order_relaxed);
   if (ticket_next(seen) >= ticket_chunks(seen)) return -1;
   jitter();
   const uint64_t t = J.ticket.fetch_add(1, std::memory_order_relaxed);
+  if (gen) *gen = ticket_gen(t);
   return ticket_next(t) < ticket_chunks(t) ? ticket_next(t) : -1;
 }
 
@@ -56,6 +60,7 @@ int main(int argc, char** argv) {
   const int owners = argc > 1 ? atoi(argv[1]) : 3;
   const int helpers = argc > 2 ? atoi(argv[2]) : 12;
   const int gens = argc > 3 ? atoi(argv[3]) : 20000;
+  const int runs = argc > 4 ? atoi(argv[4]) : 1;   // chunks a helper takes in a row
   std::vector<Job> jobs(owners);
   std::atomic<uint32_t> mask{0};
   // worked[o][gen % 4096][chunk]: how often that chunk was worked
@@ -124,19 +129,33 @@ int main(int argc, char** argv) {
         for (int i = 0; i < owners; ++i)
           if ((m >> ((h + i) % owners)) & 1u) { pick = (h + i) % owners; break; }
         Job& J = jobs[pick];
-        const int32_t c = claim_chunk(J);
+        uint32_t gen = 0;
+        int32_t c = claim_chunk(J, &gen);
         if (c < 0) continue;
-        std::atomic_thread_fence(std::memory_order_seq_cst);
-        jitter();
-        work(pick, J.fields_gen.load(std::memory_order_relaxed), J.fields_chunks.load(std::memory_order_relaxed), c);
-        std::atomic_thread_fence(std::memory_order_seq_cst);
-        jitter();
-        J.done.fetch_add(1, std::memory_order_relaxed);
+        uint32_t have = 0;   // generation (with bit 16 set) whose fields are held
+        int32_t fgen = 0, fchunks = 0;
+        for (int run = 0;;) {
+          std::atomic_thread_fence(std::memory_order_seq_cst);
+          jitter();
+          if (have != (gen | 0x10000u)) {
+            fgen = J.fields_gen.load(std::memory_order_relaxed);
+            fchunks = J.fields_chunks.load(std::memory_order_relaxed);
+            have = gen | 0x10000u;
+          }
+          work(pick, fgen, fchunks, c);
+          std::atomic_thread_fence(std::memory_order_seq_cst);
+          jitter();
+          J.done.fetch_add(1, std::memory_order_relaxed);
+          if (++run >= runs) break;
+          c = claim_chunk(J, &gen);
+          if (c < 0) break;
+        }
       }
     });
   for (int o = 0; o < owners; ++o) th[o].join();
   stop.store(1);
   for (size_t i = owners; i < th.size(); ++i) th[i].join();
-  printf("%s: %d owners x %d generations, %d helpers\n", bad.load() ? "FAIL" : "ok", owners, gens, helpers);
+  printf("%s: %d owners x %d generations, %d helpers, runs of %d\n", bad.load() ? "FAIL" : "ok", owners, gens,
+         helpers, runs);
   return bad.load() ? 1 : 0;
 }
